@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@pytest.fixture(scope="session")
+def slice64():
+    import numpy as np
+    return dict(np.load(os.path.join(ROOT, "tests", "golden", "slice_n64.npz")))
+
+
+@pytest.fixture(scope="session")
+def slice128():
+    import numpy as np
+    return dict(np.load(os.path.join(ROOT, "tests", "golden", "slice_n128.npz")))
