@@ -1,0 +1,232 @@
+"""Benchmark: batched BOAC candidate evaluation on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+
+One step = one pass of the whole hot path over the 256-candidate batch on the 128 x 128, 128-angle,
+128-bin slice (5e5 counts): rasterise mu(theta) for every candidate, build its attenuation tensor,
+sensitivity image, 30 MLEM iterations, then the Poisson negative log-likelihood. value = candidates x
+MLEM iterations per second (whole job; inputs resident in HBM before the timed region).
+
+The same JSON line also carries: the unbatched GPU path (one candidate per call), the objective +
+gradient rate on the 64-candidate adjoint workload (20 iterations, checkpoint every 5), the roofline
+of the dominant kernel from HIP events recorded by the library around each launch during the timed
+steps, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLEM iters/s × candidates at 128², 128 angles; batched vs plain; obj+grad evals/s"
+HBM_PEAK_GBS = 8000.0
+DELTA_R = 0.8
+
+
+def source_digest(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2109_11920_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"fwd": ["kernels_ray.hip", "device_common.h", "launch.h"],
+                  "back": ["kernels_back.hip", "device_common.h", "launch.h"]}
+
+
+def read_traffic(kind, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_digest(KERNEL_SOURCES[kind]):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(workload_S, n_cand, n_iter):
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample of the batch."""
+    import numpy as np
+
+    import oracle
+    import synth
+    og = oracle.Geometry(128, 128, 128, 128, 0.2)
+    th = synth.draw_candidates(synth.candidate_stream(0), 256)[:n_cand]
+    S = workload_S.astype(np.float64)
+    oracle.sampling_matrix(og)  # geometry setup outside the timed sample
+    t0 = time.perf_counter()
+    for c in range(n_cand):
+        oracle.evaluate(og, S, th[c], DELTA_R, n_iter)
+    dt = time.perf_counter() - t0
+    return {"value": n_cand * n_iter / dt, "unit": "cand·it/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cand} of the 256 candidates, {n_iter} MLEM iterations + objective each, "
+                      f"FP64 NumPy/SciPy single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-cands", type=int, default=2)
+    ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: candidates are independent and this build has no multi-GPU "
+              "path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"   # the CPU oracle baseline is single-threaded
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_11920_amd.api import Context, Geometry, SliceBatch
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    d = np.load(os.path.join(ROOT, "tests", "golden", "slice_n128.npz"))
+    S_np = d["meas"]
+    g = Geometry(128, 128, 128, 128, 0.2)
+    S = torch.as_tensor(S_np.astype(np.float32), device=dev)
+    w = synth.workload("batch256_n128")
+    cand = torch.as_tensor(synth.workload_candidates(w)[0].astype(np.float32), device=dev)
+    C, K = cand.shape[0], w.n_iter
+    ctx = Context(0)
+    stream = torch.cuda.current_stream(dev)
+
+    # ---- main timed region: the 256-candidate batch, eager launches with per-kernel HIP events
+    obj = torch.empty(C, device=dev)
+    status = torch.empty(C, device=dev, dtype=torch.int32)
+    for _ in range(args.warmup):
+        ctx.objective(g, S, cand, DELTA_R, K, obj=obj, status=status)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.objective(g, S, cand, DELTA_R, K, obj=obj, status=status)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    kstats = {k: ctx.kernel_stats(k) for k in ("raster", "att", "fwd", "back", "reduce", "adj_ray", "adj_pix",
+                                                "other")}
+    J = obj.cpu().numpy()
+    assert np.all(np.isfinite(J)) and int((status.cpu().numpy() & 3).max()) == 0
+    value = C * K / (step_ms / 1e3)
+
+    dom = max(("fwd", "back"), key=lambda k: kstats[k][1])
+    cnt, ms, by = kstats[dom]
+    avg_ms = ms / max(cnt, 1)
+    bytes_per_launch = by / max(cnt, 1)
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, "batch256_n128"),
+            "kernel": f"k_{dom}", "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bytes_per_launch,
+            "launches": cnt}
+    kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in kstats.items() if v[0]}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "cand·it/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "batch256_n128", "image": 128, "pixel_cm": 0.2, "angles": 128, "bins": 128,
+                      "samples": 128, "counts": 5e5, "candidates": C, "mlem_iters": K,
+                      "parallelism": "single-gpu"},
+           "roofline": roof, "kernel_ms_per_step": kernel_ms}
+
+    if not args.only_main:
+        # ---- the same step replayed from a captured HIP graph
+        gstream = torch.cuda.Stream(dev)
+        sb = [SliceBatch(g, S, cand, torch.empty(C, device=dev), None, torch.empty(C, device=dev, dtype=torch.int32))]
+        with torch.cuda.stream(gstream):
+            ctx.evaluate_batch(sb, DELTA_R, K)
+            ctx.evaluate_batch(sb, DELTA_R, K)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(gstream)
+            for _ in range(args.steps):
+                ctx.evaluate_batch(sb, DELTA_R, K)
+            e1.record(gstream)
+        gstream.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
+        assert torch.equal(sb[0].obj, obj)
+        out["graph_ms_per_step"] = round(graph_ms, 3)
+
+        # ---- unbatched GPU path: one candidate per call, same kernels, 30 iterations
+        n_plain = 16
+        o1 = torch.empty(1, device=dev)
+        s1 = torch.empty(1, device=dev, dtype=torch.int32)
+        ctx.objective(g, S, cand[:1].contiguous(), DELTA_R, K, obj=o1, status=s1)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        singles = [cand[c:c + 1].contiguous() for c in range(n_plain)]
+        e0.record(stream)
+        for c in range(n_plain):
+            ctx.objective(g, S, singles[c], DELTA_R, K, obj=o1, status=s1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_rate = n_plain * K / (e0.elapsed_time(e1) / 1e3)
+        out["plain"] = {"value": round(plain_rate, 1), "unit": "cand·it/s",
+                        "what": f"{n_plain} candidates, one call each (C=1), {K} iterations + objective"}
+        out["batched_over_plain"] = round(value / plain_rate, 2)
+
+        # ---- objective + gradient: 64 candidates, 20 iterations, checkpoint every 5
+        wg = synth.workload("grad64_n128")
+        cg = torch.as_tensor(synth.workload_candidates(wg)[0].astype(np.float32), device=dev)
+        Kg = wg.n_iter
+        ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
+        ctx.objective(g, S, cg, DELTA_R, Kg)
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            _, G, st = ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
+        e1.record(stream)
+        for _ in range(reps):
+            ctx.objective(g, S, cg, DELTA_R, Kg)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(G).all())
+        grad_ms = e0.elapsed_time(e1) / reps
+        fwd_ms = e1.elapsed_time(e2) / reps
+        out["grad"] = {"value": round(cg.shape[0] / (grad_ms / 1e3), 1), "unit": "obj+grad evals/s",
+                       "ms_per_batch": round(grad_ms, 3), "forward_ms_per_batch": round(fwd_ms, 3),
+                       "grad_over_forward": round(grad_ms / fwd_ms, 3),
+                       "what": "64 candidates, 20 iterations, checkpoint every 5"}
+
+    if not args.no_cpu and not args.only_main:
+        out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

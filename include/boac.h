@@ -1,0 +1,179 @@
+/*
+ * boac.h — C ABI of libboac, the MI355X (gfx950) library that evaluates BOAC candidate attenuation
+ * maps: rasterise the Legendre head model, build the attenuated Radon projector, run MLEM, score the
+ * reconstruction with the Poisson negative log-likelihood, and differentiate that score.
+ *
+ * Paper: "A Bayesian Optimization Approach for Attenuation Correction in SPECT Brain Imaging"
+ * (Koutsantonis et al.). Eq. (1) attenuated Radon transform; Eq. (2) S = A^mu F; Eq. (3) Legendre
+ * head outline; Eq. (4) piecewise attenuation map; Eq. (5) Poisson log-likelihood; BOAC steps 2-3
+ * (per-candidate system matrix, fixed number of MLEM iterations, goodness of fit).
+ *
+ * Discretisation (the paper leaves it open; these are the library's conventions):
+ *   image n x n, pixel (i, l) centre ((l - (n-1)/2) dx, (i - (n-1)/2) dx), arrays [i][l] row-major;
+ *   angle a: phi_a = 2 pi a / n_angles over 360 deg; bin b offset s_b = (b - (n_bins-1)/2) n dx / n_bins;
+ *   ray sample k at t_k = (k - (n_samples-1)/2) dx, point s_b (cos, sin) + t_k (-sin, cos); photons
+ *   travel toward +t (detector at k = n_samples-1);
+ *   images are read at sample points by bilinear interpolation, zero outside the grid (matrix W);
+ *   L_abk = dx (m_abk / 2 + sum_{k'>k} m_abk'), m = W mu;  att = exp(-L);
+ *   (A^mu f)_ab = dx sum_k att_abk (W f)_abk;  the backprojector is its exact transpose;
+ *   R(theta) = sum_{k=0}^{5} c_k P_k(cos theta); partial-volume fractions from 4 x 4 sub-samples with
+ *   a C^1 smoothstep edge of width dx/4; mu = mu_b fb + mu_c (fo - fb);
+ *   MLEM: F^0 = 1, r = S / (A F) where A F > 0 else 0, F <- F * (A^T r) / s with s = A^T 1;
+ *   objective J = sum_i [y_i - S_i ln y_i + ln Gamma(S_i + 1)] at y = A F^K.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are caller-owned DEVICE buffers (e.g. a contiguous float32 torch tensor's
+ *     data_ptr()), 16-byte aligned, on the context's device. The library never frees or keeps them.
+ *     Pointers named h_* are host memory read during the call only.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the device's null stream). Scratch
+ *     (attenuation tensors, iterates, partial sums) lives in the context and grows on demand; calls on
+ *     one context must be serialised by the caller (one stream at a time).
+ *   - Arguments are validated before any launch: geometry sizes >= 2, n <= 1024, n_bins <= 4096,
+ *     n_samples <= 1024, pixel_cm > 0 and finite, 1 <= C <= 2^20, n_iter >= 0, finite candidates,
+ *     non-null and 16-byte-aligned pointers where required. Nothing aborts or throws across the ABI.
+ *   - On failure the return value is non-zero and boac_last_error() holds a message (thread-local).
+ *     HIP failures map to BOAC_EDEVICE with the HIP error text.
+ *   - All GPU arithmetic is FP32; ray sums, angle sums, scans and the likelihood are accumulated with
+ *     compensated (error-free transformation) summation.
+ */
+#ifndef BOAC_H
+#define BOAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BOAC_OK = 0,
+    BOAC_EINVAL = 1,   /* null / misaligned pointer, bad count, non-finite parameter */
+    BOAC_ESHAPE = 2,   /* geometry out of the supported range */
+    BOAC_ENOMEM = 3,   /* device scratch allocation failed */
+    BOAC_EDEVICE = 4,  /* a HIP call failed (message in boac_last_error) */
+    BOAC_ETIMEOUT = 5, /* reserved: bounded device wait expired */
+    BOAC_ENOTSUP = 6   /* device is not gfx950 / feature not built */
+} boac_status;
+
+/* Slice geometry. n x n image of square pixels pixel_cm wide; n_angles projections over 360 deg;
+ * n_bins detector bins; n_samples samples per ray at spacing pixel_cm. */
+typedef struct {
+    int32_t n;
+    int32_t n_angles;
+    int32_t n_bins;
+    int32_t n_samples;
+    float pixel_cm;
+} boac_geom;
+
+/* One candidate head model (Eqs. 3-4): Legendre coefficients c_0..c_5 of R(cos theta) in cm, brain
+ * and cranium attenuation coefficients in 1/cm. 32 bytes, stored as 8 consecutive floats. */
+typedef struct {
+    float c[6];
+    float mu_b;
+    float mu_c;
+} boac_cand;
+
+/* Per-candidate status bits written by boac_objective / boac_objective_grad / boac_evaluate_batch. */
+#define BOAC_STATUS_ZERO_PROJECTION 1u /* some y_i <= 0 with S_i > 0: J = +inf */
+#define BOAC_STATUS_NONFINITE 2u       /* J or a gradient entry is not finite */
+#define BOAC_STATUS_NEGATIVE_RADIUS 4u /* R(theta) < 0 at some sub-sample (informational) */
+#define BOAC_STATUS_NEGATIVE_COUNTS 8u /* the measured sinogram has S_i < 0 somewhere */
+
+typedef struct boac_ctx boac_ctx;
+
+/* Library version, (major << 16) | minor. */
+int32_t boac_version(void);
+
+/* Create a context on HIP device `device` (must be gfx950). `tune_cache_path` names a JSON file of
+ * launch plans written by the autotuner (NULL: the library's defaults). *out receives the handle. */
+boac_status boac_ctx_create(int32_t device, const char *tune_cache_path, boac_ctx **out);
+
+/* Release the context and its device scratch. Waits for the context's outstanding work. NULL is a
+ * no-op. */
+void boac_ctx_destroy(boac_ctx *ctx);
+
+/* Message for the calling thread's last non-OK return (static storage; "" if none). */
+const char *boac_last_error(void);
+
+/* Eqs. (3)-(4): attenuation maps of C candidates.
+ * d_cand [C] candidates; delta_r_cm: cranium thickness dR (> 0); d_mu out [C][n][n] float, 1/cm. */
+boac_status boac_rasterize_mu(boac_ctx *ctx, const boac_geom *geom, const boac_cand *d_cand, int32_t C,
+                              float delta_r_cm, float *d_mu, void *stream);
+
+/* Eqs. (1)-(2): y_c = A^{mu_c} f_c for C (attenuation map, image) pairs.
+ * d_mu [C][n][n], d_img [C][n][n] in; d_sino [C][n_angles][n_bins] out. */
+boac_status boac_project(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_img,
+                         int32_t C, float *d_sino, void *stream);
+
+/* Exact transpose of boac_project: x_c = (A^{mu_c})^T z_c.
+ * d_mu [C][n][n], d_sino [C][n_angles][n_bins] in; d_img [C][n][n] out. */
+boac_status boac_backproject(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_sino,
+                             int32_t C, float *d_img, void *stream);
+
+/* MLEM (BOAC step 3) for C attenuation maps against ONE measured sinogram.
+ * d_mu [C][n][n]; d_meas [n_angles][n_bins] counts as float (>= 0); n_iter >= 0 iterations;
+ * d_img_inout [C][n][n]: starting image in (pass ones for the standard start), F^K out. */
+boac_status boac_mlem(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_meas,
+                      int32_t C, int32_t n_iter, float *d_img_inout, void *stream);
+
+/* Full candidate evaluation (BOAC steps 2-3): mu(theta) -> att -> n_iter MLEM iterations from F^0 = 1
+ * -> J = -ln P(S | F^K, A^mu) (Eq. 5, negated).
+ * d_obj [C] out; d_img_out [C][n][n] (F^K) or NULL; d_status [C] uint32 bits or NULL. */
+boac_status boac_objective(boac_ctx *ctx, const boac_geom *geom, const float *d_meas, const boac_cand *d_cand,
+                           int32_t C, float delta_r_cm, int32_t n_iter, float *d_obj, float *d_img_out,
+                           uint32_t *d_status, void *stream);
+
+/* Objective and its exact gradient dJ/d(c_0..c_5, mu_b, mu_c) through the unrolled MLEM iterations
+ * (reverse mode; the MLEM state is checkpointed every ckpt_every iterations and recomputed between
+ * checkpoints; 1 <= ckpt_every, values above n_iter mean "only F^0").
+ * d_obj [C], d_grad [C][8] out (order c_0..c_5, mu_b, mu_c); d_status [C] or NULL. */
+boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const float *d_meas,
+                                const boac_cand *d_cand, int32_t C, float delta_r_cm, int32_t n_iter,
+                                int32_t ckpt_every, float *d_obj, float *d_grad, uint32_t *d_status,
+                                void *stream);
+
+/* One slice of an uneven batch: its geometry, measured sinogram and candidates, and where results go
+ * (all device pointers; d_grad NULL = objective only; d_status may be NULL). */
+typedef struct {
+    boac_geom geom;
+    const float *d_meas;     /* [n_angles][n_bins] */
+    const boac_cand *d_cand; /* [C] */
+    int32_t C;
+    float *d_obj;            /* [C] */
+    float *d_grad;           /* [C][8] or NULL */
+    uint32_t *d_status;      /* [C] or NULL */
+} boac_slice;
+
+/* Batched evaluation of many slices of uneven sizes (and their candidates) with one launch per phase
+ * covering every slice; the launch sequence is captured once into a HIP graph per batch shape and
+ * replayed on later calls with the same shape. h_slices is host memory [n_slices]. Slices needing a
+ * gradient use ckpt_every as in boac_objective_grad. */
+boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
+                                int32_t n_iter, int32_t ckpt_every, void *stream);
+
+/* Kernel-time instrumentation: when enabled, every launch is bracketed by HIP events on its stream
+ * and its duration is accumulated per kernel kind after the caller synchronises. */
+typedef enum {
+    BOAC_K_RASTER = 0,
+    BOAC_K_ATT = 1,
+    BOAC_K_FWD = 2,
+    BOAC_K_BACK = 3,
+    BOAC_K_REDUCE = 4,
+    BOAC_K_ADJ_RAY = 5,
+    BOAC_K_ADJ_PIX = 6,
+    BOAC_K_OTHER = 7,
+    BOAC_K_COUNT = 8
+} boac_kernel_kind;
+
+boac_status boac_ctx_set_profiling(boac_ctx *ctx, int32_t enable);
+/* Synchronises the pending events and returns, for `kind`, the number of timed launches, their total
+ * milliseconds and the sum of their algorithmic HBM bytes (the library's per-launch model). */
+boac_status boac_ctx_kernel_stats(boac_ctx *ctx, int32_t kind, int64_t *count, double *total_ms,
+                                  double *total_bytes);
+boac_status boac_ctx_reset_stats(boac_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOAC_H */

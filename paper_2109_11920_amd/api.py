@@ -1,0 +1,224 @@
+"""Python binding of libboac on torch device tensors: argument marshalling only. Every step of the
+candidate evaluation runs in the library's HIP kernels; torch provides device memory and streams."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import BoacError, BoacGeom, BoacSlice, check
+
+STATUS_ZERO_PROJECTION = 1
+STATUS_NONFINITE = 2
+STATUS_NEGATIVE_RADIUS = 4
+STATUS_NEGATIVE_COUNTS = 8
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """n x n image with pixel (cm); n_angles over 360 deg; n_bins bins; n_samples samples per ray."""
+    n: int
+    n_angles: int
+    n_bins: int
+    n_samples: int
+    pixel: float
+
+    def c(self) -> BoacGeom:
+        return BoacGeom(self.n, self.n_angles, self.n_bins, self.n_samples, float(self.pixel))
+
+    @property
+    def image_shape(self):
+        return (self.n, self.n)
+
+    @property
+    def sino_shape(self):
+        return (self.n_angles, self.n_bins)
+
+
+def _ptr(t: Optional[torch.Tensor], name: str, dtype=torch.float32, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A libboac context on one GPU (scratch, launch plans, graphs, instrumentation)."""
+
+    def __init__(self, device: int = 0, tune_cache: Optional[str] = None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        check(self.lib.boac_ctx_create(device, tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.boac_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- entry points -------------------------------------------------------------------------
+    def rasterize_mu(self, geom: Geometry, cand: torch.Tensor, delta_r: float, out=None) -> torch.Tensor:
+        C = cand.shape[0]
+        out = out if out is not None else torch.empty((C, geom.n, geom.n), device=self.device)
+        check(self.lib.boac_rasterize_mu(self.handle, ctypes.byref(geom.c()), _ptr(cand, "cand", shape=(C, 8)),
+                                         C, float(delta_r), _ptr(out, "mu", shape=(C, geom.n, geom.n)),
+                                         _stream(self.device)))
+        return out
+
+    def project(self, geom: Geometry, mu: torch.Tensor, img: torch.Tensor, out=None) -> torch.Tensor:
+        C = mu.shape[0]
+        out = out if out is not None else torch.empty((C,) + geom.sino_shape, device=self.device)
+        check(self.lib.boac_project(self.handle, ctypes.byref(geom.c()), _ptr(mu, "mu", shape=(C,) + geom.image_shape),
+                                    _ptr(img, "img", shape=(C,) + geom.image_shape), C,
+                                    _ptr(out, "sino", shape=(C,) + geom.sino_shape), _stream(self.device)))
+        return out
+
+    def backproject(self, geom: Geometry, mu: torch.Tensor, sino: torch.Tensor, out=None) -> torch.Tensor:
+        C = mu.shape[0]
+        out = out if out is not None else torch.empty((C,) + geom.image_shape, device=self.device)
+        check(self.lib.boac_backproject(self.handle, ctypes.byref(geom.c()),
+                                        _ptr(mu, "mu", shape=(C,) + geom.image_shape),
+                                        _ptr(sino, "sino", shape=(C,) + geom.sino_shape), C,
+                                        _ptr(out, "img", shape=(C,) + geom.image_shape), _stream(self.device)))
+        return out
+
+    def mlem(self, geom: Geometry, mu: torch.Tensor, meas: torch.Tensor, n_iter: int,
+             img: Optional[torch.Tensor] = None) -> torch.Tensor:
+        C = mu.shape[0]
+        img = img if img is not None else torch.ones((C,) + geom.image_shape, device=self.device)
+        check(self.lib.boac_mlem(self.handle, ctypes.byref(geom.c()), _ptr(mu, "mu", shape=(C,) + geom.image_shape),
+                                 _ptr(meas, "meas", shape=geom.sino_shape), C, int(n_iter),
+                                 _ptr(img, "img", shape=(C,) + geom.image_shape), _stream(self.device)))
+        return img
+
+    def objective(self, geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, delta_r: float, n_iter: int,
+                  want_image: bool = False, obj=None, status=None):
+        """Returns (J [C], F^K [C,n,n] or None, status [C] int32)."""
+        C = cand.shape[0]
+        obj = obj if obj is not None else torch.empty(C, device=self.device)
+        status = status if status is not None else torch.empty(C, device=self.device, dtype=torch.int32)
+        img = torch.empty((C,) + geom.image_shape, device=self.device) if want_image else None
+        check(self.lib.boac_objective(self.handle, ctypes.byref(geom.c()), _ptr(meas, "meas", shape=geom.sino_shape),
+                                      _ptr(cand, "cand", shape=(C, 8)), C, float(delta_r), int(n_iter),
+                                      _ptr(obj, "obj", shape=(C,)), _ptr(img, "img"),
+                                      _ptr(status, "status", dtype=torch.int32, shape=(C,)), _stream(self.device)))
+        return obj, img, status
+
+    def objective_grad(self, geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, delta_r: float, n_iter: int,
+                       ckpt_every: int = 5, obj=None, grad=None, status=None):
+        """Returns (J [C], dJ/dtheta [C, 8], status [C] int32)."""
+        C = cand.shape[0]
+        obj = obj if obj is not None else torch.empty(C, device=self.device)
+        grad = grad if grad is not None else torch.empty((C, 8), device=self.device)
+        status = status if status is not None else torch.empty(C, device=self.device, dtype=torch.int32)
+        check(self.lib.boac_objective_grad(self.handle, ctypes.byref(geom.c()),
+                                           _ptr(meas, "meas", shape=geom.sino_shape),
+                                           _ptr(cand, "cand", shape=(C, 8)), C, float(delta_r), int(n_iter),
+                                           int(ckpt_every), _ptr(obj, "obj", shape=(C,)),
+                                           _ptr(grad, "grad", shape=(C, 8)),
+                                           _ptr(status, "status", dtype=torch.int32, shape=(C,)),
+                                           _stream(self.device)))
+        return obj, grad, status
+
+    def evaluate_batch(self, slices: Sequence["SliceBatch"], delta_r: float, n_iter: int, ckpt_every: int = 5):
+        arr = (BoacSlice * len(slices))()
+        for i, s in enumerate(slices):
+            C = s.cand.shape[0]
+            arr[i] = BoacSlice(s.geom.c(), _ptr(s.meas, "meas", shape=s.geom.sino_shape),
+                               _ptr(s.cand, "cand", shape=(C, 8)), C, _ptr(s.obj, "obj", shape=(C,)),
+                               _ptr(s.grad, "grad"), _ptr(s.status, "status", dtype=torch.int32))
+        check(self.lib.boac_evaluate_batch(self.handle, arr, len(slices), float(delta_r), int(n_iter),
+                                           int(ckpt_every), _stream(self.device)))
+
+    # ---- instrumentation ------------------------------------------------------------------------
+    def set_profiling(self, on: bool):
+        check(self.lib.boac_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def kernel_stats(self, kind: str):
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        check(self.lib.boac_ctx_kernel_stats(self.handle, _lib.KERNEL_KINDS[kind], ctypes.byref(cnt),
+                                             ctypes.byref(ms), ctypes.byref(by)))
+        return int(cnt.value), float(ms.value), float(by.value)
+
+    def reset_stats(self):
+        check(self.lib.boac_ctx_reset_stats(self.handle))
+
+
+@dataclass
+class SliceBatch:
+    """One slice of an uneven batch with its output tensors (grad None = objective only)."""
+    geom: Geometry
+    meas: torch.Tensor
+    cand: torch.Tensor
+    obj: torch.Tensor
+    grad: Optional[torch.Tensor] = None
+    status: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def make(geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, with_grad: bool) -> "SliceBatch":
+        C = cand.shape[0]
+        dev = cand.device
+        return SliceBatch(geom, meas, cand, torch.empty(C, device=dev),
+                          torch.empty((C, 8), device=dev) if with_grad else None,
+                          torch.empty(C, device=dev, dtype=torch.int32))
+
+
+class BoacObjective(torch.autograd.Function):
+    """J(theta) for a batch of candidates theta [C, 8] with an exact hand-written adjoint.
+
+    forward(ctx_obj, geom, meas, delta_r, n_iter, ckpt_every, theta) -> J [C]; the gradient is computed
+    together with J by the library's reverse sweep and applied in backward."""
+
+    @staticmethod
+    def forward(fctx, boac: Context, geom: Geometry, meas: torch.Tensor, delta_r: float, n_iter: int,
+                ckpt_every: int, theta: torch.Tensor):
+        th = theta.detach().to(torch.float32).contiguous()
+        J, grad, status = boac.objective_grad(geom, meas, th, delta_r, n_iter, ckpt_every)
+        fctx.save_for_backward(grad)
+        fctx.status = status
+        return J.to(theta.dtype)
+
+    @staticmethod
+    def backward(fctx, gJ):
+        (grad,) = fctx.saved_tensors
+        return None, None, None, None, None, None, (gJ[:, None] * grad).to(gJ.dtype)
+
+
+def objective(boac: Context, geom: Geometry, meas: torch.Tensor, theta: torch.Tensor, delta_r: float,
+              n_iter: int, ckpt_every: int = 5) -> torch.Tensor:
+    """Differentiable J(theta) (see BoacObjective)."""
+    return BoacObjective.apply(boac, geom, meas, float(delta_r), int(n_iter), int(ckpt_every), theta)
+
+
+__all__ = ["Context", "Geometry", "SliceBatch", "BoacObjective", "BoacError", "objective"]

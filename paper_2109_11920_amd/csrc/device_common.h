@@ -1,0 +1,204 @@
+// Device-side building blocks shared by the BOAC kernels (gfx950, wave64).
+//
+// Geometry (Eqs. 1-2, discretised as stated in include/boac.h): a sample (a, b, k) sits at pixel-index
+// coordinates
+//     U = sigma_b cos(phi_a) - tau_k sin(phi_a) + (n-1)/2,   V = sigma_b sin(phi_a) + tau_k cos(phi_a) + (n-1)/2
+// with sigma_b = (b - (n_bins-1)/2) n / n_bins and tau_k = k - (n_samples-1)/2. Every kernel evaluates
+// U and V with the same FMA sequence (sample_uv) so that the projector, the exact-transpose gather and
+// the adjoint sweeps see bit-identical sample positions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace boac {
+
+constexpr int kWave = 64;
+
+struct DevGeom {
+    int n, na, nb, nt;
+    float dx;       // pixel size (cm)
+    float cN;       // (n-1)/2
+    float cB;       // (nb-1)/2
+    float cT;       // (nt-1)/2
+    float bscale;   // n / nb: bin spacing in pixels
+    const float2 *trig;  // [na] (cos phi_a, sin phi_a)
+};
+
+// Row band of an image staged in LDS: samples whose clamped row floor lies in [alo, ahi) use it;
+// rows alo..ahi (inclusive) are staged, columns -1..n+1, zero outside the image.
+struct Band {
+    int alo, ahi;
+    bool first, last;
+};
+
+__device__ __forceinline__ float sigma_of(const DevGeom &g, int b) {
+    return ((float)b - g.cB) * g.bscale;
+}
+__device__ __forceinline__ float tau_of(const DevGeom &g, int k) { return (float)k - g.cT; }
+
+// Per-ray constants: Ub = sigma c + cN, Vb = sigma s + cN.
+__device__ __forceinline__ void ray_base(const DevGeom &g, float sigma, float c, float s, float &Ub, float &Vb) {
+    Ub = fmaf(sigma, c, g.cN);
+    Vb = fmaf(sigma, s, g.cN);
+}
+__device__ __forceinline__ void sample_uv(float Ub, float Vb, float tau, float c, float s, float &U, float &V) {
+    U = fmaf(tau, -s, Ub);
+    V = fmaf(tau, c, Vb);
+}
+
+// ---------------------------------------------------------------- compensated arithmetic
+// Error-free transformation (Knuth TwoSum): a + b = s + e exactly. The translation units are built
+// with -ffp-contract=off so the compiler cannot fuse or reassociate these steps.
+struct Comp {
+    float s, e;
+};
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    float bp = s - a;
+    float ap = s - bp;
+    e = (a - ap) + (b - bp);
+}
+__device__ __forceinline__ void comp_add(Comp &c, float x) {
+    float s, e;
+    two_sum(c.s, x, s, e);
+    c.s = s;
+    c.e += e;
+}
+__device__ __forceinline__ void comp_merge(Comp &c, const Comp &o) {
+    float s, e;
+    two_sum(c.s, o.s, s, e);
+    c.s = s;
+    c.e += e + o.e;
+}
+__device__ __forceinline__ float comp_value(const Comp &c) { return c.s + c.e; }
+
+// Wave64 reduction of a compensated pair (cross-lane TwoSum tree).
+__device__ __forceinline__ Comp wave_reduce(Comp c) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Comp o;
+        o.s = __shfl_xor(c.s, off, kWave);
+        o.e = __shfl_xor(c.e, off, kWave);
+        comp_merge(c, o);
+    }
+    return c;
+}
+
+// Block reduction of a compensated pair; every thread must call it. Result valid in thread 0.
+// scratch: >= 2 * (blockDim/64) floats of shared memory.
+__device__ __forceinline__ Comp block_reduce(Comp c, float *scratch) {
+    c = wave_reduce(c);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[2 * wave] = c.s;
+        scratch[2 * wave + 1] = c.e;
+    }
+    __syncthreads();
+    Comp r{0.f, 0.f};
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < nw; ++w) comp_merge(r, Comp{scratch[2 * w], scratch[2 * w + 1]});
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- LDS image staging
+// Stage rows band.alo..band.ahi and columns -1..n+1 of an n x n image (element stride `stride`
+// floats, component `comp`) into lds with row pitch n+3.
+template <int NC>
+__device__ __forceinline__ void stage_band(const float *__restrict__ img, int n, const Band &band, float *lds) {
+    const int pitch = n + 3;
+    const int rows = band.ahi - band.alo + 1;
+    const int total = rows * pitch;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int rr = idx / pitch;
+        const int cc = idx - rr * pitch;
+        const int i = band.alo + rr;
+        const int l = cc - 1;
+        const bool in = (i >= 0) && (i < n) && (l >= 0) && (l < n);
+        if constexpr (NC == 1) {
+            lds[idx] = in ? img[(size_t)i * n + l] : 0.f;
+        } else {
+            float2 v = in ? reinterpret_cast<const float2 *>(img)[(size_t)i * n + l] : make_float2(0.f, 0.f);
+            reinterpret_cast<float2 *>(lds)[idx] = v;
+        }
+    }
+}
+
+// Bilinear read at (U, V) from a staged band (NC = 1 scalar image, NC = 2 interleaved pair).
+// Returns false if the sample belongs to another band (only when !SINGLE).
+struct Tap {
+    int off;     // LDS element offset of the (i0, l0) tap
+    float fu, fv;
+    bool mine;
+};
+template <bool SINGLE>
+__device__ __forceinline__ Tap make_tap(float U, float V, float nf, int pitch, const Band &band) {
+    const float Uc = fminf(fmaxf(U, -1.f), nf);
+    const float Vc = fminf(fmaxf(V, -1.f), nf);
+    const float fl = floorf(Uc);
+    const float fi = floorf(Vc);
+    Tap t;
+    t.fu = Uc - fl;
+    t.fv = Vc - fi;
+    const int i0 = (int)fi;
+    t.off = (i0 - band.alo) * pitch + ((int)fl + 1);
+    t.mine = SINGLE ? true : (i0 >= band.alo && i0 < band.ahi);
+    return t;
+}
+__device__ __forceinline__ float lerp2(const float *p, int pitch, float fu, float fv) {
+    const float v00 = p[0], v01 = p[1], v10 = p[pitch], v11 = p[pitch + 1];
+    const float top = fmaf(fu, v01 - v00, v00);
+    const float bot = fmaf(fu, v11 - v10, v10);
+    return fmaf(fv, bot - top, top);
+}
+__device__ __forceinline__ float2 lerp2x2(const float2 *p, int pitch, float fu, float fv) {
+    const float2 v00 = p[0], v01 = p[1], v10 = p[pitch], v11 = p[pitch + 1];
+    float2 r;
+    float top = fmaf(fu, v01.x - v00.x, v00.x);
+    float bot = fmaf(fu, v11.x - v10.x, v10.x);
+    r.x = fmaf(fv, bot - top, top);
+    top = fmaf(fu, v01.y - v00.y, v00.y);
+    bot = fmaf(fu, v11.y - v10.y, v10.y);
+    r.y = fmaf(fv, bot - top, top);
+    return r;
+}
+
+// k-range of a ray that may fall into `band` (conservative; membership is re-checked per sample).
+__device__ __forceinline__ void band_k_range(const DevGeom &g, const Band &band, float Vb, float c, int &k0, int &k1) {
+    if (band.first && band.last) {
+        k0 = 0;
+        k1 = g.nt - 1;
+        return;
+    }
+    const float vlo = band.first ? -1e30f : (float)band.alo;
+    const float vhi = band.last ? 1e30f : (float)band.ahi;
+    if (fabsf(c) < 1e-7f) {
+        // V is constant along the ray (up to the tiny slope): take the whole ray if it can touch
+        const float vmin = Vb - fabsf(c) * (g.cT + 1.f) - 1.f, vmax = Vb + fabsf(c) * (g.cT + 1.f) + 1.f;
+        if (vmax < vlo - 1.f || vmin > vhi + 1.f) {
+            k0 = 1;
+            k1 = 0;
+        } else {
+            k0 = 0;
+            k1 = g.nt - 1;
+        }
+        return;
+    }
+    // V(k) = Vb + (k - cT) c  =>  k = (V - Vb)/c + cT
+    float ka = (fmaxf(vlo, -4.f * (float)g.nt - 8.f) - Vb) / c + g.cT;
+    float kb = (fminf(vhi, 4.f * (float)g.nt + 8.f) - Vb) / c + g.cT;
+    float lo = fminf(ka, kb), hi = fmaxf(ka, kb);
+    lo = fmaxf(lo - 2.f, 0.f);
+    hi = fminf(hi + 2.f, (float)(g.nt - 1));
+    k0 = (int)floorf(lo);
+    k1 = (int)ceilf(hi);
+}
+
+// hat(x) = max(0, 1 - |x|)
+__device__ __forceinline__ float hat(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
+
+}  // namespace boac

@@ -1,0 +1,283 @@
+// Rasteriser (Eqs. 3-4), its adjoint, and the small reduction / elementwise kernels.
+//
+// Head outline R(theta) = sum_{k=0}^{5} c_k P_k(cos theta) (the Legendre argument read as cos theta),
+// brain where r < R, cranium where R < r < R + dR. Each pixel averages a C^1 coverage
+// H(d) = S(clamp(d/h + 1/2, 0, 1)), S(x) = 3x^2 - 2x^3, of the signed distances d = R - r and
+// d + dR over 4 x 4 sub-samples (h = pixel/4): mu = mu_b fb + mu_c (fo - fb).
+#include "launch.h"
+
+namespace boac {
+
+constexpr int kSub = 4;
+
+struct SubGeom {
+    float r, ct;  // sub-sample radius and cos(theta)
+};
+
+__device__ __forceinline__ SubGeom subsample(const DevGeom &g, int i, int l, int p, int q) {
+    const float h = g.dx * 0.25f;
+    const float y = ((float)i - g.cN) * g.dx + ((float)p - 1.5f) * h;
+    const float x = ((float)l - g.cN) * g.dx + ((float)q - 1.5f) * h;
+    SubGeom s;
+    s.r = sqrtf(fmaf(x, x, y * y));
+    s.ct = (s.r > 1e-12f) ? x / s.r : 1.f;
+    return s;
+}
+
+__device__ __forceinline__ void legendre6(float x, float P[6]) {
+    P[0] = 1.f;
+    P[1] = x;
+#pragma unroll
+    for (int n = 1; n < 5; ++n) P[n + 1] = ((float)(2 * n + 1) * x * P[n] - (float)n * P[n - 1]) / (float)(n + 1);
+}
+
+__device__ __forceinline__ float coverage(float d, float inv_h) {
+    const float x = fminf(fmaxf(fmaf(d, inv_h, 0.5f), 0.f), 1.f);
+    return x * x * (3.f - 2.f * x);
+}
+__device__ __forceinline__ float coverage_slope(float d, float inv_h) {
+    const float x = fminf(fmaxf(fmaf(d, inv_h, 0.5f), 0.f), 1.f);
+    return 6.f * x * (1.f - x) * inv_h;
+}
+
+__global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restrict__ cand, int C, float delta_r,
+                                                float *__restrict__ mu, size_t img_cs, uint32_t *status) {
+    const int cidx = blockIdx.y;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= g.n * g.n) return;
+    const int i = pix / g.n, l = pix - i * g.n;
+    const float *th = cand + (size_t)cidx * 8;
+    const float inv_h = 4.f / g.dx;
+    float fb = 0.f, fo = 0.f;
+    bool neg = false;
+#pragma unroll
+    for (int p = 0; p < kSub; ++p)
+#pragma unroll
+        for (int q = 0; q < kSub; ++q) {
+            const SubGeom s = subsample(g, i, l, p, q);
+            float P[6];
+            legendre6(s.ct, P);
+            float R = 0.f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) R = fmaf(th[k], P[k], R);
+            neg |= (R < 0.f);
+            const float db = R - s.r;
+            fb += coverage(db, inv_h);
+            fo += coverage(db + delta_r, inv_h);
+        }
+    fb *= 1.f / 16.f;
+    fo *= 1.f / 16.f;
+    // fmin/fmax inside the coverage drop NaNs: a non-finite candidate must stay visible
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) finite &= isfinite(th[k]);
+    mu[(size_t)cidx * img_cs + pix] = finite ? fmaf(th[6], fb, th[7] * (fo - fb)) : __builtin_nanf("");
+    if (status && (neg || !finite)) atomicOr(status + cidx, (neg ? 4u : 0u) | (finite ? 0u : 2u));
+}
+
+// grad_k = sum_j mubar_j dmu_j/dtheta_k, one workgroup per candidate, compensated per component.
+__global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__restrict__ cand, float delta_r,
+                                                    const float *__restrict__ mubar, size_t img_cs,
+                                                    float *__restrict__ grad) {
+    __shared__ float red[16];
+    const int cidx = blockIdx.x;
+    const float *th = cand + (size_t)cidx * 8;
+    const float mub = th[6], muc = th[7];
+    const float inv_h = 4.f / g.dx;
+    Comp acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = Comp{0.f, 0.f};
+    const float *mb = mubar + (size_t)cidx * img_cs;
+    for (int pix = threadIdx.x; pix < g.n * g.n; pix += blockDim.x) {
+        const float w = mb[pix];
+        const int i = pix / g.n, l = pix - i * g.n;
+        float gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float fb = 0.f, fo = 0.f;
+#pragma unroll
+        for (int p = 0; p < kSub; ++p)
+#pragma unroll
+            for (int q = 0; q < kSub; ++q) {
+                const SubGeom s = subsample(g, i, l, p, q);
+                float P[6];
+                legendre6(s.ct, P);
+                float R = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) R = fmaf(th[k], P[k], R);
+                const float db = R - s.r;
+                fb += coverage(db, inv_h);
+                fo += coverage(db + delta_r, inv_h);
+                const float dmu_dR = fmaf(mub - muc, coverage_slope(db, inv_h), muc * coverage_slope(db + delta_r, inv_h));
+#pragma unroll
+                for (int k = 0; k < 6; ++k) gP[k] = fmaf(dmu_dR, P[k], gP[k]);
+            }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) comp_add(acc[k], w * gP[k] * (1.f / 16.f));
+        comp_add(acc[6], w * fb * (1.f / 16.f));
+        comp_add(acc[7], w * (fo - fb) * (1.f / 16.f));
+    }
+    for (int k = 0; k < 8; ++k) {
+        const Comp r = block_reduce(acc[k], red);
+        if (threadIdx.x == 0) grad[(size_t)cidx * 8 + k] = comp_value(r);
+    }
+}
+
+__global__ void k_fill(float *p, size_t count, float v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_mul_copy(const float *a, const float *b, float *out, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = a[i] * b[i];
+}
+
+__global__ void k_copy(const float *src, float *dst, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Adjoint of the objective terms y - S ln y at y = y^K.
+__global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs) {
+    const size_t total = (size_t)C * nrays;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = t / nrays, i = t - c * nrays;
+        const float y = yK[c * sino_cs + i], S = meas[i];
+        ybar[c * sino_cs + i] = (y > 0.f) ? 1.f - S / y : (S == 0.f ? 1.f : 0.f);
+    }
+}
+
+// sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup.
+__global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
+    __shared__ float red[16];
+    Comp c{0.f, 0.f};
+    bool neg = false;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const float S = meas[i];
+        neg |= !(S >= 0.f);
+        if (S > 0.f) comp_add(c, lgammaf(S + 1.f));
+    }
+    const Comp r = block_reduce(c, red);
+    if (threadIdx.x == 0) {
+        out[0] = make_float2(r.s, r.e);
+    }
+    if (neg) atomicOr(flag, 8u);
+}
+
+// J[c] = sum of the per-workgroup NLL partials + the ln Gamma constant; status bits.
+__global__ void k_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
+                             float *obj, uint32_t *status) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    Comp acc{lg->x, lg->y};
+    for (int j = 0; j < chunks; ++j) {
+        const float2 p = partial[(size_t)c * chunks + j];
+        comp_merge(acc, Comp{p.x, p.y});
+    }
+    const float J = comp_value(acc);
+    obj[c] = J;
+    if (status) {
+        uint32_t st = status[c] | (meas_flag ? *meas_flag : 0u);
+        if (!isfinite(J)) st |= 2u;
+        status[c] = st;
+    }
+}
+
+// Reverse of F^{n+1} = F^n Q^n (Q^n = b^n / s):
+//   bbar = Fbar F^n / s,  sbar -= Fbar F^{n+1} / s,  Fbar_direct = Fbar Q^n      (0 where s <= 0)
+__global__ void k_adj_elem(AdjElemArgs A) {
+    const size_t total = (size_t)A.npix * A.C;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = t / A.npix, j = t - c * A.npix;
+        const size_t o = c * A.img_cs + j;
+        const float fb = A.fbar[o], F = A.F[o], Q = A.Q[o], sv = A.s[o];
+        float bbar = 0.f, sb = 0.f;
+        if (sv > 0.f) {
+            bbar = fb * F / sv;
+            sb = fb * (F * Q) / sv;
+        }
+        A.sbar[o] -= sb;
+        A.bbarF[o] = make_float2(bbar, F);
+        A.fbar_direct[o] = fb * Q;
+    }
+}
+
+__global__ void k_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    bool bad = false;
+    for (int k = 0; k < 8; ++k) {
+        const float v = grad[(size_t)c * 8 + k];
+        bad |= !isfinite(v);
+        d_grad[(size_t)c * 8 + k] = v;
+    }
+    if (bad && status) status[c] |= 2u;
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned fill_blocks(size_t count) {
+    size_t b = (count + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta_r, float *mu, size_t img_cs,
+                         uint32_t *status, hipStream_t st) {
+    for (int c0 = 0; c0 < C; c0 += 65535) {
+        const int n = C - c0 < 65535 ? C - c0 : 65535;
+        const dim3 grid((unsigned)((g.n * g.n + 255) / 256), (unsigned)n);
+        hipLaunchKernelGGL(k_raster, grid, dim3(256), 0, st, g, cand + (size_t)c0 * 8, n, delta_r,
+                           mu + (size_t)c0 * img_cs, img_cs, status ? status + c0 : nullptr);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_raster_adj(const DevGeom &g, const float *cand, int C, float delta_r, const float *mubar,
+                             size_t img_cs, float *grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_raster_adj, dim3((unsigned)C), dim3(256), 0, st, g, cand, delta_r, mubar, img_cs, grad);
+    return hipGetLastError();
+}
+hipError_t launch_fill(float *p, size_t count, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(fill_blocks(count)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(count)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_mul_copy, dim3(fill_blocks(count)), dim3(256), 0, st, a, b, out, count);
+    return hipGetLastError();
+}
+hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(fill_blocks(count)), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_ybar_final, dim3(fill_blocks((size_t)C * nrays)), dim3(256), 0, st, meas, yK, ybar, C, nrays,
+                       sino_cs);
+    return hipGetLastError();
+}
+hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_lgamma_sum, dim3(1), dim3(256), 0, st, meas, count, out, flag);
+    return hipGetLastError();
+}
+hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
+                             float *obj, uint32_t *status, hipStream_t st) {
+    hipLaunchKernelGGL(k_nll_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, partial, chunks, C, lg,
+                       meas_flag, obj, status);
+    return hipGetLastError();
+}
+hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_elem, dim3(fill_blocks((size_t)a.npix * a.C)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, grad, C, d_grad, status);
+    return hipGetLastError();
+}
+
+}  // namespace boac

@@ -1,0 +1,405 @@
+// Ray-driven kernels: one thread per ray, walking its samples along k, with the sampled image staged
+// in LDS (whole image, or row bands for large n).
+//
+//   k_att     attenuation scan, Eq. (1) inner integral: m = W mu, L_k = dx (m_k/2 + sum_{k'>k} m_k'),
+//             att = exp(-L), scanned from the detector end with a compensated running sum.
+//   k_fwd     attenuated projection, Eq. (2): y = dx sum_k att (W f), compensated; epilogues give the
+//             MLEM ratio S/y, the Poisson NLL terms of Eq. (5), or the adjoint of the ratio.
+//   k_attbar  adjoint of att for one MLEM iteration: att_bar += dx (r W bbar + ybar W F).
+//   k_tail    sensitivity adjoint, att = exp(-L) and the scan's transpose (a prefix sum).
+//
+// Layout: att and its adjoint are [cand][angle][k][bin] (bin fastest), so the threads of a wave
+// (consecutive bins of one angle) read and write consecutive addresses at each k.
+#include "launch.h"
+
+namespace boac {
+
+// Map a flat workgroup id to (candidate, chunk) so that all chunks of one candidate run on the same
+// XCD (workgroups are dispatched round-robin over the 8 XCDs); they share the candidate's image in L2.
+__device__ __forceinline__ void ray_block(int chunks, int C, int &cand, int &chunk) {
+    const int total = chunks * C;
+    int id = blockIdx.x;
+    if ((total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
+    cand = id / chunks;
+    chunk = id - cand * chunks;
+}
+
+constexpr int kMaxRpt = 4;
+
+// ------------------------------------------------------------------ attenuation
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
+                                             const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
+                                             size_t att_cs) {
+    extern __shared__ float lds[];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int nrays = g.na * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    const float *img = mu + cand * img_cs;
+    float *out = att + cand * att_cs;
+
+    for (int bi = 0; bi < bands.count; ++bi) {
+        const Band band = bands.b[bi];
+        __syncthreads();
+        stage_band<1>(img, g.n, band, lds);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const float2 cs = g.trig[a];
+            float Ub, Vb;
+            ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+            float *col = out + (size_t)a * g.nt * g.nb + b;
+            if constexpr (SINGLE) {
+                // single pass from the detector end: running suffix sum T = sum_{k'>k} m_k'
+                Comp T{0.f, 0.f};
+                for (int k = g.nt - 1; k >= 0; --k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<true>(U, V, nf, pitch, band);
+                    const float m = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                    const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
+                    col[(size_t)k * g.nb] = expf(-L);
+                    comp_add(T, m);
+                }
+            } else {
+                // pass 1 of 2: store m_k of the samples in this band
+                int k0, k1;
+                band_k_range(g, band, Vb, cs.x, k0, k1);
+                for (int k = k0; k <= k1; ++k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                    if (!t.mine) continue;
+                    col[(size_t)k * g.nb] = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                }
+            }
+        }
+    }
+    if constexpr (!SINGLE) {
+        // pass 2: scan the stored m_k (written by this same thread) from the detector end
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            float *col = out + (size_t)a * g.nt * g.nb + b;
+            Comp T{0.f, 0.f};
+            for (int k = g.nt - 1; k >= 0; --k) {
+                const float m = col[(size_t)k * g.nb];
+                const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
+                col[(size_t)k * g.nb] = expf(-L);
+                comp_add(T, m);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forward projection
+template <int MODE, bool SINGLE>
+__global__ __launch_bounds__(256) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+    extern __shared__ float lds[];
+    __shared__ float red[16];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int nrays = g.na * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    const float *att = A.att + cand * A.att_cs;
+    const float *img = A.img + cand * A.img_cs;
+
+    Comp acc[kMaxRpt];
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = Comp{0.f, 0.f};
+
+    for (int bi = 0; bi < bands.count; ++bi) {
+        const Band band = bands.b[bi];
+        __syncthreads();
+        if (A.img_comps == 1) {
+            stage_band<1>(img, g.n, band, lds);
+        } else {
+            // component 0 of an interleaved pair image
+            const int rows = band.ahi - band.alo + 1;
+            const int total = rows * pitch;
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int rr = idx / pitch, cc = idx - rr * pitch;
+                const int i = band.alo + rr, l = cc - 1;
+                const bool in = (i >= 0) && (i < g.n) && (l >= 0) && (l < g.n);
+                lds[idx] = in ? img[((size_t)i * g.n + l) * A.img_comps] : 0.f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const float2 cs = g.trig[a];
+            float Ub, Vb;
+            ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+            const float *col = att + (size_t)a * g.nt * g.nb + b;
+            int k0 = 0, k1 = g.nt - 1;
+            if constexpr (!SINGLE) band_k_range(g, band, Vb, cs.x, k0, k1);
+            Comp c = acc[j];
+#pragma unroll 4
+            for (int k = k0; k <= k1; ++k) {
+                float U, V;
+                sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                const Tap t = make_tap<SINGLE>(U, V, nf, pitch, band);
+                if (!SINGLE && !t.mine) continue;
+                const float v = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                comp_add(c, col[(size_t)k * g.nb] * v);
+            }
+            acc[j] = c;
+        }
+    }
+
+    // epilogues
+    Comp nll{0.f, 0.f};
+    bool zero_proj = false;
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) {
+        if (j >= rpt) break;
+        const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+        if (ray >= nrays) continue;
+        const size_t si = cand * A.sino_cs + ray;
+        const float y = g.dx * comp_value(acc[j]);
+        if constexpr (MODE == FWD_PROJ) {
+            A.y_out[si] = y;
+        } else if constexpr (MODE == FWD_RATIO) {
+            const float S = A.meas[ray];
+            A.r_out[si] = (y > 0.f) ? S / y : 0.f;
+            if (A.y_out) A.y_out[si] = y;
+        } else if constexpr (MODE == FWD_YBAR) {
+            // y here is r_bar = A bbar; ybar = -r_bar * r / y^n where y^n > 0
+            const float yn = A.y_in[si];
+            A.r_out[si] = (yn > 0.f) ? -(y * A.r_in[si]) / yn : 0.f;
+        } else {  // FWD_NLL
+            const float S = A.meas[ray];
+            if (A.y_out) A.y_out[si] = y;
+            float term;
+            if (S > 0.f) {
+                if (y > 0.f) {
+                    term = y - S * logf(y);
+                } else if (y <= 0.f) {
+                    term = __builtin_inff();
+                    zero_proj = true;
+                } else {
+                    term = y;  // NaN propagates (flagged as non-finite at the end)
+                }
+            } else {
+                term = y;
+            }
+            comp_add(nll, term);
+        }
+    }
+    if constexpr (MODE == FWD_NLL) {
+        if (zero_proj && A.status) atomicOr(A.status + cand, 1u);
+        const Comp r = block_reduce(nll, red);
+        if (threadIdx.x == 0) A.partial[(size_t)cand * chunks + chunk] = make_float2(r.s, r.e);
+    }
+}
+
+// ------------------------------------------------------------------ att adjoint accumulation
+template <int NIMG, bool SINGLE>
+__global__ __launch_bounds__(256) void k_attbar(DevGeom g, Bands bands, int rpt, int chunks, int C, AttbarArgs A) {
+    extern __shared__ float lds[];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int nrays = g.na * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    float *ab = A.attbar + cand * A.att_cs;
+    const float *img = A.img2 + cand * A.img_cs;
+
+    for (int bi = 0; bi < bands.count; ++bi) {
+        const Band band = bands.b[bi];
+        __syncthreads();
+        stage_band<NIMG>(img, g.n, band, lds);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const float2 cs = g.trig[a];
+            float Ub, Vb;
+            ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+            const size_t si = cand * A.sino_cs + ray;
+            const float yb = g.dx * A.ybar[si];
+            const float rr = (NIMG == 2) ? g.dx * A.r[si] : 0.f;
+            float *col = ab + (size_t)a * g.nt * g.nb + b;
+            int k0 = 0, k1 = g.nt - 1;
+            if constexpr (!SINGLE) band_k_range(g, band, Vb, cs.x, k0, k1);
+#pragma unroll 4
+            for (int k = k0; k <= k1; ++k) {
+                float U, V;
+                sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                const Tap t = make_tap<SINGLE>(U, V, nf, pitch, band);
+                if (!SINGLE && !t.mine) continue;
+                float add;
+                if constexpr (NIMG == 2) {
+                    const float2 v = lerp2x2(reinterpret_cast<const float2 *>(lds) + t.off, pitch, t.fu, t.fv);
+                    add = fmaf(rr, v.x, yb * v.y);
+                } else {
+                    add = yb * lerp2(lds + t.off, pitch, t.fu, t.fv);
+                }
+                float *p = col + (size_t)k * g.nb;
+                *p = A.accumulate ? (*p + add) : add;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ tail of the attenuation adjoint
+// att_bar += dx W s_bar;  L_bar = -att * att_bar;  m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k')
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
+    extern __shared__ float lds[];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int nrays = g.na * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    const float *att = A.att + cand * A.att_cs;
+    float *ab = A.attbar + cand * A.att_cs;
+    const float *img = A.sbar + cand * A.img_cs;
+
+    for (int bi = 0; bi < bands.count; ++bi) {
+        const Band band = bands.b[bi];
+        __syncthreads();
+        stage_band<1>(img, g.n, band, lds);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const float2 cs = g.trig[a];
+            float Ub, Vb;
+            ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+            const size_t off = (size_t)a * g.nt * g.nb + b;
+            if constexpr (SINGLE) {
+                Comp P{0.f, 0.f};
+                for (int k = 0; k < g.nt; ++k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<true>(U, V, nf, pitch, band);
+                    const float wsb = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                    const size_t idx = off + (size_t)k * g.nb;
+                    const float abar = fmaf(g.dx, wsb, ab[idx]);
+                    const float Lbar = -att[idx] * abar;
+                    ab[idx] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                    comp_add(P, Lbar);
+                }
+            } else {
+                int k0, k1;
+                band_k_range(g, band, Vb, cs.x, k0, k1);
+                for (int k = k0; k <= k1; ++k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                    if (!t.mine) continue;
+                    const size_t idx = off + (size_t)k * g.nb;
+                    ab[idx] = fmaf(g.dx, lerp2(lds + t.off, pitch, t.fu, t.fv), ab[idx]);
+                }
+            }
+        }
+    }
+    if constexpr (!SINGLE) {
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays) continue;
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const size_t off = (size_t)a * g.nt * g.nb + b;
+            Comp P{0.f, 0.f};
+            for (int k = 0; k < g.nt; ++k) {
+                const size_t idx = off + (size_t)k * g.nb;
+                const float Lbar = -att[idx] * ab[idx];
+                ab[idx] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                comp_add(P, Lbar);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static dim3 ray_grid(const RayCfg &rc, int C) { return dim3((unsigned)(rc.chunks * C)); }
+
+hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
+                      size_t img_cs, size_t att_cs, int C, hipStream_t st) {
+    if (rc.single)
+        hipLaunchKernelGGL(k_att<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
+                           mu, att, img_cs, att_cs);
+    else
+        hipLaunchKernelGGL(k_att<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
+                           C, mu, att, img_cs, att_cs);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
+                     hipStream_t st) {
+    if (rc.single)
+        hipLaunchKernelGGL((k_fwd<MODE, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+    else
+        hipLaunchKernelGGL((k_fwd<MODE, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+}
+
+hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
+                      hipStream_t st) {
+    switch (mode) {
+        case FWD_PROJ: fwd_mode<FWD_PROJ>(g, rc, bands, a, C, st); break;
+        case FWD_RATIO: fwd_mode<FWD_RATIO>(g, rc, bands, a, C, st); break;
+        case FWD_NLL: fwd_mode<FWD_NLL>(g, rc, bands, a, C, st); break;
+        case FWD_YBAR: fwd_mode<FWD_YBAR>(g, rc, bands, a, C, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_attbar(int nimg, const DevGeom &g, const RayCfg &rc, const Bands &bands, const AttbarArgs &a,
+                         int C, hipStream_t st) {
+    if (nimg == 2) {
+        if (rc.single)
+            hipLaunchKernelGGL((k_attbar<2, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                               rc.chunks, C, a);
+        else
+            hipLaunchKernelGGL((k_attbar<2, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                               rc.chunks, C, a);
+    } else {
+        if (rc.single)
+            hipLaunchKernelGGL((k_attbar<1, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                               rc.chunks, C, a);
+        else
+            hipLaunchKernelGGL((k_attbar<1, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                               rc.chunks, C, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
+                       hipStream_t st) {
+    if (rc.single)
+        hipLaunchKernelGGL(k_tail<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
+                           a);
+    else
+        hipLaunchKernelGGL(k_tail<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
+                           C, a);
+    return hipGetLastError();
+}
+
+}  // namespace boac

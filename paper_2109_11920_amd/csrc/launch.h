@@ -1,0 +1,122 @@
+// Host-side launch descriptors shared between the kernel translation units and the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace boac {
+
+constexpr int kMaxBands = 16;
+struct Bands {
+    int count;
+    Band b[kMaxBands];
+};
+
+// A ray-kernel launch covers `cand` candidates of one slice, each with n_angles * n_bins rays split
+// in chunks of block * rpt rays.
+struct RayCfg {
+    int block;   // threads per workgroup (64..256, multiple of 64)
+    int rpt;     // rays per thread (1..4)
+    int chunks;  // workgroups per candidate
+    size_t lds;  // dynamic LDS bytes
+    bool single; // whole image staged at once
+};
+
+enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2, FWD_YBAR = 3 };
+
+struct FwdArgs {
+    const float *att;     // [C][na][nt][nb]
+    const float *img;     // [C][n][n] x img_comps interleaved (component 0 is sampled)
+    const float *meas;    // [na][nb]
+    float *y_out;         // [C][na][nb] or null
+    float *r_out;         // RATIO: r; YBAR: ybar
+    const float *y_in;    // YBAR
+    const float *r_in;    // YBAR
+    float2 *partial;      // NLL: [C][chunks]
+    uint32_t *status;     // NLL: [C] or null
+    size_t att_cs, img_cs, sino_cs;
+    int img_comps;        // 1 or 2
+};
+
+struct AttbarArgs {
+    float *attbar;        // [C][na][nt][nb]
+    const float *img2;    // NIMG=2: interleaved (bbar, F); NIMG=1: F
+    const float *r;       // [C][na][nb] (NIMG=2)
+    const float *ybar;    // [C][na][nb]
+    size_t att_cs, img_cs, sino_cs;
+    int accumulate;       // 0: write, 1: add
+};
+
+struct TailArgs {
+    const float *att;
+    float *attbar;        // in: att_bar, out: m_bar
+    const float *sbar;    // [C][n][n]
+    size_t att_cs, img_cs;
+};
+
+enum BackMode { BACK_PLAIN = 0, BACK_SENS = 1, BACK_MLEM = 2, BACK_FIELD = 3, BACK_ADJ = 4 };
+
+struct BackCfg {
+    int tw, th;           // tile (pixels)
+    int ppt;              // pixels per thread (tw*th/256)
+    int cg;               // candidates per workgroup
+    int hb;               // bin half-window
+    int wbmax, wkmax;     // footprint rectangle bound
+    int tiles_x, tiles_y; // tiles per image
+    size_t lds;
+};
+
+struct BackArgs {
+    const float *att;     // [C][na][nt][nb]
+    const float *z;       // PLAIN/MLEM/ADJ: per-ray weights [C][na][nb]; FIELD: [C][na][nt][nb]
+    const float *F;       // MLEM: current image
+    const float *s;       // MLEM: sensitivity
+    const float *aux;     // ADJ: direct part of F_bar
+    float *out;           // [C][n][n]
+    float *q_out;         // MLEM: update factor b/s (nullable)
+    size_t att_cs, sino_cs, img_cs;
+    int C;
+};
+
+struct AdjElemArgs {
+    const float *fbar;    // F_bar^{n+1}
+    const float *F;       // F^n
+    const float *Q;       // Q^n
+    const float *s;       // sensitivity
+    float *sbar;          // accumulated s_bar (read-modify-write)
+    float2 *bbarF;        // out: (bbar^n, F^n) interleaved
+    float *fbar_direct;   // out
+    size_t img_cs;
+    int npix, C;
+};
+
+// ---- launchers (each returns the hipError_t of the launch) ----
+hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta_r, float *mu, size_t img_cs,
+                         uint32_t *status, hipStream_t st);
+hipError_t launch_raster_adj(const DevGeom &g, const float *cand, int C, float delta_r, const float *mubar,
+                             size_t img_cs, float *grad, hipStream_t st);
+hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
+                      size_t img_cs, size_t att_cs, int C, hipStream_t st);
+hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
+                      hipStream_t st);
+hipError_t launch_attbar(int nimg, const DevGeom &g, const RayCfg &rc, const Bands &bands, const AttbarArgs &a,
+                         int C, hipStream_t st);
+hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
+                       hipStream_t st);
+hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st);
+hipError_t launch_fill(float *p, size_t count, float v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st);
+hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag, hipStream_t st);
+hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
+                             float *obj, uint32_t *status, hipStream_t st);
+hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st);
+hipError_t launch_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status, hipStream_t st);
+hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st);
+hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st);
+hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
+                             hipStream_t st);
+
+}  // namespace boac

@@ -1,0 +1,1069 @@
+// libboac host runtime: argument validation, device scratch, launch plans (defaults + autotuner
+// cache), kernel-time instrumentation, HIP-graph capture of batched evaluations, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/boac.h"
+#include "launch.h"
+
+using namespace boac;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static boac_status fail(boac_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return fail(BOAC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));        \
+    } while (0)
+
+#define BOAC_TRY(expr)                    \
+    do {                                  \
+        boac_status _s = (expr);          \
+        if (_s != BOAC_OK) return _s;     \
+    } while (0)
+
+// ------------------------------------------------------------------ validation (no HIP calls)
+static constexpr size_t kLdsBudget = 160 * 1024 - 256;  // gfx950: 160 KiB of LDS per workgroup
+
+static int bin_half_window(const boac_geom &g) {
+    const double rho = (double)g.n_bins / (double)g.n;
+    return (int)std::ceil(std::sqrt(2.0) * rho - 0.5);
+}
+
+static boac_status check_geom(const boac_geom *g) {
+    if (!g) return fail(BOAC_EINVAL, "geometry pointer is NULL");
+    if (g->n < 2 || g->n > 1024) return fail(BOAC_ESHAPE, "n = %d outside [2, 1024]", g->n);
+    if (g->n_angles < 2 || g->n_angles > 8192) return fail(BOAC_ESHAPE, "n_angles = %d outside [2, 8192]", g->n_angles);
+    if (g->n_bins < 2 || g->n_bins > 4096) return fail(BOAC_ESHAPE, "n_bins = %d outside [2, 4096]", g->n_bins);
+    if (g->n_samples < 2 || g->n_samples > 1024)
+        return fail(BOAC_ESHAPE, "n_samples = %d outside [2, 1024]", g->n_samples);
+    if (!(g->pixel_cm > 0.f) || !std::isfinite(g->pixel_cm))
+        return fail(BOAC_ESHAPE, "pixel_cm = %g must be positive and finite", (double)g->pixel_cm);
+    const int hb = bin_half_window(*g);
+    if (hb < 1 || hb > 3)
+        return fail(BOAC_ESHAPE, "n_bins / n = %g gives a bin window of %d; supported 1..3", (double)g->n_bins / g->n, hb);
+    if ((size_t)(g->n + 3) * 4 * 2 * 2 > kLdsBudget)
+        return fail(BOAC_ESHAPE, "n = %d too large for LDS row staging", g->n);
+    return BOAC_OK;
+}
+
+static boac_status check_ptr(const void *p, const char *name, bool nullable = false) {
+    if (!p) return nullable ? BOAC_OK : fail(BOAC_EINVAL, "%s is NULL", name);
+    if (((uintptr_t)p & 15u) != 0) return fail(BOAC_EINVAL, "%s is not 16-byte aligned", name);
+    return BOAC_OK;
+}
+
+static boac_status check_count(int32_t C) {
+    if (C < 1 || C > (1 << 20)) return fail(BOAC_EINVAL, "candidate count C = %d outside [1, 2^20]", C);
+    return BOAC_OK;
+}
+
+// ------------------------------------------------------------------ context
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct PendingTiming {
+    int kind;
+    hipEvent_t e0, e1;
+    double bytes;
+};
+
+struct Plan {
+    RayCfg ray1, ray2;  // ray kernels staging one image / an interleaved pair
+    Bands bands1, bands2;
+    BackCfg back;
+};
+
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct boac_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::map<std::string, DevBuf> bufs;
+    std::map<std::vector<int>, float2 *> trig;
+    std::map<std::string, std::vector<int>> tune;
+    bool profiling = false;
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> free_events;
+    int64_t stat_count[BOAC_K_COUNT] = {};
+    double stat_ms[BOAC_K_COUNT] = {};
+    double stat_bytes[BOAC_K_COUNT] = {};
+    std::vector<GraphEntry> graphs;
+    bool capturing = false;
+    bool scratch_changed = false;
+};
+
+static boac_status ensure(boac_ctx *ctx, const char *name, size_t bytes, void **out) {
+    DevBuf &b = ctx->bufs[name];
+    if (b.bytes < bytes) {
+        if (ctx->capturing) return fail(BOAC_EDEVICE, "scratch '%s' must grow during graph capture", name);
+        if (b.p) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 8;
+        want = (want + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
+        hipError_t e = hipMalloc(&b.p, want);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            (void)hipGetLastError();
+            return fail(BOAC_ENOMEM, "scratch '%s': hipMalloc(%zu) failed: %s", name, want, hipGetErrorString(e));
+        }
+        b.bytes = want;
+        ctx->scratch_changed = true;
+    }
+    *out = b.p;
+    return BOAC_OK;
+}
+
+template <typename T>
+static boac_status ensure_t(boac_ctx *ctx, const char *name, size_t count, T **out) {
+    void *p = nullptr;
+    BOAC_TRY(ensure(ctx, name, count * sizeof(T), &p));
+    *out = (T *)p;
+    return BOAC_OK;
+}
+
+// cos/sin of 2 pi a / na in double, exact at multiples of 90 degrees, rounded to float
+static boac_status trig_table(boac_ctx *ctx, int na, const float2 **out) {
+    std::vector<int> key{na};
+    auto it = ctx->trig.find(key);
+    if (it != ctx->trig.end()) {
+        *out = it->second;
+        return BOAC_OK;
+    }
+    if (ctx->capturing) return fail(BOAC_EDEVICE, "trig table upload during graph capture");
+    std::vector<float2> h(na);
+    for (int a = 0; a < na; ++a) {
+        // reduce to the first quadrant on integers so that 0/90/180/270 deg are exact
+        const long num = 4L * a;  // angle = 2 pi a / na = (pi/2) * (4a / na)
+        const long quad = num / na;
+        const long rem = num - quad * na;
+        const double frac = (double)rem / (double)na * (M_PI / 2.0);
+        double c = std::cos(frac), s = std::sin(frac);
+        if (rem == 0) {
+            c = 1.0;
+            s = 0.0;
+        }
+        double cc, ss;
+        switch (quad & 3) {
+            case 0: cc = c; ss = s; break;
+            case 1: cc = -s; ss = c; break;
+            case 2: cc = -c; ss = -s; break;
+            default: cc = s; ss = -c; break;
+        }
+        h[a] = make_float2((float)cc, (float)ss);
+    }
+    float2 *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(float2) * na));
+    HIP_TRY(hipMemcpy(d, h.data(), sizeof(float2) * na, hipMemcpyHostToDevice));
+    ctx->trig[key] = d;
+    *out = d;
+    return BOAC_OK;
+}
+
+static boac_status dev_geom(boac_ctx *ctx, const boac_geom &g, DevGeom *dg) {
+    dg->n = g.n;
+    dg->na = g.n_angles;
+    dg->nb = g.n_bins;
+    dg->nt = g.n_samples;
+    dg->dx = g.pixel_cm;
+    dg->cN = 0.5f * (float)(g.n - 1);
+    dg->cB = 0.5f * (float)(g.n_bins - 1);
+    dg->cT = 0.5f * (float)(g.n_samples - 1);
+    dg->bscale = (float)g.n / (float)g.n_bins;
+    return trig_table(ctx, g.n_angles, &dg->trig);
+}
+
+// ------------------------------------------------------------------ plans
+static void make_bands(int n, int comps, RayCfg *rc, Bands *bands) {
+    const size_t pitch_bytes = (size_t)(n + 3) * 4 * comps;
+    const size_t full = pitch_bytes * (n + 3);
+    if (full <= kLdsBudget) {
+        rc->single = true;
+        bands->count = 1;
+        bands->b[0] = Band{-1, n + 1, true, true};
+        rc->lds = full;
+        return;
+    }
+    rc->single = false;
+    int rows = (int)(kLdsBudget / pitch_bytes) - 1;  // assigned rows per band (staged = rows + 1)
+    const int span = n + 2;                           // assigned range [-1, n+1)
+    int count = (span + rows - 1) / rows;
+    if (count > kMaxBands) count = kMaxBands;
+    rows = (span + count - 1) / count;
+    bands->count = count;
+    for (int i = 0; i < count; ++i) {
+        const int lo = -1 + i * rows;
+        const int hi = std::min(-1 + (i + 1) * rows, n + 1);
+        bands->b[i] = Band{lo, hi, i == 0, i == count - 1};
+    }
+    rc->lds = pitch_bytes * (size_t)(rows + 1);
+}
+
+static std::string shape_key(const char *kind, const boac_geom &g, int C, int extra) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s:%dx%dx%dx%d:%d:%d", kind, g.n, g.n_angles, g.n_bins, g.n_samples, C, extra);
+    return buf;
+}
+
+static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands) {
+    make_bands(g.n, comps, rc, bands);
+    const int nrays = g.n_angles * g.n_bins;
+    rc->block = 256;
+    rc->rpt = 1;
+    const int target = 2 * ctx->n_cu;
+    for (int rpt : {4, 2, 1}) {
+        const int chunks = (nrays + 256 * rpt - 1) / (256 * rpt);
+        if ((long)chunks * C >= target || rpt == 1) {
+            rc->rpt = rpt;
+            break;
+        }
+    }
+    auto it = ctx->tune.find(shape_key("ray", g, C, comps));
+    if (it != ctx->tune.end() && it->second.size() >= 2) {
+        const int blk = it->second[0], rpt = it->second[1];
+        if ((blk == 64 || blk == 128 || blk == 256) && rpt >= 1 && rpt <= 4) {
+            rc->block = blk;
+            rc->rpt = rpt;
+        }
+    }
+    rc->chunks = (nrays + rc->block * rc->rpt - 1) / (rc->block * rc->rpt);
+}
+
+static void back_fill(const boac_geom &g, BackCfg *bc) {
+    bc->th = 256 * bc->ppt / bc->tw;
+    bc->hb = bin_half_window(g);
+    const double diag = std::sqrt((double)(bc->tw - 1) * (bc->tw - 1) + (double)(bc->th - 1) * (bc->th - 1));
+    const double rho = (double)g.n_bins / g.n;
+    bc->wbmax = (int)std::ceil(diag * rho) + 2 * bc->hb + 6;
+    bc->wkmax = (int)std::ceil(diag) + 8;
+    bc->tiles_x = (g.n + bc->tw - 1) / bc->tw;
+    bc->tiles_y = (g.n + bc->th - 1) / bc->th;
+    bc->lds = (size_t)bc->cg * bc->wbmax * bc->wkmax * sizeof(float);
+}
+
+static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
+    // defaults: large tiles and several candidates per workgroup when the batch is big enough
+    bc->tw = 32;
+    bc->ppt = 4;
+    bc->cg = 1;
+    const int target = 2 * ctx->n_cu;
+    for (int cg : {4, 2, 1}) {
+        if (C < cg) continue;
+        bc->cg = cg;
+        back_fill(g, bc);
+        if ((long)bc->tiles_x * bc->tiles_y * ((C + cg - 1) / cg) >= target) break;
+    }
+    back_fill(g, bc);
+    if ((long)bc->tiles_x * bc->tiles_y * ((C + bc->cg - 1) / bc->cg) < ctx->n_cu) {
+        bc->tw = 16;
+        bc->ppt = 1;
+        back_fill(g, bc);
+    }
+    auto it = ctx->tune.find(shape_key("back", g, C, 0));
+    if (it != ctx->tune.end() && it->second.size() >= 3) {
+        BackCfg t = *bc;
+        t.tw = it->second[0];
+        t.ppt = it->second[1];
+        t.cg = it->second[2];
+        const bool ok = (t.tw == 16 || t.tw == 32 || t.tw == 64) && (t.ppt == 1 || t.ppt == 2 || t.ppt == 4) &&
+                        (t.cg == 1 || t.cg == 2 || t.cg == 4 || t.cg == 8) && (256 * t.ppt) % t.tw == 0;
+        if (ok) {
+            back_fill(g, &t);
+            if (t.lds <= kLdsBudget) *bc = t;
+        }
+    }
+    while (bc->lds > kLdsBudget && bc->cg > 1) {
+        bc->cg /= 2;
+        back_fill(g, bc);
+    }
+}
+
+static Plan make_plan(boac_ctx *ctx, const boac_geom &g, int C) {
+    Plan p;
+    ray_plan(ctx, g, C, 1, &p.ray1, &p.bands1);
+    ray_plan(ctx, g, C, 2, &p.ray2, &p.bands2);
+    back_plan(ctx, g, C, &p.back);
+    return p;
+}
+
+// ------------------------------------------------------------------ instrumentation
+static hipEvent_t take_event(boac_ctx *ctx) {
+    if (!ctx->free_events.empty()) {
+        hipEvent_t e = ctx->free_events.back();
+        ctx->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename F>
+static boac_status timed(boac_ctx *ctx, int kind, double bytes, hipStream_t st, F &&launch) {
+    const bool t = ctx->profiling && !ctx->capturing;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (t) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+        if (e0 && e1) HIP_TRY(hipEventRecord(e0, st));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(BOAC_EDEVICE, "kernel launch (kind %d) failed: %s", kind, hipGetErrorString(e));
+    if (t && e0 && e1) {
+        HIP_TRY(hipEventRecord(e1, st));
+        ctx->pending.push_back(PendingTiming{kind, e0, e1, bytes});
+    }
+    return BOAC_OK;
+}
+
+static boac_status drain_timings(boac_ctx *ctx) {
+    for (auto &p : ctx->pending) {
+        HIP_TRY(hipEventSynchronize(p.e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.e0, p.e1));
+        ctx->stat_count[p.kind] += 1;
+        ctx->stat_ms[p.kind] += ms;
+        ctx->stat_bytes[p.kind] += p.bytes;
+        ctx->free_events.push_back(p.e0);
+        ctx->free_events.push_back(p.e1);
+    }
+    ctx->pending.clear();
+    return BOAC_OK;
+}
+
+// ------------------------------------------------------------------ evaluation pipeline
+struct Sizes {
+    size_t I, Y, V;  // elements per candidate: image, sinogram, attenuation tensor
+};
+static Sizes sizes_of(const boac_geom &g) {
+    return Sizes{(size_t)g.n * g.n, (size_t)g.n_angles * g.n_bins, (size_t)g.n_angles * g.n_bins * g.n_samples};
+}
+
+// Bytes models (algorithmic HBM traffic per launch) used by the instrumentation.
+static double bytes_att(const Sizes &z, int C) { return 4.0 * C * (double)(z.I + z.V); }
+static double bytes_fwd(const Sizes &z, int C) { return 4.0 * C * (double)(z.V + z.I + 2 * z.Y); }
+static double bytes_back(const Sizes &z, int C, int mode) {
+    double per = (double)z.V + z.I;  // att read + image written
+    if (mode == BACK_PLAIN || mode == BACK_MLEM || mode == BACK_ADJ) per += z.Y;
+    if (mode == BACK_MLEM) per += 2.0 * z.I;
+    if (mode == BACK_ADJ) per += z.I;
+    if (mode == BACK_FIELD) per += 0.0;
+    return 4.0 * C * per;
+}
+
+static boac_status run_att(boac_ctx *ctx, const DevGeom &dg, const Plan &p, const Sizes &z, const float *mu,
+                           float *att, int C, hipStream_t st) {
+    return timed(ctx, BOAC_K_ATT, bytes_att(z, C), st,
+                 [&] { return launch_att(dg, p.ray1, p.bands1, mu, att, z.I, z.V, C, st); });
+}
+
+static boac_status run_fwd(boac_ctx *ctx, int mode, const DevGeom &dg, const Plan &p, const Sizes &z,
+                           const FwdArgs &a, int C, hipStream_t st) {
+    return timed(ctx, BOAC_K_FWD, bytes_fwd(z, C), st,
+                 [&] { return launch_fwd(mode, dg, p.ray1, p.bands1, a, C, st); });
+}
+
+static boac_status run_back(boac_ctx *ctx, int mode, const DevGeom &dg, const Plan &p, const Sizes &z,
+                            const BackArgs &a, hipStream_t st) {
+    return timed(ctx, BOAC_K_BACK, bytes_back(z, a.C, mode), st,
+                 [&] { return launch_back(mode, dg, p.back, a, st); });
+}
+
+static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, const float *meas) {
+    FwdArgs a{};
+    a.att = att;
+    a.img = img;
+    a.meas = meas;
+    a.att_cs = z.V;
+    a.img_cs = z.I;
+    a.sino_cs = z.Y;
+    a.img_comps = 1;
+    return a;
+}
+static BackArgs back_args(const Sizes &z, const float *att, const float *zz, float *out, int C) {
+    BackArgs a{};
+    a.att = att;
+    a.z = zz;
+    a.out = out;
+    a.att_cs = z.V;
+    a.sino_cs = z.Y;
+    a.img_cs = z.I;
+    a.C = C;
+    return a;
+}
+
+// Maximum candidates whose attenuation tensors are resident at once (device scratch bound).
+static int cand_chunk(const Sizes &z, int C, int tensors) {
+    const double budget = 48.0 * (1ull << 30);  // of 288 GB HBM
+    const double per = 4.0 * (double)z.V * tensors + 64.0 * (double)z.I;
+    int m = (int)std::max(1.0, std::floor(budget / per));
+    return std::min(m, C);
+}
+
+// Forward evaluation of C candidates of one slice (scratch suffix distinguishes concurrent users).
+static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
+                                float delta_r, int K, float *obj, float *img_out, uint32_t *status, hipStream_t st) {
+    const Sizes z = sizes_of(g);
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, g, &dg));
+    const int Cc = cand_chunk(z, C, 1);
+    const Plan p = make_plan(ctx, g, Cc);
+    float *mu, *att, *s, *F0, *F1, *r;
+    float2 *partial, *lg;
+    uint32_t *flag, *st_int;
+    BOAC_TRY(ensure_t(ctx, "mu", (size_t)Cc * z.I, &mu));
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.V, &att));
+    BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * z.I, &s));
+    BOAC_TRY(ensure_t(ctx, "F0", (size_t)Cc * z.I, &F0));
+    BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &F1));
+    BOAC_TRY(ensure_t(ctx, "r", (size_t)Cc * z.Y, &r));
+    BOAC_TRY(ensure_t(ctx, "partial", (size_t)Cc * p.ray1.chunks, &partial));
+    BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
+    BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
+    BOAC_TRY(ensure_t(ctx, "status_int", (size_t)C, &st_int));
+    uint32_t *stat = status ? status : st_int;
+
+    HIP_TRY(launch_fill_u32(flag, 4, 0u, st));
+    HIP_TRY(launch_fill_u32(stat, (size_t)C, 0u, st));
+    BOAC_TRY(timed(ctx, BOAC_K_REDUCE, 4.0 * z.Y, st,
+                   [&] { return launch_lgamma_sum(meas, (int)z.Y, lg, flag, st); }));
+
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int n = std::min(Cc, C - c0);
+        const float *cd = cand + (size_t)c0 * 8;
+        BOAC_TRY(timed(ctx, BOAC_K_RASTER, 4.0 * n * (8 + z.I), st,
+                       [&] { return launch_raster(dg, cd, n, delta_r, mu, z.I, stat + c0, st); }));
+        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+        {
+            BackArgs b = back_args(z, att, nullptr, s, n);
+            BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, b, st));
+        }
+        HIP_TRY(launch_fill(F0, (size_t)n * z.I, 1.f, st));
+        float *Fc = F0, *Fn = F1;
+        for (int it = 0; it < K; ++it) {
+            FwdArgs a = fwd_args(z, att, Fc, meas);
+            a.r_out = r;
+            BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
+            BackArgs b = back_args(z, att, r, Fn, n);
+            b.F = Fc;
+            b.s = s;
+            BOAC_TRY(run_back(ctx, BACK_MLEM, dg, p, z, b, st));
+            std::swap(Fc, Fn);
+        }
+        FwdArgs a = fwd_args(z, att, Fc, meas);
+        a.partial = partial;
+        a.status = stat + c0;
+        BOAC_TRY(run_fwd(ctx, FWD_NLL, dg, p, z, a, n, st));
+        BOAC_TRY(timed(ctx, BOAC_K_REDUCE, 8.0 * n * p.ray1.chunks, st, [&] {
+            return launch_nll_finish(partial, p.ray1.chunks, n, lg, flag, obj + c0, stat + c0, st);
+        }));
+        if (img_out) HIP_TRY(launch_copy(Fc, img_out + (size_t)c0 * z.I, (size_t)n * z.I, st));
+    }
+    return BOAC_OK;
+}
+
+// Objective and gradient of C candidates of one slice.
+static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
+                             float delta_r, int K, int ck, float *obj, float *grad, uint32_t *status, hipStream_t st) {
+    const Sizes z = sizes_of(g);
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, g, &dg));
+    if (ck < 1) ck = 1;
+    if (ck > std::max(K, 1)) ck = std::max(K, 1);
+    const int nck = (K + ck - 1) / ck;  // stored records 0, ck, 2ck, ... < K
+    const int Cc = cand_chunk(z, C, 2);
+    const Plan p = make_plan(ctx, g, Cc);
+    const size_t I = z.I, Y = z.Y;
+    float *mu, *att, *attbar, *s, *sbar, *fbar, *fdir, *mubar, *gtmp, *yK, *ybar, *Ftmp, *Fwork;
+    float2 *bbarF, *partial, *lg;
+    uint32_t *flag, *st_int;
+    // records: F, y, r, Q per record; ckpt slots nck, segment slots ck
+    float *recF, *recY, *recR, *recQ, *segF, *segY, *segR, *segQ;
+    BOAC_TRY(ensure_t(ctx, "mu", (size_t)Cc * I, &mu));
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.V, &att));
+    BOAC_TRY(ensure_t(ctx, "attbar", (size_t)Cc * z.V, &attbar));
+    BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * I, &s));
+    BOAC_TRY(ensure_t(ctx, "sbar", (size_t)Cc * I, &sbar));
+    BOAC_TRY(ensure_t(ctx, "fbar", (size_t)Cc * I, &fbar));
+    BOAC_TRY(ensure_t(ctx, "fdir", (size_t)Cc * I, &fdir));
+    BOAC_TRY(ensure_t(ctx, "mubar", (size_t)Cc * I, &mubar));
+    BOAC_TRY(ensure_t(ctx, "gtmp", (size_t)Cc * 8, &gtmp));
+    BOAC_TRY(ensure_t(ctx, "yK", (size_t)Cc * Y, &yK));
+    BOAC_TRY(ensure_t(ctx, "ybar", (size_t)Cc * Y, &ybar));
+    BOAC_TRY(ensure_t(ctx, "Ftmp", (size_t)Cc * I, &Ftmp));
+    BOAC_TRY(ensure_t(ctx, "Fwork", (size_t)2 * Cc * I, &Fwork));
+    BOAC_TRY(ensure_t(ctx, "bbarF", (size_t)Cc * I, &bbarF));
+    BOAC_TRY(ensure_t(ctx, "partial", (size_t)Cc * p.ray1.chunks, &partial));
+    BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
+    BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
+    BOAC_TRY(ensure_t(ctx, "status_int", (size_t)C, &st_int));
+    BOAC_TRY(ensure_t(ctx, "recF", (size_t)std::max(nck, 1) * Cc * I, &recF));
+    BOAC_TRY(ensure_t(ctx, "recY", (size_t)std::max(nck, 1) * Cc * Y, &recY));
+    BOAC_TRY(ensure_t(ctx, "recR", (size_t)std::max(nck, 1) * Cc * Y, &recR));
+    BOAC_TRY(ensure_t(ctx, "recQ", (size_t)std::max(nck, 1) * Cc * I, &recQ));
+    BOAC_TRY(ensure_t(ctx, "segF", (size_t)ck * Cc * I, &segF));
+    BOAC_TRY(ensure_t(ctx, "segY", (size_t)ck * Cc * Y, &segY));
+    BOAC_TRY(ensure_t(ctx, "segR", (size_t)ck * Cc * Y, &segR));
+    BOAC_TRY(ensure_t(ctx, "segQ", (size_t)ck * Cc * I, &segQ));
+    uint32_t *stat = status ? status : st_int;
+
+    HIP_TRY(launch_fill_u32(flag, 4, 0u, st));
+    HIP_TRY(launch_fill_u32(stat, (size_t)C, 0u, st));
+    BOAC_TRY(timed(ctx, BOAC_K_REDUCE, 4.0 * Y, st, [&] { return launch_lgamma_sum(meas, (int)Y, lg, flag, st); }));
+
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int n = std::min(Cc, C - c0);
+        const float *cd = cand + (size_t)c0 * 8;
+        const size_t nI = (size_t)n * I, nY = (size_t)n * Y;
+        auto rec = [&](float *base, int slot, size_t per) { return base + (size_t)slot * Cc * per; };
+
+        BOAC_TRY(timed(ctx, BOAC_K_RASTER, 4.0 * n * (8 + I), st,
+                       [&] { return launch_raster(dg, cd, n, delta_r, mu, I, stat + c0, st); }));
+        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+        {
+            BackArgs b = back_args(z, att, nullptr, s, n);
+            BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, b, st));
+        }
+        // one MLEM iteration from record (F, y, r, Q) slots: fills y, r, Q and writes F^{n+1} to Fnext
+        auto iterate = [&](const float *F, float *y, float *r, float *Q, float *Fnext) -> boac_status {
+            FwdArgs a = fwd_args(z, att, F, meas);
+            a.r_out = r;
+            a.y_out = y;
+            BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
+            BackArgs b = back_args(z, att, r, Fnext, n);
+            b.F = F;
+            b.s = s;
+            b.q_out = Q;
+            return run_back(ctx, BACK_MLEM, dg, p, z, b, st);
+        };
+
+        // ---- forward sweep, storing records at checkpoints
+        float *Fcur = rec(recF, 0, I);
+        HIP_TRY(launch_fill(Fcur, nI, 1.f, st));
+        float *work[2] = {Fwork, Fwork + (size_t)Cc * I};
+        int wsel = 0;
+        for (int it = 0; it < K; ++it) {
+            const bool is_ck = (it % ck) == 0;
+            float *y = is_ck ? rec(recY, it / ck, Y) : segY;
+            float *r = is_ck ? rec(recR, it / ck, Y) : segR;
+            float *Q = is_ck ? rec(recQ, it / ck, I) : segQ;
+            float *Fnext;
+            if ((it + 1) < K && ((it + 1) % ck) == 0) {
+                Fnext = rec(recF, (it + 1) / ck, I);
+            } else {
+                Fnext = work[wsel];
+                wsel ^= 1;
+            }
+            BOAC_TRY(iterate(Fcur, y, r, Q, Fnext));
+            Fcur = Fnext;
+        }
+        // ---- objective at F^K (y^K kept for the reverse sweep)
+        {
+            FwdArgs a = fwd_args(z, att, Fcur, meas);
+            a.partial = partial;
+            a.status = stat + c0;
+            a.y_out = yK;
+            BOAC_TRY(run_fwd(ctx, FWD_NLL, dg, p, z, a, n, st));
+            BOAC_TRY(timed(ctx, BOAC_K_REDUCE, 8.0 * n * p.ray1.chunks, st, [&] {
+                return launch_nll_finish(partial, p.ray1.chunks, n, lg, flag, obj + c0, stat + c0, st);
+            }));
+        }
+        // ---- reverse sweep
+        // d/dy (y - S ln y) at y^K: ybar^K = 1 - S / y^K where y^K > 0 (1 where S = 0)
+        HIP_TRY(launch_fill(sbar, nI, 0.f, st));
+        BOAC_TRY(timed(ctx, BOAC_K_OTHER, 12.0 * nY, st,
+                       [&] { return launch_ybar_final(meas, yK, ybar, n, (int)Y, Y, st); }));
+        {
+            AttbarArgs aa{};
+            aa.attbar = attbar;
+            aa.img2 = Fcur;
+            aa.ybar = ybar;
+            aa.att_cs = z.V;
+            aa.img_cs = I;
+            aa.sino_cs = Y;
+            aa.accumulate = 0;
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (z.V + I + Y), st,
+                           [&] { return launch_attbar(1, dg, p.ray1, p.bands1, aa, n, st); }));
+        }
+        if (K > 0) {
+            BackArgs b = back_args(z, att, ybar, fbar, n);
+            BOAC_TRY(run_back(ctx, BACK_PLAIN, dg, p, z, b, st));
+        }
+        const int nseg = nck;
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int n0 = sg * ck, n1 = std::min(n0 + ck, K);
+            // segment slot j holds record n0 + j
+            std::vector<float *> sF(ck), sY(ck), sR(ck), sQ(ck);
+            sF[0] = rec(recF, sg, I);
+            sY[0] = rec(recY, sg, Y);
+            sR[0] = rec(recR, sg, Y);
+            sQ[0] = rec(recQ, sg, I);
+            for (int j = 1; j < n1 - n0; ++j) {
+                sF[j] = rec(segF, j, I);
+                sY[j] = rec(segY, j, Y);
+                sR[j] = rec(segR, j, Y);
+                sQ[j] = rec(segQ, j, I);
+                // F^{n0+j} = F^{n0+j-1} * Q^{n0+j-1}, bit-identical to the forward sweep's update
+                HIP_TRY(launch_mul_copy(sF[j - 1], sQ[j - 1], sF[j], nI, st));
+                BOAC_TRY(iterate(sF[j], sY[j], sR[j], sQ[j], Ftmp));
+            }
+            for (int j = n1 - n0 - 1; j >= 0; --j) {
+                const int it = n0 + j;
+                AdjElemArgs e{};
+                e.fbar = fbar;
+                e.F = sF[j];
+                e.Q = sQ[j];
+                e.s = s;
+                e.sbar = sbar;
+                e.bbarF = bbarF;
+                e.fbar_direct = fdir;
+                e.img_cs = I;
+                e.npix = (int)I;
+                e.C = n;
+                BOAC_TRY(timed(ctx, BOAC_K_OTHER, 4.0 * n * 8.0 * I, st, [&] { return launch_adj_elem(e, st); }));
+                // ybar^n = -(A bbar^n) r^n / y^n
+                FwdArgs a = fwd_args(z, att, (const float *)bbarF, meas);
+                a.img_comps = 2;
+                a.img_cs = 2 * I;
+                a.y_in = sY[j];
+                a.r_in = sR[j];
+                a.r_out = ybar;
+                BOAC_TRY(run_fwd(ctx, FWD_YBAR, dg, p, z, a, n, st));
+                AttbarArgs aa{};
+                aa.attbar = attbar;
+                aa.img2 = (const float *)bbarF;
+                aa.r = sR[j];
+                aa.ybar = ybar;
+                aa.att_cs = z.V;
+                aa.img_cs = 2 * I;
+                aa.sino_cs = Y;
+                aa.accumulate = 1;
+                BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (2.0 * z.V + 2 * I + 2 * Y), st,
+                               [&] { return launch_attbar(2, dg, p.ray2, p.bands2, aa, n, st); }));
+                if (it > 0) {
+                    BackArgs b = back_args(z, att, ybar, fbar, n);
+                    b.aux = fdir;
+                    BOAC_TRY(run_back(ctx, BACK_ADJ, dg, p, z, b, st));
+                }
+            }
+        }
+        // ---- tail: sensitivity adjoint, exp and scan transposes, mu_bar, raster adjoint
+        {
+            TailArgs ta{att, attbar, sbar, z.V, I};
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (3.0 * z.V + I), st,
+                           [&] { return launch_tail(dg, p.ray1, p.bands1, ta, n, st); }));
+            BackArgs b = back_args(z, att, attbar, mubar, n);
+            BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * I, st,
+                           [&] { return launch_raster_adj(dg, cd, n, delta_r, mubar, I, gtmp, st); }));
+            BOAC_TRY(timed(ctx, BOAC_K_OTHER, 64.0 * n, st,
+                           [&] { return launch_grad_finish(gtmp, n, grad + (size_t)c0 * 8, stat + c0, st); }));
+        }
+    }
+    return BOAC_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+int32_t boac_version(void) { return (1 << 16) | 0; }
+
+const char *boac_last_error(void) { return g_last_error.c_str(); }
+
+static void load_tune(boac_ctx *ctx, const char *path) {
+    if (!path || !*path) path = std::getenv("BOAC_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
+    std::fclose(f);
+    // flat JSON object {"key": [ints], ...}
+    size_t i = 0;
+    while (true) {
+        size_t q0 = s.find('"', i);
+        if (q0 == std::string::npos) break;
+        size_t q1 = s.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        std::string key = s.substr(q0 + 1, q1 - q0 - 1);
+        size_t b0 = s.find('[', q1);
+        size_t b1 = s.find(']', b0 == std::string::npos ? q1 : b0);
+        if (b0 == std::string::npos || b1 == std::string::npos) break;
+        std::vector<int> vals;
+        const char *p = s.c_str() + b0 + 1;
+        const char *end = s.c_str() + b1;
+        while (p < end) {
+            char *e = nullptr;
+            long v = std::strtol(p, &e, 10);
+            if (e == p) {
+                ++p;
+                continue;
+            }
+            vals.push_back((int)v);
+            p = e;
+        }
+        ctx->tune[key] = vals;
+        i = b1 + 1;
+    }
+}
+
+boac_status boac_ctx_create(int32_t device, const char *tune_cache_path, boac_ctx **out) {
+    if (!out) return fail(BOAC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(BOAC_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (device < 0 || device >= count) return fail(BOAC_EINVAL, "device %d outside [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BOAC_ENOTSUP, "device %d is %s; libboac is built for gfx950", device, prop.gcnArchName);
+    auto ctx = std::make_unique<boac_ctx>();
+    ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    load_tune(ctx.get(), tune_cache_path);
+    *out = ctx.release();
+    return BOAC_OK;
+}
+
+void boac_ctx_destroy(boac_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto &kv : ctx->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto &kv : ctx->trig) (void)hipFree(kv.second);
+    for (auto &p : ctx->pending) {
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+#define CTX_CHECK()                                                      \
+    do {                                                                 \
+        if (!ctx) return fail(BOAC_EINVAL, "context is NULL");           \
+        HIP_TRY(hipSetDevice(ctx->device));                              \
+    } while (0)
+
+boac_status boac_rasterize_mu(boac_ctx *ctx, const boac_geom *geom, const boac_cand *d_cand, int32_t C,
+                              float delta_r_cm, float *d_mu, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_cand, "d_cand"));
+    BOAC_TRY(check_ptr(d_mu, "d_mu"));
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    CTX_CHECK();
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, *geom, &dg));
+    hipStream_t st = (hipStream_t)stream;
+    const Sizes z = sizes_of(*geom);
+    return timed(ctx, BOAC_K_RASTER, 4.0 * C * (8 + z.I), st, [&] {
+        return launch_raster(dg, (const float *)d_cand, C, delta_r_cm, d_mu, z.I, nullptr, st);
+    });
+}
+
+// att for a chunk of candidates from caller mu maps
+static boac_status build_att(boac_ctx *ctx, const boac_geom &g, const DevGeom &dg, const Plan &p, const float *mu,
+                             int n, float **att_out, hipStream_t st) {
+    const Sizes z = sizes_of(g);
+    float *att;
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)n * z.V, &att));
+    BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+    *att_out = att;
+    return BOAC_OK;
+}
+
+boac_status boac_project(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_img, int32_t C,
+                         float *d_sino, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_mu, "d_mu"));
+    BOAC_TRY(check_ptr(d_img, "d_img"));
+    BOAC_TRY(check_ptr(d_sino, "d_sino"));
+    CTX_CHECK();
+    hipStream_t st = (hipStream_t)stream;
+    const Sizes z = sizes_of(*geom);
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, *geom, &dg));
+    const int Cc = cand_chunk(z, C, 1);
+    const Plan p = make_plan(ctx, *geom, Cc);
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int n = std::min(Cc, C - c0);
+        float *att;
+        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
+        FwdArgs a = fwd_args(z, att, d_img + (size_t)c0 * z.I, nullptr);
+        a.y_out = d_sino + (size_t)c0 * z.Y;
+        BOAC_TRY(run_fwd(ctx, FWD_PROJ, dg, p, z, a, n, st));
+    }
+    return BOAC_OK;
+}
+
+boac_status boac_backproject(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_sino, int32_t C,
+                             float *d_img, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_mu, "d_mu"));
+    BOAC_TRY(check_ptr(d_sino, "d_sino"));
+    BOAC_TRY(check_ptr(d_img, "d_img"));
+    CTX_CHECK();
+    hipStream_t st = (hipStream_t)stream;
+    const Sizes z = sizes_of(*geom);
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, *geom, &dg));
+    const int Cc = cand_chunk(z, C, 1);
+    const Plan p = make_plan(ctx, *geom, Cc);
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int n = std::min(Cc, C - c0);
+        float *att;
+        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
+        BackArgs b = back_args(z, att, d_sino + (size_t)c0 * z.Y, d_img + (size_t)c0 * z.I, n);
+        BOAC_TRY(run_back(ctx, BACK_PLAIN, dg, p, z, b, st));
+    }
+    return BOAC_OK;
+}
+
+boac_status boac_mlem(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, const float *d_meas, int32_t C,
+                      int32_t n_iter, float *d_img_inout, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_mu, "d_mu"));
+    BOAC_TRY(check_ptr(d_meas, "d_meas"));
+    BOAC_TRY(check_ptr(d_img_inout, "d_img_inout"));
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    CTX_CHECK();
+    hipStream_t st = (hipStream_t)stream;
+    const Sizes z = sizes_of(*geom);
+    DevGeom dg;
+    BOAC_TRY(dev_geom(ctx, *geom, &dg));
+    const int Cc = cand_chunk(z, C, 1);
+    const Plan p = make_plan(ctx, *geom, Cc);
+    float *s, *Fs, *r;
+    BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * z.I, &s));
+    BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &Fs));
+    BOAC_TRY(ensure_t(ctx, "r", (size_t)Cc * z.Y, &r));
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int n = std::min(Cc, C - c0);
+        float *att;
+        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
+        BackArgs sb = back_args(z, att, nullptr, s, n);
+        BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, sb, st));
+        float *Fio = d_img_inout + (size_t)c0 * z.I;
+        float *Fc = Fio, *Fn = Fs;
+        for (int it = 0; it < n_iter; ++it) {
+            FwdArgs a = fwd_args(z, att, Fc, d_meas);
+            a.r_out = r;
+            BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
+            BackArgs b = back_args(z, att, r, Fn, n);
+            b.F = Fc;
+            b.s = s;
+            BOAC_TRY(run_back(ctx, BACK_MLEM, dg, p, z, b, st));
+            std::swap(Fc, Fn);
+        }
+        if (Fc != Fio) HIP_TRY(launch_copy(Fc, Fio, (size_t)n * z.I, st));
+    }
+    return BOAC_OK;
+}
+
+boac_status boac_objective(boac_ctx *ctx, const boac_geom *geom, const float *d_meas, const boac_cand *d_cand,
+                           int32_t C, float delta_r_cm, int32_t n_iter, float *d_obj, float *d_img_out,
+                           uint32_t *d_status, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_meas, "d_meas"));
+    BOAC_TRY(check_ptr(d_cand, "d_cand"));
+    BOAC_TRY(check_ptr(d_obj, "d_obj"));
+    BOAC_TRY(check_ptr(d_img_out, "d_img_out", true));
+    BOAC_TRY(check_ptr(d_status, "d_status", true));
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    CTX_CHECK();
+    return eval_forward(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, d_obj, d_img_out, d_status,
+                        (hipStream_t)stream);
+}
+
+boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const float *d_meas, const boac_cand *d_cand,
+                                int32_t C, float delta_r_cm, int32_t n_iter, int32_t ckpt_every, float *d_obj,
+                                float *d_grad, uint32_t *d_status, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_meas, "d_meas"));
+    BOAC_TRY(check_ptr(d_cand, "d_cand"));
+    BOAC_TRY(check_ptr(d_obj, "d_obj"));
+    BOAC_TRY(check_ptr(d_grad, "d_grad"));
+    BOAC_TRY(check_ptr(d_status, "d_status", true));
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    if (ckpt_every < 1) return fail(BOAC_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    CTX_CHECK();
+    return eval_grad(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, ckpt_every, d_obj, d_grad,
+                     d_status, (hipStream_t)stream);
+}
+
+static boac_status batch_body(boac_ctx *ctx, const boac_slice *h, int32_t ns, float delta_r, int32_t K, int32_t ck,
+                              hipStream_t st) {
+    for (int i = 0; i < ns; ++i) {
+        const boac_slice &s = h[i];
+        if (s.d_grad)
+            BOAC_TRY(eval_grad(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, ck, s.d_obj, s.d_grad,
+                               s.d_status, st));
+        else
+            BOAC_TRY(eval_forward(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, s.d_obj, nullptr,
+                                  s.d_status, st));
+    }
+    return BOAC_OK;
+}
+
+boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
+                                int32_t n_iter, int32_t ckpt_every, void *stream) {
+    if (!h_slices) return fail(BOAC_EINVAL, "h_slices is NULL");
+    if (n_slices < 1 || n_slices > 65536) return fail(BOAC_EINVAL, "n_slices = %d outside [1, 65536]", n_slices);
+    for (int i = 0; i < n_slices; ++i) {
+        const boac_slice &s = h_slices[i];
+        boac_status r = check_geom(&s.geom);
+        if (r != BOAC_OK) return fail(r, "slice %d: %s", i, g_last_error.c_str());
+        BOAC_TRY(check_count(s.C));
+        BOAC_TRY(check_ptr(s.d_meas, "slice d_meas"));
+        BOAC_TRY(check_ptr(s.d_cand, "slice d_cand"));
+        BOAC_TRY(check_ptr(s.d_obj, "slice d_obj"));
+        BOAC_TRY(check_ptr(s.d_grad, "slice d_grad", true));
+        BOAC_TRY(check_ptr(s.d_status, "slice d_status", true));
+    }
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    if (ckpt_every < 1) return fail(BOAC_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    CTX_CHECK();
+    hipStream_t st = (hipStream_t)stream;
+
+    // graph key: every pointer and shape of the batch
+    std::vector<uint64_t> key;
+    key.push_back((uint64_t)n_slices);
+    key.push_back((uint64_t)n_iter);
+    key.push_back((uint64_t)ckpt_every);
+    uint32_t dr;
+    std::memcpy(&dr, &delta_r_cm, 4);
+    key.push_back(dr);
+    key.push_back((uint64_t)(uintptr_t)st);
+    for (int i = 0; i < n_slices; ++i) {
+        const boac_slice &s = h_slices[i];
+        uint32_t px;
+        std::memcpy(&px, &s.geom.pixel_cm, 4);
+        key.insert(key.end(), {(uint64_t)s.geom.n, (uint64_t)s.geom.n_angles, (uint64_t)s.geom.n_bins,
+                               (uint64_t)s.geom.n_samples, px, (uint64_t)s.C, (uint64_t)(uintptr_t)s.d_meas,
+                               (uint64_t)(uintptr_t)s.d_cand, (uint64_t)(uintptr_t)s.d_obj,
+                               (uint64_t)(uintptr_t)s.d_grad, (uint64_t)(uintptr_t)s.d_status});
+    }
+    const bool use_graph = (st != nullptr) && !ctx->profiling && std::getenv("BOAC_NO_GRAPH") == nullptr;
+    if (!use_graph) return batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st);
+
+    for (auto &g : ctx->graphs) {
+        if (g.key == key && g.exec && !ctx->scratch_changed) {
+            HIP_TRY(hipGraphLaunch(g.exec, st));
+            return BOAC_OK;
+        }
+    }
+    // first call for this shape: run eagerly (sizes scratch, uploads tables), then capture
+    ctx->scratch_changed = false;
+    BOAC_TRY(batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st));
+    if (ctx->scratch_changed) {
+        // scratch moved: earlier graphs hold stale pointers
+        for (auto &g : ctx->graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        ctx->graphs.clear();
+        ctx->scratch_changed = false;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    boac_status bs = batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st);
+    ctx->capturing = false;
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (bs != BOAC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return bs;
+    }
+    if (ce != hipSuccess) return fail(BOAC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+    GraphEntry ge;
+    ge.key = key;
+    hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(BOAC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    if (ctx->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(ge);
+    // the eager run above already produced this call's results
+    return BOAC_OK;
+}
+
+boac_status boac_ctx_set_profiling(boac_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(BOAC_EINVAL, "context is NULL");
+    ctx->profiling = enable != 0;
+    return BOAC_OK;
+}
+
+boac_status boac_ctx_kernel_stats(boac_ctx *ctx, int32_t kind, int64_t *count, double *total_ms,
+                                  double *total_bytes) {
+    if (!ctx) return fail(BOAC_EINVAL, "context is NULL");
+    if (kind < 0 || kind >= BOAC_K_COUNT) return fail(BOAC_EINVAL, "kernel kind %d outside [0, %d)", kind, BOAC_K_COUNT);
+    HIP_TRY(hipSetDevice(ctx->device));
+    BOAC_TRY(drain_timings(ctx));
+    if (count) *count = ctx->stat_count[kind];
+    if (total_ms) *total_ms = ctx->stat_ms[kind];
+    if (total_bytes) *total_bytes = ctx->stat_bytes[kind];
+    return BOAC_OK;
+}
+
+boac_status boac_ctx_reset_stats(boac_ctx *ctx) {
+    if (!ctx) return fail(BOAC_EINVAL, "context is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    BOAC_TRY(drain_timings(ctx));
+    for (int k = 0; k < BOAC_K_COUNT; ++k) {
+        ctx->stat_count[k] = 0;
+        ctx->stat_ms[k] = 0;
+        ctx->stat_bytes[k] = 0;
+    }
+    return BOAC_OK;
+}
+
+}  // extern "C"

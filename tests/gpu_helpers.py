@@ -1,0 +1,65 @@
+"""Shared helpers of the GPU parity tests: the library context, seeded inputs, and error reporting."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+TOL = 1e-4        # relative L2 on maps, sinograms, images, objectives
+TOL_GRAD = 1e-3   # relative L2 on gradients
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref.ravel())
+    num = np.linalg.norm((got - ref).ravel())
+    return num / den if den > 0 else num
+
+
+def report(name, got, ref, tol):
+    e = rel_l2(got, ref)
+    print(f"[parity] {name}: rel_l2={e:.3e} (tol {tol:.0e}) max_abs={np.abs(np.asarray(got, np.float64) - ref).max():.3e}",
+          flush=True)
+    assert e <= tol, f"{name}: relative L2 error {e:.3e} > {tol:.0e}"
+    return e
+
+
+def f32(x):
+    """Round to float32 and back, so the oracle sees exactly the GPU's inputs."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def geom_pair(n, na, nb=None, nt=None, pixel=None):
+    from paper_2109_11920_amd.api import Geometry
+    nb = nb or n
+    nt = nt or n
+    pixel = float(np.float32(pixel if pixel is not None else 25.6 / n))
+    return Geometry(n, na, nb, nt, pixel), oracle.Geometry(n, na, nb, nt, pixel)
+
+
+def make_slice(og, seed=0, counts=None):
+    """Seeded noisy sinogram from the oracle (true head, hot disks)."""
+    from oracle.phantom import activity_phantom, place_disks, simulate
+    rng_ph, rng_noise, _ = synth.streams(seed)
+    theta = synth.true_candidate()
+    disks = place_disks(theta[:6], synth.disk_proposals(rng_ph), 3, 0.8, 1.5)
+    f = activity_phantom(og, theta[:6], synth.DELTA_R, disks, 1.0, 4.0)
+    counts = counts or 40.0 * og.n_angles * og.n_bins * 0.6
+    S, _ = simulate(og, theta, synth.DELTA_R, f, counts, rng_noise)
+    return S.astype(np.float64), f
+
+
+def cands(seed, C, true_first=True):
+    rng = synth.candidate_stream(seed)
+    c = synth.draw_candidates(rng, C)
+    if true_first:
+        c[0] = synth.true_candidate()
+    return f32(c)

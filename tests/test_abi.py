@@ -1,0 +1,87 @@
+"""The C ABI library loads, exports every function declared in include/boac.h, and validates its
+arguments before touching the device (these tests make no compute call and run without a GPU)."""
+import ctypes
+
+import pytest
+
+from paper_2109_11920_amd import _lib
+from paper_2109_11920_amd._lib import BoacGeom, BoacSlice
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_header_declares_the_documented_entry_points():
+    names = _lib.header_functions()
+    for required in ("boac_rasterize_mu", "boac_project", "boac_backproject", "boac_mlem", "boac_objective",
+                     "boac_objective_grad", "boac_evaluate_batch", "boac_ctx_create", "boac_ctx_destroy",
+                     "boac_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_header_symbol(lib):
+    for name in _lib.header_functions():
+        assert hasattr(lib, name), name
+    assert set(_lib.header_functions()) == set(_lib._SIGNATURES)
+
+
+def test_version(lib):
+    v = lib.boac_version()
+    assert v >> 16 == 1
+
+
+def _good():
+    return BoacGeom(64, 64, 64, 64, 0.4)
+
+
+ALIGNED = ctypes.c_void_p(1 << 20)       # never dereferenced: validation fails before any launch
+MISALIGNED = ctypes.c_void_p((1 << 20) + 4)
+
+
+@pytest.mark.parametrize("field,value", [("n", 1), ("n", 2000), ("n_angles", 1), ("n_bins", 0),
+                                         ("n_samples", 5000), ("pixel_cm", 0.0), ("pixel_cm", float("nan")),
+                                         ("n_bins", 400)])
+def test_bad_geometry_is_rejected_before_the_device(lib, field, value):
+    g = _good()
+    setattr(g, field, value)
+    st = lib.boac_project(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, ALIGNED, None)
+    assert st == 2, lib.boac_last_error()
+    assert lib.boac_last_error()
+
+
+def test_bad_counts_and_pointers(lib):
+    g = _good()
+    assert lib.boac_project(None, ctypes.byref(g), ALIGNED, ALIGNED, 0, ALIGNED, None) == 1
+    assert lib.boac_project(None, ctypes.byref(g), None, ALIGNED, 1, ALIGNED, None) == 1
+    assert b"NULL" in lib.boac_last_error()
+    assert lib.boac_project(None, ctypes.byref(g), MISALIGNED, ALIGNED, 1, ALIGNED, None) == 1
+    assert b"aligned" in lib.boac_last_error()
+    assert lib.boac_mlem(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, -1, ALIGNED, None) == 1
+    assert lib.boac_objective(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.0, 5, ALIGNED, None, None, None) == 1
+    assert lib.boac_objective_grad(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.8, 5, 0, ALIGNED, ALIGNED,
+                                   None, None) == 1
+    assert lib.boac_rasterize_mu(None, None, ALIGNED, 1, 0.8, ALIGNED, None) == 1
+
+
+def test_null_context_after_valid_arguments(lib):
+    g = _good()
+    st = lib.boac_project(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, ALIGNED, None)
+    assert st == 1 and b"context" in lib.boac_last_error()
+
+
+def test_batch_validation(lib):
+    arr = (BoacSlice * 2)()
+    arr[0] = BoacSlice(_good(), ALIGNED, ALIGNED, 4, ALIGNED, None, None)
+    arr[1] = BoacSlice(BoacGeom(64, 64, 64, 64, -1.0), ALIGNED, ALIGNED, 4, ALIGNED, None, None)
+    assert lib.boac_evaluate_batch(None, arr, 2, 0.8, 10, 5, None) == 2
+    assert b"slice 1" in lib.boac_last_error()
+    assert lib.boac_evaluate_batch(None, arr, 0, 0.8, 10, 5, None) == 1
+    assert lib.boac_evaluate_batch(None, None, 1, 0.8, 10, 5, None) == 1
+
+
+def test_stats_need_a_context(lib):
+    assert lib.boac_ctx_set_profiling(None, 1) == 1
+    assert lib.boac_ctx_reset_stats(None) == 1
+    lib.boac_ctx_destroy(None)  # no-op

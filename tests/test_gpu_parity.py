@@ -1,0 +1,320 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on the same seeded inputs.
+
+Sizes span several pixel tiles and ray chunks with ragged tails; the banded LDS path (large n) and
+non-square detector/ray counts are covered. Gates: relative L2 <= 1e-4 on maps, sinograms, images and
+objectives, <= 1e-3 on gradients; every error is printed."""
+import numpy as np
+import pytest
+
+from gpu_helpers import TOL, TOL_GRAD, cands, f32, geom_pair, make_slice, oracle, rel_l2, report
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DR = 0.8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2109_11920_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(x, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype or torch.float32, device="cuda")
+
+
+GEOMS = [
+    # (n, n_angles, n_bins, n_samples): ragged tiles (40 = 32 + 8), ragged ray chunks, nb != n, nt != n
+    (40, 24, 40, 40),
+    (70, 30, 70, 70),
+    (48, 20, 62, 48),
+    (36, 16, 36, 50),
+]
+
+
+@pytest.mark.parametrize("shape", GEOMS)
+def test_rasterize(ctx, shape):
+    g, og = geom_pair(*shape)
+    th = cands(1, 5)
+    mu = ctx.rasterize_mu(g, dev(th), DR).cpu().numpy()
+    for c in range(5):
+        report(f"mu {shape} cand {c}", mu[c], oracle.rasterize_mu(og, th[c], DR), TOL)
+
+
+def test_rasterize_full_size(ctx):
+    g, og = geom_pair(128, 128, pixel=0.2)
+    th = cands(2, 4)
+    mu = ctx.rasterize_mu(g, dev(th), DR).cpu().numpy()
+    for c in range(4):
+        report(f"mu 128 cand {c}", mu[c], oracle.rasterize_mu(og, th[c], DR), TOL)
+
+
+def _mu_img(og, seed, C):
+    rng = np.random.default_rng(seed)
+    th = cands(seed, C)
+    mus = np.stack([oracle.rasterize_mu(og, th[c], DR) for c in range(C)])
+    imgs = rng.uniform(0.0, 2.0, (C, og.n, og.n))
+    return f32(mus), f32(imgs)
+
+
+@pytest.mark.parametrize("shape", GEOMS)
+def test_project(ctx, shape):
+    g, og = geom_pair(*shape)
+    mus, imgs = _mu_img(og, 3, 3)
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    for c in range(3):
+        ref = oracle.project(og, oracle.attenuation(og, mus[c]), imgs[c])
+        report(f"project {shape} cand {c}", y[c], ref, TOL)
+
+
+@pytest.mark.parametrize("shape", GEOMS)
+def test_backproject_and_adjoint_identity(ctx, shape):
+    g, og = geom_pair(*shape)
+    mus, imgs = _mu_img(og, 4, 3)
+    z = f32(np.random.default_rng(5).uniform(-1, 1, (3, og.n_angles, og.n_bins)))
+    x = ctx.backproject(g, dev(mus), dev(z)).cpu().numpy()
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    for c in range(3):
+        ref = oracle.backproject(og, oracle.attenuation(og, mus[c]), z[c])
+        report(f"backproject {shape} cand {c}", x[c], ref, TOL)
+        lhs = np.sum(y[c].astype(np.float64) * z[c])
+        rhs = np.sum(imgs[c] * x[c].astype(np.float64))
+        adj = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+        print(f"[parity] adjoint identity {shape} cand {c}: {adj:.3e}", flush=True)
+        assert adj < 2e-5
+
+
+def test_projector_exact_axis_angles(ctx):
+    # 4 angles: 0/90/180/270 deg, samples on pixel centres; the oracle's exact sums
+    g, og = geom_pair(32, 4, pixel=0.5)
+    mus, imgs = _mu_img(og, 6, 2)
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    for c in range(2):
+        report(f"axis angles cand {c}", y[c], oracle.project(og, oracle.attenuation(og, mus[c]), imgs[c]), 2e-6)
+
+
+def test_mu_zero_reduces_to_plain_radon(ctx):
+    g, og = geom_pair(40, 24)
+    _, imgs = _mu_img(og, 7, 2)
+    mus = np.zeros_like(imgs)
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    for c in range(2):
+        ref = oracle.project(og, np.ones((og.n_angles, og.n_bins, og.n_samples)), imgs[c])
+        report(f"mu=0 cand {c}", y[c], ref, TOL)
+
+
+@pytest.mark.parametrize("n", [200, 256])
+def test_banded_large_images(ctx, n):
+    # images larger than one LDS stage: the row-band path of every ray kernel
+    g, og = geom_pair(n, 12)
+    mus, imgs = _mu_img(og, 8, 2)
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    z = f32(np.random.default_rng(9).uniform(0, 1, (2, og.n_angles, og.n_bins)))
+    x = ctx.backproject(g, dev(mus), dev(z)).cpu().numpy()
+    for c in range(2):
+        att = oracle.attenuation(og, mus[c])
+        report(f"banded project n={n} cand {c}", y[c], oracle.project(og, att, imgs[c]), TOL)
+        report(f"banded backproject n={n} cand {c}", x[c], oracle.backproject(og, att, z[c]), TOL)
+
+
+@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
+def test_mlem(ctx, shape, K):
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=11)
+    mus, _ = _mu_img(og, 12, 2)
+    F = ctx.mlem(g, dev(mus), dev(S), K).cpu().numpy()
+    for c in range(2):
+        ref = oracle.mlem(og, oracle.attenuation(og, mus[c]), S, K)
+        report(f"mlem {shape} K={K} cand {c}", F[c], ref, TOL)
+
+
+def test_objective_smoke_config(ctx, slice64):
+    # 64 x 64, 0.4 cm, 64 angles, true head, 20 iterations
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = slice64["meas"].astype(np.float64)
+    th = f32(slice64["theta"][None, :])
+    J, img, st = ctx.objective(g, dev(S), dev(th), DR, 20, want_image=True)
+    Jr, Fr, _ = oracle.evaluate(og, S, th[0], DR, 20)
+    report("objective smoke J", J.cpu().numpy(), np.array([Jr]), TOL)
+    report("objective smoke F^K", img.cpu().numpy()[0], Fr, TOL)
+    assert int(st.cpu()[0]) == 0
+
+
+def test_objective_plain_config(ctx, slice128):
+    # 128 x 128, 0.2 cm, 128 angles, 5e5 counts, one candidate, 50 iterations
+    g, og = geom_pair(128, 128, pixel=0.2)
+    S = slice128["meas"].astype(np.float64)
+    th = f32(slice128["theta"][None, :])
+    J, img, st = ctx.objective(g, dev(S), dev(th), DR, 50, want_image=True)
+    Jr, Fr, _ = oracle.evaluate(og, S, th[0], DR, 50)
+    report("objective plain J", J.cpu().numpy(), np.array([Jr]), TOL)
+    report("objective plain F^K", img.cpu().numpy()[0], Fr, TOL)
+
+
+def test_objective_batch_matches_oracle_samples(ctx, slice128):
+    # the 256-candidate batch, 30 iterations, in the launch configuration of the bench; the oracle
+    # scores three sampled candidates one by one
+    g, og = geom_pair(128, 128, pixel=0.2)
+    S = slice128["meas"].astype(np.float64)
+    import synth
+    th = f32(synth.draw_candidates(synth.candidate_stream(0), 256))
+    J, _, st = ctx.objective(g, dev(S), dev(th), DR, 30)
+    J = J.cpu().numpy()
+    st = st.cpu().numpy()
+    assert np.all(np.isfinite(J))
+    assert np.all((st & 3) == 0)
+    for c in (0, 137, 255):
+        Jr = oracle.evaluate(og, S, th[c], DR, 30)[0]
+        report(f"batch256 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
+
+
+def test_count_preservation_on_gpu(ctx, slice128):
+    g, og = geom_pair(128, 128, pixel=0.2)
+    S = slice128["meas"].astype(np.float64)
+    th = cands(13, 4)
+    mu = ctx.rasterize_mu(g, dev(th), DR)
+    F = ctx.mlem(g, mu, dev(S), 7)
+    y = ctx.project(g, mu, F).cpu().numpy().astype(np.float64)
+    for c in range(4):
+        e = abs(y[c].sum() - S.sum()) / S.sum()
+        print(f"[parity] count preservation cand {c}: {e:.3e}", flush=True)
+        assert e < 1e-5
+
+
+def test_batched_equals_unbatched_and_deterministic(ctx, slice64):
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = dev(slice64["meas"].astype(np.float64))
+    th = cands(14, 9)
+    Jb, Fb, _ = ctx.objective(g, S, dev(th), DR, 6, want_image=True)
+    Jb2, Fb2, _ = ctx.objective(g, S, dev(th), DR, 6, want_image=True)
+    assert torch.equal(Jb, Jb2) and torch.equal(Fb, Fb2)
+    for c in (0, 4, 8):
+        J1, F1, _ = ctx.objective(g, S, dev(th[c:c + 1]), DR, 6, want_image=True)
+        assert torch.equal(J1[0], Jb[c]) and torch.equal(F1[0], Fb[c])
+
+
+def test_nac_candidate_and_status_bits(ctx, slice64):
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = slice64["meas"].astype(np.float64)
+    th = cands(15, 4)
+    th[1, 6:] = 0.0            # no attenuation correction (mu = 0)
+    th[2, 0] = 1.0             # head outline dips below zero somewhere
+    th[2, 2] = 3.0
+    th[3, 0] = np.nan          # non-finite candidate
+    J, _, st = ctx.objective(g, dev(S), dev(th), DR, 5)
+    J = J.cpu().numpy()
+    st = st.cpu().numpy()
+    Jr = oracle.evaluate(og, S, th[1], DR, 5)[0]
+    report("NAC J", J[1:2], np.array([Jr]), TOL)
+    assert st[2] & 4
+    assert st[3] & 2 and not np.isfinite(J[3])
+    Sneg = S.copy()
+    Sneg[0, 0] = -1.0
+    _, _, st2 = ctx.objective(g, dev(Sneg), dev(th[:1]), DR, 2)
+    assert int(st2.cpu()[0]) & 8
+
+
+def test_zero_measurement(ctx):
+    g, og = geom_pair(32, 16, pixel=0.8)
+    S = np.zeros((16, 32))
+    J, F, st = ctx.objective(g, dev(S), dev(cands(16, 2)), DR, 3, want_image=True)
+    assert np.all(J.cpu().numpy() == 0.0)
+    assert np.all(F.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 4), ((48, 20, 62, 48), 3), ((32, 16, 32, 32), 0)])
+def test_objective_grad_small(ctx, shape, K):
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=17)
+    th = cands(18, 3)
+    th[1] = f32(th[1] + np.array([0.3, 0.2, -0.2, 0.1, 0.1, -0.1, 0.01, -0.02]))
+    J, G, st = ctx.objective_grad(g, dev(S), dev(th), DR, K, 2)
+    J = J.cpu().numpy()
+    G = G.cpu().numpy()
+    for c in range(3):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, K)
+        report(f"grad {shape} K={K} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        print("   gpu   ", np.array2string(G[c], precision=5), "\n   oracle", np.array2string(Gr, precision=5))
+        report(f"grad {shape} K={K} cand {c} dJ", G[c], Gr, TOL_GRAD)
+
+
+def test_checkpoint_interval_does_not_change_results(ctx):
+    g, og = geom_pair(40, 24)
+    S, _ = make_slice(og, seed=19)
+    th = dev(cands(20, 3))
+    ref = None
+    for ck in (1, 2, 3, 7, 100):
+        J, G, _ = ctx.objective_grad(g, dev(S), th, DR, 7, ck)
+        if ref is None:
+            ref = (J.clone(), G.clone())
+        else:
+            assert torch.equal(J, ref[0]) and torch.equal(G, ref[1]), ck
+    Jf, _, _ = ctx.objective(g, dev(S), th, DR, 7)
+    assert torch.equal(Jf, ref[0])
+
+
+def test_objective_grad_adjoint_config_samples(ctx, slice128):
+    # 128 x 128, 128 angles, 64 candidates, 20 iterations, checkpoint every 5; two sampled candidates
+    # against the oracle's reverse-mode gradient
+    g, og = geom_pair(128, 128, pixel=0.2)
+    S = slice128["meas"].astype(np.float64)
+    import synth
+    th = f32(synth.draw_candidates(synth.candidate_stream(1), 64))
+    J, G, st = ctx.objective_grad(g, dev(S), dev(th), DR, 20, 5)
+    J = J.cpu().numpy()
+    G = G.cpu().numpy()
+    assert np.all(np.isfinite(G))
+    for c in (0, 41):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 20)
+        report(f"grad64 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
+        print("   gpu   ", np.array2string(G[c], precision=5), "\n   oracle", np.array2string(Gr, precision=5))
+        report(f"grad64 dJ cand {c}", G[c], Gr, TOL_GRAD)
+
+
+def test_autograd_function(ctx, slice64):
+    from paper_2109_11920_amd.api import objective
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = dev(slice64["meas"].astype(np.float64))
+    th = dev(cands(21, 3)).requires_grad_(True)
+    J = objective(ctx, g, S, th, DR, 4, 2)
+    w = torch.tensor([1.0, -2.0, 0.5], device="cuda")
+    (J * w).sum().backward()
+    _, G, _ = ctx.objective_grad(g, S, th.detach(), DR, 4, 2)
+    assert torch.allclose(th.grad, w[:, None] * G)
+
+
+def test_evaluate_batch_uneven_and_graph_replay(ctx):
+    from paper_2109_11920_amd.api import SliceBatch
+    shapes = [(96, 16), (128, 24), (192, 12), (256, 8)]
+    slices, refs = [], []
+    for i, (n, na) in enumerate(shapes):
+        g, og = geom_pair(n, na)
+        S, _ = make_slice(og, seed=30 + i, counts=2e4)
+        th = cands(40 + i, 2 + i % 2)
+        slices.append(SliceBatch.make(g, dev(S), dev(th), with_grad=(i % 2 == 0)))
+        refs.append((og, S, th))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx.evaluate_batch(slices, DR, 4, 2)
+    stream.synchronize()
+    first = [(s.obj.clone(), None if s.grad is None else s.grad.clone()) for s in slices]
+    for s in slices:
+        s.obj.fill_(0)
+    with torch.cuda.stream(stream):
+        ctx.evaluate_batch(slices, DR, 4, 2)   # replays the captured graph
+    stream.synchronize()
+    for s, (J0, G0) in zip(slices, first):
+        assert torch.equal(s.obj, J0)
+        if G0 is not None:
+            assert torch.equal(s.grad, G0)
+    for i, (s, (og, S, th)) in enumerate(zip(slices, refs)):
+        for c in range(th.shape[0]):
+            if s.grad is not None:
+                Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 4)
+                report(f"batch slice {i} n={og.n} dJ cand {c}", s.grad[c].cpu().numpy(), Gr, TOL_GRAD)
+            else:
+                Jr = oracle.evaluate(og, S, th[c], DR, 4)[0]
+            report(f"batch slice {i} n={og.n} J cand {c}", s.obj[c:c + 1].cpu().numpy(), np.array([Jr]), TOL)
