@@ -29,7 +29,7 @@
  *     (attenuation tensors, iterates, partial sums) lives in the context and grows on demand; calls on
  *     one context must be serialised by the caller (one stream at a time).
  *   - Arguments are validated before any launch: geometry sizes >= 2, n <= 1024, n_bins <= 4096,
- *     n_samples <= 1024, pixel_cm > 0 and finite, 1 <= C <= 2^20, n_iter >= 0, finite candidates,
+ *     n_bins <= 2 n, n_samples <= 1024, pixel_cm > 0 and finite, 1 <= C <= 2^20, n_iter >= 0, finite candidates,
  *     non-null and 16-byte-aligned pointers where required. Nothing aborts or throws across the ABI.
  *   - On failure the return value is non-zero and boac_last_error() holds a message (thread-local).
  *     HIP failures map to BOAC_EDEVICE with the HIP error text.

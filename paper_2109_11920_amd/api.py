@@ -3,6 +3,7 @@ candidate evaluation runs in the library's HIP kernels; torch provides device me
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -10,6 +11,8 @@ import torch
 
 from . import _lib
 from ._lib import BoacError, BoacGeom, BoacSlice, check
+
+DEFAULT_TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 STATUS_ZERO_PROJECTION = 1
 STATUS_NONFINITE = 2
@@ -62,7 +65,11 @@ class Context:
     """A libboac context on one GPU (scratch, launch plans, graphs, instrumentation)."""
 
     def __init__(self, device: int = 0, tune_cache: Optional[str] = None):
+        """tune_cache: plan cache written by the autotuner; default: the package's tune_cache.json
+        when present (or $BOAC_TUNE_CACHE, read by the library)."""
         self.lib = _lib.load()
+        if tune_cache is None and os.path.exists(DEFAULT_TUNE_CACHE) and not os.environ.get("BOAC_TUNE_CACHE"):
+            tune_cache = DEFAULT_TUNE_CACHE
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
         check(self.lib.boac_ctx_create(device, tune_cache.encode() if tune_cache else None, ctypes.byref(h)))

@@ -72,6 +72,13 @@ __device__ __forceinline__ void comp_merge(Comp &c, const Comp &o) {
     c.e += e + o.e;
 }
 __device__ __forceinline__ float comp_value(const Comp &c) { return c.s + c.e; }
+// Kahan's compensated step (4 operations): e carries the running rounding residual.
+__device__ __forceinline__ void kahan_add(Comp &c, float x) {
+    const float y = x + c.e;
+    const float t = c.s + y;
+    c.e = y - (t - c.s);
+    c.s = t;
+}
 
 // Wave64 reduction of a compensated pair (cross-lane TwoSum tree).
 __device__ __forceinline__ Comp wave_reduce(Comp c) {
@@ -106,24 +113,70 @@ __device__ __forceinline__ Comp block_reduce(Comp c, float *scratch) {
 }
 
 // ---------------------------------------------------------------- LDS image staging
-// Stage rows band.alo..band.ahi and columns -1..n+1 of an n x n image (element stride `stride`
-// floats, component `comp`) into lds with row pitch n+3.
+// Stage rows band.alo..band.ahi and columns -1..n+1 of an n x n image (NC = 1 scalar image, NC = 2
+// interleaved pair) into lds with row pitch n+3, zero outside the image. Eight loads per thread are
+// issued before their stores so the copy is not one memory round trip per element; the row index
+// uses an exact float reciprocal (idx < 2^20, pitch <= 1027).
 template <int NC>
 __device__ __forceinline__ void stage_band(const float *__restrict__ img, int n, const Band &band, float *lds) {
+    constexpr int U = 8;
     const int pitch = n + 3;
     const int rows = band.ahi - band.alo + 1;
     const int total = rows * pitch;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int rr = idx / pitch;
-        const int cc = idx - rr * pitch;
-        const int i = band.alo + rr;
-        const int l = cc - 1;
-        const bool in = (i >= 0) && (i < n) && (l >= 0) && (l < n);
-        if constexpr (NC == 1) {
-            lds[idx] = in ? img[(size_t)i * n + l] : 0.f;
-        } else {
-            float2 v = in ? reinterpret_cast<const float2 *>(img)[(size_t)i * n + l] : make_float2(0.f, 0.f);
-            reinterpret_cast<float2 *>(lds)[idx] = v;
+    const float inv_pitch = 1.f / (float)pitch;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float v[U][NC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int rr = (int)(((float)idx + 0.5f) * inv_pitch);
+            const int i = band.alo + rr;
+            const int l = idx - rr * pitch - 1;
+            const bool in = (idx < total) && (i >= 0) && (i < n) && (l >= 0) && (l < n);
+            if constexpr (NC == 1) {
+                v[u][0] = in ? img[(size_t)i * n + l] : 0.f;
+            } else {
+                const float2 t = in ? reinterpret_cast<const float2 *>(img)[(size_t)i * n + l] : make_float2(0.f, 0.f);
+                v[u][0] = t.x;
+                v[u][1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) {
+                if constexpr (NC == 1)
+                    lds[idx] = v[u][0];
+                else
+                    reinterpret_cast<float2 *>(lds)[idx] = make_float2(v[u][0], v[u][1]);
+            }
+        }
+    }
+}
+
+// Component `comp` of an image with `stride` floats per pixel (one plane of an interleaved image).
+__device__ __forceinline__ void stage_band_strided(const float *__restrict__ img, int n, int stride, const Band &band,
+                                                   float *lds) {
+    constexpr int U = 8;
+    const int pitch = n + 3;
+    const int rows = band.ahi - band.alo + 1;
+    const int total = rows * pitch;
+    const float inv_pitch = 1.f / (float)pitch;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int rr = (int)(((float)idx + 0.5f) * inv_pitch);
+            const int i = band.alo + rr;
+            const int l = idx - rr * pitch - 1;
+            const bool in = (idx < total) && (i >= 0) && (i < n) && (l >= 0) && (l < n);
+            v[u] = in ? img[((size_t)i * n + l) * stride] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) lds[idx] = v[u];
         }
     }
 }
@@ -196,6 +249,18 @@ __device__ __forceinline__ void band_k_range(const DevGeom &g, const Band &band,
     hi = fminf(hi + 2.f, (float)(g.nt - 1));
     k0 = (int)floorf(lo);
     k1 = (int)ceilf(hi);
+}
+
+// Bilinear read at (U, V) from a whole-image stage (rows -1..n+1, columns -1..n+1, pitch n+3):
+// the clamp to [-1, n] keeps every tap inside the zero border.
+__device__ __forceinline__ float bilinear_whole(const float *lds, float U, float V, float nf, int pitch) {
+    const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
+    const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
+    const float fu = __builtin_amdgcn_fractf(Uc);
+    const float fv = __builtin_amdgcn_fractf(Vc);
+    const int l0 = __float2int_rd(Uc);
+    const int i0 = __float2int_rd(Vc);
+    return lerp2(lds + (i0 + 1) * pitch + (l0 + 1), pitch, fu, fv);
 }
 
 // hat(x) = max(0, 1 - |x|)

@@ -3,152 +3,258 @@
 //
 // (A^T z)_j = dx sum_a sum_{(b,k)} W_{abk,j} att_abk z_ab. For each angle, pixel j receives from the
 // samples whose bilinear footprint covers it; those lie in a (2 hb + 1) x 3 window of (bin, k) around
-// the pixel's position in the rotated sample lattice. Each weight is hat(U_bk - l) * hat(V_bk - i)
-// with (U_bk, V_bk) evaluated by the same FMA sequence as the forward projector, so the pair is an
-// exact transpose up to FP32 rounding of the weights.
+// the pixel's position in the rotated sample lattice, each with weight hat(U_bk - l) * hat(V_bk - i)
+// (hat(x) = max(0, 1 - |x|)), i.e. the forward projector's bilinear weight of that pixel.
 //
-// A workgroup owns a tile of pixels of cg candidates of one slice and loops over every angle: it stages
-// the tile's footprint rectangle of att * z (bin fastest, coalesced) for its candidates in LDS, then
-// each thread gathers for its pixels. The window weights are computed once and applied to all cg
-// candidates. Angle sums are compensated. Because the workgroup sees all angles of its pixels, the MLEM
-// update F <- F * b / s happens in the epilogue, with no partial images in memory.
+// A workgroup owns a TW x TH tile of pixels of CG candidates of one slice and loops over every angle:
+//   1. stage the tile's footprint rectangle of att * z (bin fastest in memory, one row per wave,
+//      coalesced) into LDS with the CG candidates interleaved, so that one wide LDS read returns a
+//      window sample for every candidate;
+//   2. each thread computes the window weights of its pixels once (incrementally from the window
+//      centre) and applies them to all CG candidates.
+// Angle sums run in blocks of 8 angles, each block added to a compensated total. Because the
+// workgroup sees all angles of its pixels, the MLEM update F <- F * b / s is its epilogue: no partial
+// images are written.
 #include "launch.h"
 
 namespace boac {
 
-template <int MODE, int CG, int PPT, int HB>
-__global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A) {
-    extern __shared__ float lds[];
+template <int CG>
+struct Vec;
+template <>
+struct Vec<1> {
+    float v[1];
+    __device__ __forceinline__ void load(const float *p) { v[0] = p[0]; }
+};
+template <>
+struct Vec<2> {
+    float v[2];
+    __device__ __forceinline__ void load(const float *p) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+};
+template <>
+struct Vec<4> {
+    float v[4];
+    __device__ __forceinline__ void load(const float *p) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+};
+
+__device__ __forceinline__ float hat1(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
+
+// Rows of the footprint rectangle a wave stages per angle (waves take rows wave, wave + 4, ...).
+template <int TW, int TH>
+struct StageRows {
+    // rectangle height <= ceil(sqrt((TW-1)^2 + (TH-1)^2)) + 8 (see the host's plan), over 4 waves
+    static constexpr int value = (TW == 16 && TH == 16) ? 8 : (TW == 32 && TH == 16) ? 11 : 14;
+};
+
+template <int CG, int TW, int TH, int HB>
+__global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, int mode) {
+    constexpr int PPT = (TW * TH) / 256;
+    constexpr int MR = StageRows<TW, TH>::value;
+    extern __shared__ float lds[];  // [wkmax][wbmax][CG] footprint, then [wbmax][CG] ray weights
     const int ntiles = T.tiles_x * T.tiles_y;
     const int ngroups = (A.C + CG - 1) / CG;
     const int total = ntiles * ngroups;
     int id = blockIdx.x;
-    // keep the tiles of one candidate group on one XCD: their footprints overlap in L2
+    // the tiles of one candidate group run on one XCD: their footprints overlap in L2
     if ((total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
     const int grp = id / ntiles;
     const int tile = id - grp * ntiles;
     const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
-    const int l0 = tx * T.tw, i0 = ty * T.th;
+    const int l0 = tx * TW, i0 = ty * TH;
     const int c0 = grp * CG;
     const int ncg = min(CG, A.C - c0);
-    const int rect = T.wbmax * T.wkmax;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
     const float inv_bscale = 1.f / g.bscale;
+    const bool weighted = (mode != BACK_SENS && mode != BACK_FIELD);
+    const float *src = (mode == BACK_FIELD) ? A.z : A.att;
+    float *zl = lds + (size_t)T.wkmax * T.wbmax * CG;
 
-    // this thread's pixels
-    int pl[PPT], pi[PPT];
+    float xj[PPT], yj[PPT];
     bool pv[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int p = threadIdx.x + j * blockDim.x;
-        const int py = p / T.tw, px = p - py * T.tw;
-        pl[j] = l0 + px;
-        pi[j] = i0 + py;
-        pv[j] = (py < T.th) && (pl[j] < g.n) && (pi[j] < g.n);
+        const int p = threadIdx.x + j * 256;
+        const int py = p / TW, px = p % TW;
+        pv[j] = (l0 + px < g.n) && (i0 + py < g.n);
+        xj[j] = (float)(l0 + px);
+        yj[j] = (float)(i0 + py);
     }
     Comp acc[PPT][CG];
+    float blk[PPT][CG];
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
 #pragma unroll
-        for (int q = 0; q < CG; ++q) acc[j][q] = Comp{0.f, 0.f};
+        for (int q = 0; q < CG; ++q) {
+            acc[j][q] = Comp{0.f, 0.f};
+            blk[j][q] = 0.f;
+        }
 
-    // tile corner offsets from the image centre (pixel units)
-    const float xl0 = (float)l0 - g.cN, xl1 = (float)min(l0 + T.tw - 1, g.n - 1) - g.cN;
-    const float yi0 = (float)i0 - g.cN, yi1 = (float)min(i0 + T.th - 1, g.n - 1) - g.cN;
+    const float xl0 = (float)l0 - g.cN, xl1 = (float)min(l0 + TW - 1, g.n - 1) - g.cN;
+    const float yi0 = (float)i0 - g.cN, yi1 = (float)min(i0 + TH - 1, g.n - 1) - g.cN;
+    const size_t a_stride = (size_t)g.nt * g.nb;
 
-    for (int a = 0; a < g.na; ++a) {
+    // footprint rectangle of the tile at angle a: bins [b_lo, b_lo + wb), samples [k_lo, k_lo + wk)
+    auto rect = [&](int a, int &b_lo, int &k_lo, int &wb, int &wk) {
         const float2 cs = g.trig[a];
         const float c = cs.x, s = cs.y;
-        // footprint rectangle: S = (x c + y s)/bscale + cB, T = (-x s + y c) + cT over the tile
         const float sx0 = xl0 * c, sx1 = xl1 * c, sy0 = yi0 * s, sy1 = yi1 * s;
         const float Smin = (fminf(sx0, sx1) + fminf(sy0, sy1)) * inv_bscale + g.cB;
         const float Smax = (fmaxf(sx0, sx1) + fmaxf(sy0, sy1)) * inv_bscale + g.cB;
         const float tx0 = -xl0 * s, tx1 = -xl1 * s, ty0 = yi0 * c, ty1 = yi1 * c;
         const float Tmin = fminf(tx0, tx1) + fminf(ty0, ty1) + g.cT;
         const float Tmax = fmaxf(tx0, tx1) + fmaxf(ty0, ty1) + g.cT;
-        const int b_lo = (int)floorf(Smin + 0.5f) - HB - 1;
-        const int k_lo = (int)floorf(Tmin + 0.5f) - 2;
-        const int wb = min((int)floorf(Smax + 0.5f) + HB + 1 - b_lo + 1, T.wbmax);
-        const int wk = min((int)floorf(Tmax + 0.5f) + 2 - k_lo + 1, T.wkmax);
+        b_lo = (int)floorf(Smin + 0.5f) - HB - 1;
+        k_lo = (int)floorf(Tmin + 0.5f) - 2;
+        wb = min((int)floorf(Smax + 0.5f) + HB + 1 - b_lo + 1, min(T.wbmax, kWave));
+        wk = min((int)floorf(Tmax + 0.5f) + 2 - k_lo + 1, min(T.wkmax, 4 * MR));
+    };
+    // register prefetch of one angle's rectangle: lane = bin column, rows wave + 4 m
+    float pre[MR][CG];
+    float prez[CG];
+    auto prefetch = [&](int a, int b_lo, int k_lo, int wb, int wk) {
+        const int b = b_lo + lane;
+        const bool bin_ok = (lane < wb) && (b >= 0) && (b < g.nb);
+#pragma unroll
+        for (int q = 0; q < CG; ++q) {
+            prez[q] = 1.f;
+            if (weighted && bin_ok && q < ncg) prez[q] = A.z[(size_t)(c0 + q) * A.sino_cs + (size_t)a * g.nb + b];
+        }
+#pragma unroll
+        for (int m = 0; m < MR; ++m) {
+            const int kk = wave + 4 * m;
+            const int k = k_lo + kk;
+            const bool ok = bin_ok && (kk < wk) && (k >= 0) && (k < g.nt);
+            const size_t off = (size_t)a * a_stride + (size_t)k * g.nb + b;
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                pre[m][q] = 0.f;
+                if (ok && q < ncg) pre[m][q] = src[(size_t)(c0 + q) * A.att_cs + off];
+            }
+        }
+    };
 
-        __syncthreads();
-        // stage att * z (or the sample field) for the rectangle, zero outside the sinogram
-        const int per = wb * wk;
-        for (int idx = threadIdx.x; idx < ncg * per; idx += blockDim.x) {
-            const int q = idx / per;
-            const int rem = idx - q * per;
-            const int kk = rem / wb, bb = rem - kk * wb;
-            const int b = b_lo + bb, k = k_lo + kk;
-            float v = 0.f;
-            if (b >= 0 && b < g.nb && k >= 0 && k < g.nt) {
-                const int cand = c0 + q;
-                const size_t ai = cand * A.att_cs + ((size_t)a * g.nt + k) * g.nb + b;
-                if constexpr (MODE == BACK_FIELD) {
-                    v = A.z[ai];
-                } else if constexpr (MODE == BACK_SENS) {
-                    v = A.att[ai];
+    int b_lo, k_lo, wb, wk;
+    rect(0, b_lo, k_lo, wb, wk);
+    prefetch(0, b_lo, k_lo, wb, wk);
+
+    for (int a = 0; a < g.na; ++a) {
+        __syncthreads();  // previous gather done with the LDS
+        // ---- write the prefetched rectangle (CG candidates interleaved) and the ray weights
+        if (lane < wb) {
+#pragma unroll
+            for (int m = 0; m < MR; ++m) {
+                const int kk = wave + 4 * m;
+                if (kk >= wk) break;
+                float *dst = lds + ((size_t)kk * wb + lane) * CG;
+                if constexpr (CG == 4) {
+                    reinterpret_cast<float4 *>(dst)[0] = make_float4(pre[m][0], pre[m][1], pre[m][2], pre[m][3]);
+                } else if constexpr (CG == 2) {
+                    reinterpret_cast<float2 *>(dst)[0] = make_float2(pre[m][0], pre[m][1]);
                 } else {
-                    v = A.att[ai] * A.z[cand * A.sino_cs + (size_t)a * g.nb + b];
+#pragma unroll
+                    for (int q = 0; q < CG; ++q) dst[q] = pre[m][q];
                 }
             }
-            lds[q * rect + kk * wb + bb] = v;
+            if (wave == 0) {
+#pragma unroll
+                for (int q = 0; q < CG; ++q) zl[lane * CG + q] = prez[q];
+            }
         }
         __syncthreads();
+        const int cb_lo = b_lo, ck_lo = k_lo, cwb = wb, cwk = wk;
+        // ---- issue the next angle's loads; they complete while this angle's gather runs
+        if (a + 1 < g.na) {
+            rect(a + 1, b_lo, k_lo, wb, wk);
+            prefetch(a + 1, b_lo, k_lo, wb, wk);
+        }
 
+        // ---- gather: window weights once per pixel, applied to every candidate
+        // U(b,k) = sigma_b c - tau_k s + cN with sigma_b = (b - cB) bscale, tau_k = k - cT:
+        // one bin step moves (U, V) by (c, s) bscale, one k step by (-s, c)
+        const float2 cs = g.trig[a];
+        const float c = cs.x, s = cs.y;
+        const float ub = c * g.bscale, vb = s * g.bscale;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (!pv[j]) continue;
-            const float xj = (float)pl[j] - g.cN, yj = (float)pi[j] - g.cN;
-            const float Sj = fmaf(xj, c, yj * s) * inv_bscale + g.cB;
-            const float Tj = fmaf(yj, c, -xj * s) + g.cT;
-            // window centre, kept inside the staged rectangle
+            const float xc = xj[j] - g.cN, yc = yj[j] - g.cN;
+            const float Sj = fmaf(xc, c, yc * s) * inv_bscale + g.cB;
+            const float Tj = fmaf(yc, c, -xc * s) + g.cT;
             int bc = (int)floorf(Sj + 0.5f);
             int kc = (int)floorf(Tj + 0.5f);
-            bc = min(max(bc, b_lo + HB), b_lo + wb - 1 - HB);
-            kc = min(max(kc, k_lo + 1), k_lo + wk - 2);
-            const float fl = (float)pl[j], fi = (float)pi[j];
-            float part[CG];
-#pragma unroll
-            for (int q = 0; q < CG; ++q) part[q] = 0.f;
+            bc = min(max(bc, cb_lo + HB), cb_lo + cwb - 1 - HB);
+            kc = min(max(kc, ck_lo + 1), ck_lo + cwk - 2);
+            // offsets of sample (bc, kc) from the pixel, same FMA sequence as the projector
+            float Ub, Vb, U0, V0;
+            ray_base(g, sigma_of(g, bc), c, s, Ub, Vb);
+            sample_uv(Ub, Vb, tau_of(g, kc), c, s, U0, V0);
+            const float du0 = U0 - xj[j], dv0 = V0 - yj[j];
+            const float *base = lds + ((size_t)(kc - ck_lo) * cwb + (bc - cb_lo)) * CG;
+            const float *zb = zl + (size_t)(bc - cb_lo) * CG;
 #pragma unroll
             for (int db = -HB; db <= HB; ++db) {
-                const int b = bc + db;
-                float Ub, Vb;
-                ray_base(g, sigma_of(g, b), c, s, Ub, Vb);
+                const float dub = fmaf((float)db, ub, du0);
+                const float dvb = fmaf((float)db, vb, dv0);
+                float part[CG];
+#pragma unroll
+                for (int q = 0; q < CG; ++q) part[q] = 0.f;
 #pragma unroll
                 for (int dk = -1; dk <= 1; ++dk) {
-                    const int k = kc + dk;
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), c, s, U, V);
-                    const float w = hat(U - fl) * hat(V - fi);
-                    const int li = (k - k_lo) * wb + (b - b_lo);
+                    const float du = fmaf((float)dk, -s, dub);
+                    const float dv = fmaf((float)dk, c, dvb);
+                    const float w = hat1(du) * hat1(dv);
+                    Vec<CG> gv;
+                    gv.load(base + (dk * cwb + db) * CG);
 #pragma unroll
-                    for (int q = 0; q < CG; ++q) part[q] = fmaf(w, lds[q * rect + li], part[q]);
+                    for (int q = 0; q < CG; ++q) part[q] = fmaf(w, gv.v[q], part[q]);
                 }
-            }
+                Vec<CG> zv;
+                zv.load(zb + db * CG);
 #pragma unroll
-            for (int q = 0; q < CG; ++q) comp_add(acc[j][q], part[q]);
+                for (int q = 0; q < CG; ++q) blk[j][q] = fmaf(part[q], zv.v[q], blk[j][q]);
+            }
+        }
+        if ((a & 7) == 7 || a == g.na - 1) {
+#pragma unroll
+            for (int j = 0; j < PPT; ++j)
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    comp_add(acc[j][q], blk[j][q]);
+                    blk[j][q] = 0.f;
+                }
         }
     }
 
-    // epilogue
+    // ---- epilogue
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (!pv[j]) continue;
-        const size_t pix = (size_t)pi[j] * g.n + pl[j];
+        const size_t pix = (size_t)yj[j] * g.n + (size_t)xj[j];
 #pragma unroll
         for (int q = 0; q < CG; ++q) {
             if (q >= ncg) break;
             const size_t o = (size_t)(c0 + q) * A.img_cs + pix;
             const float v = comp_value(acc[j][q]);
-            if constexpr (MODE == BACK_FIELD) {
+            if (mode == BACK_FIELD) {
                 A.out[o] = v;
-            } else if constexpr (MODE == BACK_MLEM) {
+            } else if (mode == BACK_MLEM) {
                 const float b = g.dx * v;
                 const float sv = A.s[o];
                 const float Q = (sv > 0.f) ? b / sv : 0.f;
                 A.out[o] = A.F[o] * Q;
                 if (A.q_out) A.q_out[o] = Q;
-            } else if constexpr (MODE == BACK_ADJ) {
+            } else if (mode == BACK_ADJ) {
                 A.out[o] = fmaf(g.dx, v, A.aux[o]);
             } else {
                 A.out[o] = g.dx * v;
@@ -157,49 +263,36 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A) 
     }
 }
 
-template <int MODE, int CG, int PPT>
-static hipError_t back3(const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
+template <int CG, int TW, int TH, int HB>
+static hipError_t back_go(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
     const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
-    switch (bc.hb) {
-        case 1: hipLaunchKernelGGL((k_back<MODE, CG, PPT, 1>), grid, dim3(256), bc.lds, st, g, bc, a); break;
-        case 2: hipLaunchKernelGGL((k_back<MODE, CG, PPT, 2>), grid, dim3(256), bc.lds, st, g, bc, a); break;
-        case 3: hipLaunchKernelGGL((k_back<MODE, CG, PPT, 3>), grid, dim3(256), bc.lds, st, g, bc, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL((k_back<CG, TW, TH, HB>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
     return hipGetLastError();
 }
 
-template <int MODE, int CG>
-static hipError_t back2(const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
-    switch (bc.ppt) {
-        case 1: return back3<MODE, CG, 1>(g, bc, a, st);
-        case 2: return back3<MODE, CG, 2>(g, bc, a, st);
-        case 4: return back3<MODE, CG, 4>(g, bc, a, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int MODE>
-static hipError_t back1(const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
-    switch (bc.cg) {
-        case 1: return back2<MODE, 1>(g, bc, a, st);
-        case 2: return back2<MODE, 2>(g, bc, a, st);
-        case 4: return back2<MODE, 4>(g, bc, a, st);
-        case 8: return back2<MODE, 8>(g, bc, a, st);
-        default: return hipErrorInvalidValue;
-    }
+template <int CG, int HB>
+static hipError_t back_tile(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
+    if (bc.tw == 16 && bc.th == 16) return back_go<CG, 16, 16, HB>(g, bc, a, mode, st);
+    if (bc.tw == 32 && bc.th == 16) return back_go<CG, 32, 16, HB>(g, bc, a, mode, st);
+    if (bc.tw == 32 && bc.th == 32) return back_go<CG, 32, 32, HB>(g, bc, a, mode, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
-    switch (mode) {
-        case BACK_PLAIN: return back1<BACK_PLAIN>(g, bc, a, st);
-        case BACK_SENS: return back1<BACK_SENS>(g, bc, a, st);
-        case BACK_MLEM: return back1<BACK_MLEM>(g, bc, a, st);
-        case BACK_FIELD: return back1<BACK_FIELD>(g, bc, a, st);
-        case BACK_ADJ: return back1<BACK_ADJ>(g, bc, a, st);
-        default: return hipErrorInvalidValue;
+    if (bc.hb == 1) {
+        switch (bc.cg) {
+            case 1: return back_tile<1, 1>(g, bc, a, mode, st);
+            case 2: return back_tile<2, 1>(g, bc, a, mode, st);
+            case 4: return back_tile<4, 1>(g, bc, a, mode, st);
+            default: return hipErrorInvalidValue;
+        }
     }
+    // wider bin windows (n_bins > 1.06 n): one configuration
+    if (bc.tw != 16 || bc.th != 16 || bc.cg != 1) return hipErrorInvalidValue;
+    if (bc.hb == 2) return back_go<1, 16, 16, 2>(g, bc, a, mode, st);
+    if (bc.hb == 3) return back_go<1, 16, 16, 3>(g, bc, a, mode, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace boac

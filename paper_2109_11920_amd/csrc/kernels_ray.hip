@@ -28,7 +28,7 @@ constexpr int kMaxRpt = 4;
 
 // ------------------------------------------------------------------ attenuation
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
+__global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
                                              const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
                                              size_t att_cs) {
     extern __shared__ float lds[];
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_att(DevGeom g, Bands bands, int rpt, in
 
 // ------------------------------------------------------------------ forward projection
 template <int MODE, bool SINGLE>
-__global__ __launch_bounds__(256) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+__global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
     extern __shared__ float lds[];
     __shared__ float red[16];
     int cand, chunk;
@@ -121,19 +121,10 @@ __global__ __launch_bounds__(256) void k_fwd(DevGeom g, Bands bands, int rpt, in
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
         __syncthreads();
-        if (A.img_comps == 1) {
+        if (A.img_comps == 1)
             stage_band<1>(img, g.n, band, lds);
-        } else {
-            // component 0 of an interleaved pair image
-            const int rows = band.ahi - band.alo + 1;
-            const int total = rows * pitch;
-            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-                const int rr = idx / pitch, cc = idx - rr * pitch;
-                const int i = band.alo + rr, l = cc - 1;
-                const bool in = (i >= 0) && (i < g.n) && (l >= 0) && (l < g.n);
-                lds[idx] = in ? img[((size_t)i * g.n + l) * A.img_comps] : 0.f;
-            }
-        }
+        else
+            stage_band_strided(img, g.n, A.img_comps, band, lds);  // component 0 of an interleaved pair
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kMaxRpt; ++j) {
@@ -145,17 +136,45 @@ __global__ __launch_bounds__(256) void k_fwd(DevGeom g, Bands bands, int rpt, in
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
             const float *col = att + (size_t)a * g.nt * g.nb + b;
-            int k0 = 0, k1 = g.nt - 1;
-            if constexpr (!SINGLE) band_k_range(g, band, Vb, cs.x, k0, k1);
             Comp c = acc[j];
+            if constexpr (SINGLE) {
+                // att is streamed 16 samples ahead of use: the loads of chunk k0 + 16 are in flight
+                // while chunk k0 is computed
+                constexpr int KC = 16;
+                float cur[KC], nxt[KC];
+#pragma unroll
+                for (int q = 0; q < KC; ++q) cur[q] = (q < g.nt) ? col[(size_t)q * g.nb] : 0.f;
+                float tau = -g.cT;
+                for (int k0 = 0; k0 < g.nt; k0 += KC) {
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        const int k = k0 + KC + q;
+                        nxt[q] = (k < g.nt) ? col[(size_t)k * g.nb] : 0.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        if (k0 + q < g.nt) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
+                            kahan_add(c, cur[q] * bilinear_whole(lds, U, V, nf, pitch));
+                        }
+                        tau += 1.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) cur[q] = nxt[q];
+                }
+            } else {
+                int k0 = 0, k1 = g.nt - 1;
+                band_k_range(g, band, Vb, cs.x, k0, k1);
 #pragma unroll 4
-            for (int k = k0; k <= k1; ++k) {
-                float U, V;
-                sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                const Tap t = make_tap<SINGLE>(U, V, nf, pitch, band);
-                if (!SINGLE && !t.mine) continue;
-                const float v = lerp2(lds + t.off, pitch, t.fu, t.fv);
-                comp_add(c, col[(size_t)k * g.nb] * v);
+                for (int k = k0; k <= k1; ++k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                    if (!t.mine) continue;
+                    const float v = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                    kahan_add(c, col[(size_t)k * g.nb] * v);
+                }
             }
             acc[j] = c;
         }
@@ -209,7 +228,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevGeom g, Bands bands, int rpt, in
 
 // ------------------------------------------------------------------ att adjoint accumulation
 template <int NIMG, bool SINGLE>
-__global__ __launch_bounds__(256) void k_attbar(DevGeom g, Bands bands, int rpt, int chunks, int C, AttbarArgs A) {
+__global__ __launch_bounds__(512) void k_attbar(DevGeom g, Bands bands, int rpt, int chunks, int C, AttbarArgs A) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
@@ -262,7 +281,7 @@ __global__ __launch_bounds__(256) void k_attbar(DevGeom g, Bands bands, int rpt,
 // ------------------------------------------------------------------ tail of the attenuation adjoint
 // att_bar += dx W s_bar;  L_bar = -att * att_bar;  m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k')
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
+__global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);

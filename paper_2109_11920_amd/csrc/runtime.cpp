@@ -56,6 +56,7 @@ static boac_status check_geom(const boac_geom *g) {
     if (g->n < 2 || g->n > 1024) return fail(BOAC_ESHAPE, "n = %d outside [2, 1024]", g->n);
     if (g->n_angles < 2 || g->n_angles > 8192) return fail(BOAC_ESHAPE, "n_angles = %d outside [2, 8192]", g->n_angles);
     if (g->n_bins < 2 || g->n_bins > 4096) return fail(BOAC_ESHAPE, "n_bins = %d outside [2, 4096]", g->n_bins);
+    if (g->n_bins > 2 * g->n) return fail(BOAC_ESHAPE, "n_bins = %d above 2 n = %d", g->n_bins, 2 * g->n);
     if (g->n_samples < 2 || g->n_samples > 1024)
         return fail(BOAC_ESHAPE, "n_samples = %d outside [2, 1024]", g->n_samples);
     if (!(g->pixel_cm > 0.f) || !std::isfinite(g->pixel_cm))
@@ -251,7 +252,7 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
     auto it = ctx->tune.find(shape_key("ray", g, C, comps));
     if (it != ctx->tune.end() && it->second.size() >= 2) {
         const int blk = it->second[0], rpt = it->second[1];
-        if ((blk == 64 || blk == 128 || blk == 256) && rpt >= 1 && rpt <= 4) {
+        if ((blk == 64 || blk == 128 || blk == 256 || blk == 512) && rpt >= 1 && rpt <= 4) {
             rc->block = blk;
             rc->rpt = rpt;
         }
@@ -260,7 +261,7 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
 }
 
 static void back_fill(const boac_geom &g, BackCfg *bc) {
-    bc->th = 256 * bc->ppt / bc->tw;
+    bc->ppt = bc->tw * bc->th / 256;
     bc->hb = bin_half_window(g);
     const double diag = std::sqrt((double)(bc->tw - 1) * (bc->tw - 1) + (double)(bc->th - 1) * (bc->th - 1));
     const double rho = (double)g.n_bins / g.n;
@@ -268,43 +269,58 @@ static void back_fill(const boac_geom &g, BackCfg *bc) {
     bc->wkmax = (int)std::ceil(diag) + 8;
     bc->tiles_x = (g.n + bc->tw - 1) / bc->tw;
     bc->tiles_y = (g.n + bc->th - 1) / bc->th;
-    bc->lds = (size_t)bc->cg * bc->wbmax * bc->wkmax * sizeof(float);
+    bc->lds = (size_t)bc->cg * (bc->wbmax * bc->wkmax + bc->wbmax) * sizeof(float);
+}
+
+// rows of the footprint rectangle the back kernel can stage per angle (4 waves x rows per wave)
+static int back_stage_rows(const BackCfg &b) {
+    if (b.tw == 16 && b.th == 16) return 4 * 8;
+    if (b.tw == 32 && b.th == 16) return 4 * 11;
+    return 4 * 14;
+}
+
+static bool back_cfg_ok(const BackCfg &b) {
+    const bool tile = (b.tw == 16 && b.th == 16) || (b.tw == 32 && b.th == 16) || (b.tw == 32 && b.th == 32);
+    const bool cg = b.cg == 1 || b.cg == 2 || b.cg == 4;
+    if (!tile || !cg || b.lds > kLdsBudget) return false;
+    if (b.wbmax > 64 || b.wkmax > back_stage_rows(b)) return false;
+    if (b.hb > 1) return b.tw == 16 && b.th == 16 && b.cg == 1;
+    return b.hb == 1;
 }
 
 static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
-    // defaults: large tiles and several candidates per workgroup when the batch is big enough
-    bc->tw = 32;
-    bc->ppt = 4;
-    bc->cg = 1;
-    const int target = 2 * ctx->n_cu;
-    for (int cg : {4, 2, 1}) {
-        if (C < cg) continue;
-        bc->cg = cg;
-        back_fill(g, bc);
-        if ((long)bc->tiles_x * bc->tiles_y * ((C + cg - 1) / cg) >= target) break;
+    // preference order: big tiles and many candidates per workgroup amortise the footprint staging
+    // and the window weights; fall back while the grid would not fill the GPU twice over
+    static const int prefs[][3] = {{32, 16, 4}, {16, 16, 4}, {16, 16, 2}, {16, 16, 1}};
+    const long target = 2L * ctx->n_cu;
+    bool set = false;
+    for (const auto &pf : prefs) {
+        BackCfg t{};
+        t.tw = pf[0];
+        t.th = pf[1];
+        t.cg = pf[2];
+        back_fill(g, &t);
+        if (!back_cfg_ok(t)) continue;
+        *bc = t;
+        set = true;
+        if (C >= t.cg && (long)t.tiles_x * t.tiles_y * ((C + t.cg - 1) / t.cg) >= target) break;
     }
-    back_fill(g, bc);
-    if ((long)bc->tiles_x * bc->tiles_y * ((C + bc->cg - 1) / bc->cg) < ctx->n_cu) {
-        bc->tw = 16;
-        bc->ppt = 1;
-        back_fill(g, bc);
+    if (!set || bin_half_window(g) > 1) {
+        BackCfg t{};
+        t.tw = 16;
+        t.th = 16;
+        t.cg = 1;
+        back_fill(g, &t);
+        *bc = t;
     }
     auto it = ctx->tune.find(shape_key("back", g, C, 0));
     if (it != ctx->tune.end() && it->second.size() >= 3) {
-        BackCfg t = *bc;
+        BackCfg t{};
         t.tw = it->second[0];
-        t.ppt = it->second[1];
+        t.th = it->second[1];
         t.cg = it->second[2];
-        const bool ok = (t.tw == 16 || t.tw == 32 || t.tw == 64) && (t.ppt == 1 || t.ppt == 2 || t.ppt == 4) &&
-                        (t.cg == 1 || t.cg == 2 || t.cg == 4 || t.cg == 8) && (256 * t.ppt) % t.tw == 0;
-        if (ok) {
-            back_fill(g, &t);
-            if (t.lds <= kLdsBudget) *bc = t;
-        }
-    }
-    while (bc->lds > kLdsBudget && bc->cg > 1) {
-        bc->cg /= 2;
-        back_fill(g, bc);
+        back_fill(g, &t);
+        if (back_cfg_ok(t)) *bc = t;
     }
 }
 
