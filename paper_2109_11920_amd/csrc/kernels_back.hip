@@ -56,10 +56,22 @@ struct StageRows {
     static constexpr int value = (TW == 16 && TH == 16) ? 8 : (TW == 32 && TH == 16) ? 11 : 14;
 };
 
+// Prefetch slots per thread: the largest footprint rectangle (wb x wk, bounded by the host's plan)
+// over 256 threads.
+template <int TW, int TH, int HB>
+struct StageSlots {
+    static constexpr int value = (HB > 1) ? 8 : (TW == 16 && TH == 16) ? 4 : (TW == 32 && TH == 16) ? 8 : 11;
+};
+
+// Load with a uniform base and a 32-bit byte offset (lets the compiler use the scalar-base form).
+__device__ __forceinline__ float ld_off(const float *__restrict__ base, unsigned byte_off) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 template <int CG, int TW, int TH, int HB>
 __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int PPT = (TW * TH) / 256;
-    constexpr int MR = StageRows<TW, TH>::value;
+    constexpr int ME = StageSlots<TW, TH, HB>::value;  // prefetch slots per thread
     extern __shared__ float lds[];  // [wkmax][wbmax][CG] footprint, then [wbmax][CG] ray weights
     const int ntiles = T.tiles_x * T.tiles_y;
     const int ngroups = (A.C + CG - 1) / CG;
@@ -79,6 +91,17 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
     const bool weighted = (mode != BACK_SENS && mode != BACK_FIELD);
     const float *src = (mode == BACK_FIELD) ? A.z : A.att;
     float *zl = lds + (size_t)T.wkmax * T.wbmax * CG;
+    const int4 *rects = T.rects + (size_t)tile * g.na;
+
+    // per-candidate bases (uniform); candidates past the batch end re-read the last one, unused
+    const float *srcq[CG];
+    const float *zq_base[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        const int cq = c0 + min(q, ncg - 1);
+        srcq[q] = src + (size_t)cq * A.att_cs;
+        zq_base[q] = weighted ? A.z + (size_t)cq * A.sino_cs : nullptr;
+    }
 
     float xj[PPT], yj[PPT];
     bool pv[PPT];
@@ -100,63 +123,56 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
             blk[j][q] = 0.f;
         }
 
-    const float xl0 = (float)l0 - g.cN, xl1 = (float)min(l0 + TW - 1, g.n - 1) - g.cN;
-    const float yi0 = (float)i0 - g.cN, yi1 = (float)min(i0 + TH - 1, g.n - 1) - g.cN;
-    const size_t a_stride = (size_t)g.nt * g.nb;
-
-    // footprint rectangle of the tile at angle a: bins [b_lo, b_lo + wb), samples [k_lo, k_lo + wk)
-    auto rect = [&](int a, int &b_lo, int &k_lo, int &wb, int &wk) {
-        const float2 cs = g.trig[a];
-        const float c = cs.x, s = cs.y;
-        const float sx0 = xl0 * c, sx1 = xl1 * c, sy0 = yi0 * s, sy1 = yi1 * s;
-        const float Smin = (fminf(sx0, sx1) + fminf(sy0, sy1)) * inv_bscale + g.cB;
-        const float Smax = (fmaxf(sx0, sx1) + fmaxf(sy0, sy1)) * inv_bscale + g.cB;
-        const float tx0 = -xl0 * s, tx1 = -xl1 * s, ty0 = yi0 * c, ty1 = yi1 * c;
-        const float Tmin = fminf(tx0, tx1) + fminf(ty0, ty1) + g.cT;
-        const float Tmax = fmaxf(tx0, tx1) + fmaxf(ty0, ty1) + g.cT;
-        b_lo = (int)floorf(Smin + 0.5f) - HB - 1;
-        k_lo = (int)floorf(Tmin + 0.5f) - 2;
-        wb = min((int)floorf(Smax + 0.5f) + HB + 1 - b_lo + 1, min(T.wbmax, kWave));
-        wk = min((int)floorf(Tmax + 0.5f) + 2 - k_lo + 1, min(T.wkmax, 4 * MR));
-    };
-    // register prefetch of one angle's rectangle: lane = bin column, rows wave + 4 m
-    float pre[MR][CG];
+    const unsigned nb4 = 4u * (unsigned)g.nb;
+    const unsigned a_stride4 = 4u * (unsigned)(g.nt * g.nb);
+    // register prefetch of one angle's rectangle, flattened: element e = kk * wb + bb of the
+    // rectangle goes to thread e % 256, slot e / 256 (every loading lane carries a needed sample)
+    float pre[ME][CG];
     float prez[CG];
-    auto prefetch = [&](int a, int b_lo, int k_lo, int wb, int wk) {
-        const int b = b_lo + lane;
-        const bool bin_ok = (lane < wb) && (b >= 0) && (b < g.nb);
+    auto prefetch = [&](int a, int4 r) {
+        const int npe = r.z * r.w;
+        const float inv_wb = 1.f / (float)r.z;
+        const unsigned abase = (unsigned)a * a_stride4;
 #pragma unroll
-        for (int q = 0; q < CG; ++q) {
-            prez[q] = 1.f;
-            if (weighted && bin_ok && q < ncg) prez[q] = A.z[(size_t)(c0 + q) * A.sino_cs + (size_t)a * g.nb + b];
-        }
-#pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int kk = wave + 4 * m;
-            const int k = k_lo + kk;
-            const bool ok = bin_ok && (kk < wk) && (k >= 0) && (k < g.nt);
-            const size_t off = (size_t)a * a_stride + (size_t)k * g.nb + b;
+        for (int m = 0; m < ME; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            // e / wb by an exact float reciprocal (e < 2^16, wb <= 64)
+            const int kk = (int)(((float)e + 0.5f) * inv_wb);
+            const int bb = e - kk * r.z;
+            const int b = r.x + bb, k = r.y + kk;
+            const bool ok = (e < npe) && (b >= 0) && (b < g.nb) && (k >= 0) && (k < g.nt);
+            const unsigned off = abase + (unsigned)k * nb4 + 4u * (unsigned)b;
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
-                pre[m][q] = 0.f;
-                if (ok && q < ncg) pre[m][q] = src[(size_t)(c0 + q) * A.att_cs + off];
+                float v = 0.f;
+                if (ok) v = ld_off(srcq[q], off);
+                pre[m][q] = v;
             }
+        }
+        // ray weights of the rectangle's bins: the first wave, one bin per lane
+        const int b = r.x + lane;
+        const bool bin_ok = (lane < r.z) && (b >= 0) && (b < g.nb);
+#pragma unroll
+        for (int q = 0; q < CG; ++q) {
+            float z = bin_ok ? 1.f : 0.f;
+            if (weighted && bin_ok && wave == 0) z = ld_off(zq_base[q], 4u * (unsigned)(a * g.nb + b));
+            prez[q] = z;
         }
     };
 
-    int b_lo, k_lo, wb, wk;
-    rect(0, b_lo, k_lo, wb, wk);
-    prefetch(0, b_lo, k_lo, wb, wk);
+    int4 cur = rects[0];
+    prefetch(0, cur);
 
     for (int a = 0; a < g.na; ++a) {
         __syncthreads();  // previous gather done with the LDS
         // ---- write the prefetched rectangle (CG candidates interleaved) and the ray weights
-        if (lane < wb) {
+        {
+            const int npe = cur.z * cur.w;
 #pragma unroll
-            for (int m = 0; m < MR; ++m) {
-                const int kk = wave + 4 * m;
-                if (kk >= wk) break;
-                float *dst = lds + ((size_t)kk * wb + lane) * CG;
+            for (int m = 0; m < ME; ++m) {
+                const int e = threadIdx.x + 256 * m;
+                if (e >= npe) break;
+                float *dst = lds + e * CG;
                 if constexpr (CG == 4) {
                     reinterpret_cast<float4 *>(dst)[0] = make_float4(pre[m][0], pre[m][1], pre[m][2], pre[m][3]);
                 } else if constexpr (CG == 2) {
@@ -166,17 +182,17 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
                     for (int q = 0; q < CG; ++q) dst[q] = pre[m][q];
                 }
             }
-            if (wave == 0) {
+            if (wave == 0 && lane < cur.z) {
 #pragma unroll
                 for (int q = 0; q < CG; ++q) zl[lane * CG + q] = prez[q];
             }
         }
         __syncthreads();
-        const int cb_lo = b_lo, ck_lo = k_lo, cwb = wb, cwk = wk;
+        const int4 r = cur;
         // ---- issue the next angle's loads; they complete while this angle's gather runs
         if (a + 1 < g.na) {
-            rect(a + 1, b_lo, k_lo, wb, wk);
-            prefetch(a + 1, b_lo, k_lo, wb, wk);
+            cur = rects[a + 1];
+            prefetch(a + 1, cur);
         }
 
         // ---- gather: window weights once per pixel, applied to every candidate
@@ -185,23 +201,27 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
         const float2 cs = g.trig[a];
         const float c = cs.x, s = cs.y;
         const float ub = c * g.bscale, vb = s * g.bscale;
+        const float fbl = (float)r.x, fkl = (float)r.y, fwb = (float)r.z;
+        const float bmin = fbl + (float)HB, bmax = fbl + (float)(r.z - 1 - HB);
+        const float kmin = fkl + 1.f, kmax = fkl + (float)(r.w - 2);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (!pv[j]) continue;
             const float xc = xj[j] - g.cN, yc = yj[j] - g.cN;
             const float Sj = fmaf(xc, c, yc * s) * inv_bscale + g.cB;
             const float Tj = fmaf(yc, c, -xc * s) + g.cT;
-            int bc = (int)floorf(Sj + 0.5f);
-            int kc = (int)floorf(Tj + 0.5f);
-            bc = min(max(bc, cb_lo + HB), cb_lo + cwb - 1 - HB);
-            kc = min(max(kc, ck_lo + 1), ck_lo + cwk - 2);
+            // window centre (nearest sample), kept inside the staged rectangle
+            const float bcf = __builtin_amdgcn_fmed3f(floorf(Sj + 0.5f), bmin, bmax);
+            const float kcf = __builtin_amdgcn_fmed3f(floorf(Tj + 0.5f), kmin, kmax);
             // offsets of sample (bc, kc) from the pixel, same FMA sequence as the projector
             float Ub, Vb, U0, V0;
-            ray_base(g, sigma_of(g, bc), c, s, Ub, Vb);
-            sample_uv(Ub, Vb, tau_of(g, kc), c, s, U0, V0);
+            ray_base(g, (bcf - g.cB) * g.bscale, c, s, Ub, Vb);
+            sample_uv(Ub, Vb, kcf - g.cT, c, s, U0, V0);
             const float du0 = U0 - xj[j], dv0 = V0 - yj[j];
-            const float *base = lds + ((size_t)(kc - ck_lo) * cwb + (bc - cb_lo)) * CG;
-            const float *zb = zl + (size_t)(bc - cb_lo) * CG;
+            const int row = (int)fmaf(kcf - fkl, fwb, bcf - fbl);  // exact small integers
+            const float *base = lds + row * CG;
+            const float *zb = zl + (int)(bcf - fbl) * CG;
+            const int rstep = r.z * CG;
 #pragma unroll
             for (int db = -HB; db <= HB; ++db) {
                 const float dub = fmaf((float)db, ub, du0);
@@ -215,7 +235,7 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
                     const float dv = fmaf((float)dk, c, dvb);
                     const float w = hat1(du) * hat1(dv);
                     Vec<CG> gv;
-                    gv.load(base + (dk * cwb + db) * CG);
+                    gv.load(base + dk * rstep + db * CG);
 #pragma unroll
                     for (int q = 0; q < CG; ++q) part[q] = fmaf(w, gv.v[q], part[q]);
                 }

@@ -67,6 +67,7 @@ struct BackCfg {
     int wbmax, wkmax;     // footprint rectangle bound
     int tiles_x, tiles_y; // tiles per image
     size_t lds;
+    const int4 *rects;    // [tiles][n_angles] footprint rectangles (b_lo, k_lo, wb, wk)
 };
 
 struct BackArgs {

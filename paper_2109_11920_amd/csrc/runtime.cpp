@@ -61,6 +61,9 @@ static boac_status check_geom(const boac_geom *g) {
         return fail(BOAC_ESHAPE, "n_samples = %d outside [2, 1024]", g->n_samples);
     if (!(g->pixel_cm > 0.f) || !std::isfinite(g->pixel_cm))
         return fail(BOAC_ESHAPE, "pixel_cm = %g must be positive and finite", (double)g->pixel_cm);
+    if ((double)g->n_angles * g->n_bins * g->n_samples * 4.0 >= 4294967296.0)
+        return fail(BOAC_ESHAPE, "n_angles * n_bins * n_samples = %.0f samples: above 2^30 per candidate",
+                    (double)g->n_angles * g->n_bins * g->n_samples);
     const int hb = bin_half_window(*g);
     if (hb < 1 || hb > 3)
         return fail(BOAC_ESHAPE, "n_bins / n = %g gives a bin window of %d; supported 1..3", (double)g->n_bins / g->n, hb);
@@ -108,6 +111,7 @@ struct boac_ctx {
     int n_cu = 256;
     std::map<std::string, DevBuf> bufs;
     std::map<std::vector<int>, float2 *> trig;
+    std::map<std::vector<int>, int4 *> rects;
     std::map<std::string, std::vector<int>> tune;
     bool profiling = false;
     std::vector<PendingTiming> pending;
@@ -153,6 +157,8 @@ static boac_status ensure_t(boac_ctx *ctx, const char *name, size_t count, T **o
     return BOAC_OK;
 }
 
+static boac_status host_trig(int na, std::vector<float2> &h);
+
 // cos/sin of 2 pi a / na in double, exact at multiples of 90 degrees, rounded to float
 static boac_status trig_table(boac_ctx *ctx, int na, const float2 **out) {
     std::vector<int> key{na};
@@ -162,7 +168,18 @@ static boac_status trig_table(boac_ctx *ctx, int na, const float2 **out) {
         return BOAC_OK;
     }
     if (ctx->capturing) return fail(BOAC_EDEVICE, "trig table upload during graph capture");
-    std::vector<float2> h(na);
+    std::vector<float2> h;
+    BOAC_TRY(host_trig(na, h));
+    float2 *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(float2) * na));
+    HIP_TRY(hipMemcpy(d, h.data(), sizeof(float2) * na, hipMemcpyHostToDevice));
+    ctx->trig[key] = d;
+    *out = d;
+    return BOAC_OK;
+}
+
+static boac_status host_trig(int na, std::vector<float2> &h) {
+    h.resize(na);
     for (int a = 0; a < na; ++a) {
         // reduce to the first quadrant on integers so that 0/90/180/270 deg are exact
         const long num = 4L * a;  // angle = 2 pi a / na = (pi/2) * (4a / na)
@@ -183,11 +200,62 @@ static boac_status trig_table(boac_ctx *ctx, int na, const float2 **out) {
         }
         h[a] = make_float2((float)cc, (float)ss);
     }
-    float2 *d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(float2) * na));
-    HIP_TRY(hipMemcpy(d, h.data(), sizeof(float2) * na, hipMemcpyHostToDevice));
-    ctx->trig[key] = d;
-    *out = d;
+    return BOAC_OK;
+}
+
+// Footprint rectangles of every (pixel tile, angle) of the backprojection: bins and samples whose
+// window can reach a pixel of the tile, with one sample of margin on every side (the kernel's window
+// centres, computed in FP32, stay inside). Computed in double from the same FP32 angle table.
+static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
+    std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb};
+    auto it = ctx->rects.find(key);
+    if (it != ctx->rects.end()) {
+        bc->rects = it->second;
+        return BOAC_OK;
+    }
+    if (ctx->capturing) return fail(BOAC_EDEVICE, "rectangle table upload during graph capture");
+    std::vector<float2> trig;
+    BOAC_TRY(host_trig(g.n_angles, trig));
+    const double cN = 0.5 * (g.n - 1), cB = 0.5 * (g.n_bins - 1), cT = 0.5 * (g.n_samples - 1);
+    const double inv_bscale = (double)g.n_bins / (double)g.n;
+    const int ntiles = bc->tiles_x * bc->tiles_y;
+    const int wb_cap = std::min(bc->wbmax, 64);
+    const int wk_cap = bc->wkmax;
+    std::vector<int4> h((size_t)ntiles * g.n_angles);
+    for (int t = 0; t < ntiles; ++t) {
+        const int ty = t / bc->tiles_x, tx = t % bc->tiles_x;
+        const int l0 = tx * bc->tw, i0 = ty * bc->th;
+        const double xl[2] = {l0 - cN, std::min(l0 + bc->tw - 1, g.n - 1) - cN};
+        const double yi[2] = {i0 - cN, std::min(i0 + bc->th - 1, g.n - 1) - cN};
+        for (int a = 0; a < g.n_angles; ++a) {
+            const double c = trig[a].x, s = trig[a].y;
+            double Smin = 1e300, Smax = -1e300, Tmin = 1e300, Tmax = -1e300;
+            for (double x : xl)
+                for (double y : yi) {
+                    const double S = (x * c + y * s) * inv_bscale + cB;
+                    const double T = (-x * s + y * c) + cT;
+                    Smin = std::min(Smin, S);
+                    Smax = std::max(Smax, S);
+                    Tmin = std::min(Tmin, T);
+                    Tmax = std::max(Tmax, T);
+                }
+            const int b_lo = (int)std::floor(Smin + 0.5) - bc->hb - 1;
+            const int b_hi = (int)std::floor(Smax + 0.5) + bc->hb + 1;
+            const int k_lo = (int)std::floor(Tmin + 0.5) - 2;
+            const int k_hi = (int)std::floor(Tmax + 0.5) + 2;
+            const int wb = b_hi - b_lo + 1, wk = k_hi - k_lo + 1;
+            const int slots = (bc->hb > 1) ? 8 : (bc->tw == 16 && bc->th == 16) ? 4 : (bc->tw == 32 && bc->th == 16) ? 8 : 11;
+            if (wb > wb_cap || wk > wk_cap || wb * wk > 256 * slots)
+                return fail(BOAC_EDEVICE, "internal: footprint %dx%d exceeds the staged bound %dx%d", wb, wk, wb_cap,
+                            wk_cap);
+            h[(size_t)t * g.n_angles + a] = make_int4(b_lo, k_lo, wb, wk);
+        }
+    }
+    int4 *d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(int4) * h.size()));
+    HIP_TRY(hipMemcpy(d, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice));
+    ctx->rects[key] = d;
+    bc->rects = d;
     return BOAC_OK;
 }
 
@@ -324,12 +392,11 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
     }
 }
 
-static Plan make_plan(boac_ctx *ctx, const boac_geom &g, int C) {
-    Plan p;
-    ray_plan(ctx, g, C, 1, &p.ray1, &p.bands1);
-    ray_plan(ctx, g, C, 2, &p.ray2, &p.bands2);
-    back_plan(ctx, g, C, &p.back);
-    return p;
+static boac_status make_plan(boac_ctx *ctx, const boac_geom &g, int C, Plan *p) {
+    ray_plan(ctx, g, C, 1, &p->ray1, &p->bands1);
+    ray_plan(ctx, g, C, 2, &p->ray2, &p->bands2);
+    back_plan(ctx, g, C, &p->back);
+    return rect_table(ctx, g, &p->back);
 }
 
 // ------------------------------------------------------------------ instrumentation
@@ -453,7 +520,8 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, g, &dg));
     const int Cc = cand_chunk(z, C, 1);
-    const Plan p = make_plan(ctx, g, Cc);
+    Plan p;
+    BOAC_TRY(make_plan(ctx, g, Cc, &p));
     float *mu, *att, *s, *F0, *F1, *r;
     float2 *partial, *lg;
     uint32_t *flag, *st_int;
@@ -518,7 +586,8 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     if (ck > std::max(K, 1)) ck = std::max(K, 1);
     const int nck = (K + ck - 1) / ck;  // stored records 0, ck, 2ck, ... < K
     const int Cc = cand_chunk(z, C, 2);
-    const Plan p = make_plan(ctx, g, Cc);
+    Plan p;
+    BOAC_TRY(make_plan(ctx, g, Cc, &p));
     const size_t I = z.I, Y = z.Y;
     float *mu, *att, *attbar, *s, *sbar, *fbar, *fdir, *mubar, *gtmp, *yK, *ybar, *Ftmp, *Fwork;
     float2 *bbarF, *partial, *lg;
@@ -787,6 +856,7 @@ void boac_ctx_destroy(boac_ctx *ctx) {
     for (auto &kv : ctx->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (auto &kv : ctx->trig) (void)hipFree(kv.second);
+    for (auto &kv : ctx->rects) (void)hipFree(kv.second);
     for (auto &p : ctx->pending) {
         (void)hipEventDestroy(p.e0);
         (void)hipEventDestroy(p.e1);
@@ -842,7 +912,8 @@ boac_status boac_project(boac_ctx *ctx, const boac_geom *geom, const float *d_mu
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, *geom, &dg));
     const int Cc = cand_chunk(z, C, 1);
-    const Plan p = make_plan(ctx, *geom, Cc);
+    Plan p;
+    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int n = std::min(Cc, C - c0);
         float *att;
@@ -867,7 +938,8 @@ boac_status boac_backproject(boac_ctx *ctx, const boac_geom *geom, const float *
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, *geom, &dg));
     const int Cc = cand_chunk(z, C, 1);
-    const Plan p = make_plan(ctx, *geom, Cc);
+    Plan p;
+    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int n = std::min(Cc, C - c0);
         float *att;
@@ -892,7 +964,8 @@ boac_status boac_mlem(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, c
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, *geom, &dg));
     const int Cc = cand_chunk(z, C, 1);
-    const Plan p = make_plan(ctx, *geom, Cc);
+    Plan p;
+    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
     float *s, *Fs, *r;
     BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * z.I, &s));
     BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &Fs));
