@@ -199,9 +199,14 @@ __global__ void k_adj_elem(AdjElemArgs A) {
             sb = fb * (F * Q) / sv;
         }
         A.sbar[o] -= sb;
-        A.bbarF[o] = make_float2(bbar, F);
+        A.pair[o] = make_float2(bbar, F * Q);
         A.fbar_direct[o] = fb * Q;
     }
+}
+
+__global__ void k_pack_pair(const float *a, float b_const, float2 *out, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = make_float2(a[i], b_const);
 }
 
 __global__ void k_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status) {
@@ -273,6 +278,10 @@ hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const flo
 }
 hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_elem, dim3(fill_blocks((size_t)a.npix * a.C)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_pack_pair(const float *a, float b_const, float2 *out, size_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_pair, dim3(fill_blocks(count)), dim3(256), 0, st, a, b_const, out, count);
     return hipGetLastError();
 }
 hipError_t launch_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status, hipStream_t st) {

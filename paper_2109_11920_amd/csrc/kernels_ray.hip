@@ -4,8 +4,9 @@
 //   k_att     attenuation scan, Eq. (1) inner integral: m = W mu, L_k = dx (m_k/2 + sum_{k'>k} m_k'),
 //             att = exp(-L), scanned from the detector end with a compensated running sum.
 //   k_fwd     attenuated projection, Eq. (2): y = dx sum_k att (W f), compensated; epilogues give the
-//             MLEM ratio S/y, the Poisson NLL terms of Eq. (5), or the adjoint of the ratio.
-//   k_attbar  adjoint of att for one MLEM iteration: att_bar += dx (r W bbar + ybar W F).
+//             MLEM ratio S/y or the Poisson NLL terms of Eq. (5).
+//   k_adj_sweep  one reverse MLEM step along every ray: the projection adjoint of the ratio and the
+//             attenuation adjoint accumulation, in one sweep.
 //   k_tail    sensitivity adjoint, att = exp(-L) and the scan's transpose (a prefix sum).
 //
 // Layout: att and its adjoint are [cand][angle][k][bin] (bin fastest), so the threads of a wave
@@ -196,10 +197,6 @@ __global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, in
             const float S = A.meas[ray];
             A.r_out[si] = (y > 0.f) ? S / y : 0.f;
             if (A.y_out) A.y_out[si] = y;
-        } else if constexpr (MODE == FWD_YBAR) {
-            // y here is r_bar = A bbar; ybar = -r_bar * r / y^n where y^n > 0
-            const float yn = A.y_in[si];
-            A.r_out[si] = (yn > 0.f) ? -(y * A.r_in[si]) / yn : 0.f;
         } else {  // FWD_NLL
             const float S = A.meas[ray];
             if (A.y_out) A.y_out[si] = y;
@@ -226,22 +223,34 @@ __global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, in
     }
 }
 
-// ------------------------------------------------------------------ att adjoint accumulation
-template <int NIMG, bool SINGLE>
-__global__ __launch_bounds__(512) void k_attbar(DevGeom g, Bands bands, int rpt, int chunks, int C, AttbarArgs A) {
+// ------------------------------------------------------------------ fused reverse sweep
+// One reverse MLEM step n, per ray i (pair image = (bbar^n, F^{n+1}) staged in LDS):
+//   rbar_i   = dx sum_k att_ik (W bbar^n)_ik                          (adjoint of b^n = A^T r^n)
+//   attbar_ik (+)= dx [ r^n_i (W bbar^n)_ik + ybar^{n+1}_i (W F^{n+1})_ik ]
+//   ybar^n_i = -rbar_i r^n_i / y^n_i   (0 where y^n_i <= 0)               (adjoint of r = S / y)
+// The ybar^{n+1} term is the y^{n+1} = A F^{n+1} adjoint left pending by the previous step (or the
+// objective's adjoint for the first step), so each step sweeps the rays once.
+template <bool SINGLE>
+__global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
     const int nrays = g.na * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
+    const float *att = A.att + cand * A.att_cs;
     float *ab = A.attbar + cand * A.att_cs;
-    const float *img = A.img2 + cand * A.img_cs;
+    const float *img = A.pair + cand * A.img_cs;
+    const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
+
+    Comp acc[kMaxRpt];
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
         __syncthreads();
-        stage_band<NIMG>(img, g.n, band, lds);
+        stage_band<2>(img, g.n, band, lds);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kMaxRpt; ++j) {
@@ -253,33 +262,85 @@ __global__ __launch_bounds__(512) void k_attbar(DevGeom g, Bands bands, int rpt,
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
             const size_t si = cand * A.sino_cs + ray;
-            const float yb = g.dx * A.ybar[si];
-            const float rr = (NIMG == 2) ? g.dx * A.r[si] : 0.f;
-            float *col = ab + (size_t)a * g.nt * g.nb + b;
-            int k0 = 0, k1 = g.nt - 1;
-            if constexpr (!SINGLE) band_k_range(g, band, Vb, cs.x, k0, k1);
-#pragma unroll 4
-            for (int k = k0; k <= k1; ++k) {
-                float U, V;
-                sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                const Tap t = make_tap<SINGLE>(U, V, nf, pitch, band);
-                if (!SINGLE && !t.mine) continue;
-                float add;
-                if constexpr (NIMG == 2) {
-                    const float2 v = lerp2x2(reinterpret_cast<const float2 *>(lds) + t.off, pitch, t.fu, t.fv);
-                    add = fmaf(rr, v.x, yb * v.y);
-                } else {
-                    add = yb * lerp2(lds + t.off, pitch, t.fu, t.fv);
+            const float rr = g.dx * A.r[si];
+            const float yp = g.dx * A.ybar_in[si];
+            const size_t col0 = (size_t)a * g.nt * g.nb + b;
+            const float *cat = att + col0;
+            float *cab = ab + col0;
+            Comp c = acc[j];
+            if constexpr (SINGLE) {
+                constexpr int KC = 16;
+                float at[KC], an[KC], bt[KC], bn[KC];
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    at[q] = (q < g.nt) ? cat[(size_t)q * g.nb] : 0.f;
+                    bt[q] = (A.accumulate && q < g.nt) ? cab[(size_t)q * g.nb] : 0.f;
                 }
-                float *p = col + (size_t)k * g.nb;
-                *p = A.accumulate ? (*p + add) : add;
+                float tau = -g.cT;
+                for (int k0 = 0; k0 < g.nt; k0 += KC) {
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        const int k = k0 + KC + q;
+                        an[q] = (k < g.nt) ? cat[(size_t)k * g.nb] : 0.f;
+                        bn[q] = (A.accumulate && k < g.nt) ? cab[(size_t)k * g.nb] : 0.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        const int k = k0 + q;
+                        if (k < g.nt) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
+                            const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
+                            const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
+                            const int l0 = __float2int_rd(Uc), i0 = __float2int_rd(Vc);
+                            const float2 w = lerp2x2(lds2 + (i0 + 1) * pitch + (l0 + 1), pitch,
+                                                     __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
+                            kahan_add(c, at[q] * w.x);
+                            cab[(size_t)k * g.nb] = bt[q] + fmaf(rr, w.x, yp * w.y);
+                        }
+                        tau += 1.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        at[q] = an[q];
+                        bt[q] = bn[q];
+                    }
+                }
+            } else {
+                int k0, k1;
+                band_k_range(g, band, Vb, cs.x, k0, k1);
+                for (int k = k0; k <= k1; ++k) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                    if (!t.mine) continue;
+                    const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                    kahan_add(c, cat[(size_t)k * g.nb] * w.x);
+                    float *p = cab + (size_t)k * g.nb;
+                    const float add = fmaf(rr, w.x, yp * w.y);
+                    *p = A.accumulate ? (*p + add) : add;
+                }
             }
+            acc[j] = c;
         }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) {
+        if (j >= rpt) break;
+        const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+        if (ray >= nrays) continue;
+        const size_t si = cand * A.sino_cs + ray;
+        const float rbar = g.dx * comp_value(acc[j]);
+        const float yn = A.y[si];
+        A.ybar_out[si] = (yn > 0.f) ? -(rbar * A.r[si]) / yn : 0.f;
     }
 }
 
 // ------------------------------------------------------------------ tail of the attenuation adjoint
-// att_bar += dx W s_bar;  L_bar = -att * att_bar;  m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k')
+// att_bar (+)= dx (W G1 + rho_i W G2) with the pair image (G1, G2) = (s_bar, F^0) and rho = ybar^0
+// (the sensitivity adjoint and the last pending projection adjoint); then
+// L_bar = -att * att_bar and m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k') (the scan's transpose),
+// written in place of att_bar.
 template <bool SINGLE>
 __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
     extern __shared__ float lds[];
@@ -290,12 +351,13 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
     const float nf = (float)g.n;
     const float *att = A.att + cand * A.att_cs;
     float *ab = A.attbar + cand * A.att_cs;
-    const float *img = A.sbar + cand * A.img_cs;
+    const float *img = A.pair + cand * A.img_cs;
+    const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
         __syncthreads();
-        stage_band<1>(img, g.n, band, lds);
+        stage_band<2>(img, g.n, band, lds);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kMaxRpt; ++j) {
@@ -306,21 +368,53 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
             const float2 cs = g.trig[a];
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+            const float rho = A.rho[cand * A.sino_cs + ray];
             const size_t off = (size_t)a * g.nt * g.nb + b;
+            const float *cat = att + off;
+            float *cab = ab + off;
             if constexpr (SINGLE) {
+                constexpr int KC = 16;
+                float at[KC], an[KC], bt[KC], bn[KC];
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    at[q] = (q < g.nt) ? cat[(size_t)q * g.nb] : 0.f;
+                    bt[q] = (A.accumulate && q < g.nt) ? cab[(size_t)q * g.nb] : 0.f;
+                }
                 Comp P{0.f, 0.f};
-                for (int k = 0; k < g.nt; ++k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<true>(U, V, nf, pitch, band);
-                    const float wsb = lerp2(lds + t.off, pitch, t.fu, t.fv);
-                    const size_t idx = off + (size_t)k * g.nb;
-                    const float abar = fmaf(g.dx, wsb, ab[idx]);
-                    const float Lbar = -att[idx] * abar;
-                    ab[idx] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
-                    comp_add(P, Lbar);
+                float tau = -g.cT;
+                for (int k0 = 0; k0 < g.nt; k0 += KC) {
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        const int k = k0 + KC + q;
+                        an[q] = (k < g.nt) ? cat[(size_t)k * g.nb] : 0.f;
+                        bn[q] = (A.accumulate && k < g.nt) ? cab[(size_t)k * g.nb] : 0.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        const int k = k0 + q;
+                        if (k < g.nt) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
+                            const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
+                            const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
+                            const int l0 = __float2int_rd(Uc), i0 = __float2int_rd(Vc);
+                            const float2 w = lerp2x2(lds2 + (i0 + 1) * pitch + (l0 + 1), pitch,
+                                                     __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
+                            const float abar = bt[q] + g.dx * fmaf(rho, w.y, w.x);
+                            const float Lbar = -at[q] * abar;
+                            cab[(size_t)k * g.nb] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                            comp_add(P, Lbar);
+                        }
+                        tau += 1.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < KC; ++q) {
+                        at[q] = an[q];
+                        bt[q] = bn[q];
+                    }
                 }
             } else {
+                // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 for (int k = k0; k <= k1; ++k) {
@@ -328,13 +422,16 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
                     sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
                     const Tap t = make_tap<false>(U, V, nf, pitch, band);
                     if (!t.mine) continue;
-                    const size_t idx = off + (size_t)k * g.nb;
-                    ab[idx] = fmaf(g.dx, lerp2(lds + t.off, pitch, t.fu, t.fv), ab[idx]);
+                    const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                    float *p = cab + (size_t)k * g.nb;
+                    const float add = g.dx * fmaf(rho, w.y, w.x);
+                    *p = A.accumulate ? (*p + add) : add;
                 }
             }
         }
     }
     if constexpr (!SINGLE) {
+        // pass 2: every sample of the ray now holds att_bar (written by this thread): scan
 #pragma unroll
         for (int j = 0; j < kMaxRpt; ++j) {
             if (j >= rpt) break;
@@ -384,29 +481,19 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
         case FWD_PROJ: fwd_mode<FWD_PROJ>(g, rc, bands, a, C, st); break;
         case FWD_RATIO: fwd_mode<FWD_RATIO>(g, rc, bands, a, C, st); break;
         case FWD_NLL: fwd_mode<FWD_NLL>(g, rc, bands, a, C, st); break;
-        case FWD_YBAR: fwd_mode<FWD_YBAR>(g, rc, bands, a, C, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_attbar(int nimg, const DevGeom &g, const RayCfg &rc, const Bands &bands, const AttbarArgs &a,
-                         int C, hipStream_t st) {
-    if (nimg == 2) {
-        if (rc.single)
-            hipLaunchKernelGGL((k_attbar<2, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                               rc.chunks, C, a);
-        else
-            hipLaunchKernelGGL((k_attbar<2, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                               rc.chunks, C, a);
-    } else {
-        if (rc.single)
-            hipLaunchKernelGGL((k_attbar<1, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                               rc.chunks, C, a);
-        else
-            hipLaunchKernelGGL((k_attbar<1, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                               rc.chunks, C, a);
-    }
+hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
+                            hipStream_t st) {
+    if (rc.single)
+        hipLaunchKernelGGL(k_adj_sweep<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
+                           C, a);
+    else
+        hipLaunchKernelGGL(k_adj_sweep<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
     return hipGetLastError();
 }
 

@@ -25,36 +25,39 @@ struct RayCfg {
     bool single; // whole image staged at once
 };
 
-enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2, FWD_YBAR = 3 };
+enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2 };
 
 struct FwdArgs {
     const float *att;     // [C][na][nt][nb]
     const float *img;     // [C][n][n] x img_comps interleaved (component 0 is sampled)
     const float *meas;    // [na][nb]
     float *y_out;         // [C][na][nb] or null
-    float *r_out;         // RATIO: r; YBAR: ybar
-    const float *y_in;    // YBAR
-    const float *r_in;    // YBAR
+    float *r_out;         // RATIO: r
     float2 *partial;      // NLL: [C][chunks]
     uint32_t *status;     // NLL: [C] or null
     size_t att_cs, img_cs, sino_cs;
     int img_comps;        // 1 or 2
 };
 
-struct AttbarArgs {
-    float *attbar;        // [C][na][nt][nb]
-    const float *img2;    // NIMG=2: interleaved (bbar, F); NIMG=1: F
-    const float *r;       // [C][na][nb] (NIMG=2)
-    const float *ybar;    // [C][na][nb]
-    size_t att_cs, img_cs, sino_cs;
-    int accumulate;       // 0: write, 1: add
+struct SweepArgs {
+    const float *att;     // [C][na][nt][nb]
+    float *attbar;        // [C][na][nt][nb], written (accumulate = 0) or accumulated
+    const float *pair;    // [C][n][n] float2: (bbar^n, F^{n+1})
+    const float *r;       // r^n [C][na][nb]
+    const float *y;       // y^n
+    const float *ybar_in; // pending ybar^{n+1}
+    float *ybar_out;      // ybar^n
+    size_t att_cs, img_cs, sino_cs;  // img_cs in floats (2 n^2 per candidate)
+    int accumulate;
 };
 
 struct TailArgs {
     const float *att;
     float *attbar;        // in: att_bar, out: m_bar
-    const float *sbar;    // [C][n][n]
-    size_t att_cs, img_cs;
+    const float *pair;    // [C][n][n] float2: (s_bar, F^0)
+    const float *rho;     // ybar^0 [C][na][nb]
+    size_t att_cs, img_cs, sino_cs;
+    int accumulate;       // 0: att_bar starts at zero (no MLEM iterations)
 };
 
 enum BackMode { BACK_PLAIN = 0, BACK_SENS = 1, BACK_MLEM = 2, BACK_FIELD = 3, BACK_ADJ = 4 };
@@ -88,7 +91,7 @@ struct AdjElemArgs {
     const float *Q;       // Q^n
     const float *s;       // sensitivity
     float *sbar;          // accumulated s_bar (read-modify-write)
-    float2 *bbarF;        // out: (bbar^n, F^n) interleaved
+    float2 *pair;         // out: (bbar^n, F^{n+1}) interleaved
     float *fbar_direct;   // out
     size_t img_cs;
     int npix, C;
@@ -103,8 +106,9 @@ hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, co
                       size_t img_cs, size_t att_cs, int C, hipStream_t st);
 hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                       hipStream_t st);
-hipError_t launch_attbar(int nimg, const DevGeom &g, const RayCfg &rc, const Bands &bands, const AttbarArgs &a,
-                         int C, hipStream_t st);
+hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
+                            hipStream_t st);
+hipError_t launch_pack_pair(const float *a, float b_const, float2 *out, size_t count, hipStream_t st);
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st);
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st);

@@ -589,8 +589,8 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     Plan p;
     BOAC_TRY(make_plan(ctx, g, Cc, &p));
     const size_t I = z.I, Y = z.Y;
-    float *mu, *att, *attbar, *s, *sbar, *fbar, *fdir, *mubar, *gtmp, *yK, *ybar, *Ftmp, *Fwork;
-    float2 *bbarF, *partial, *lg;
+    float *mu, *att, *attbar, *s, *sbar, *fbar, *fdir, *mubar, *gtmp, *yK, *ybar, *ybar2, *Ftmp, *Fwork;
+    float2 *pair, *partial, *lg;
     uint32_t *flag, *st_int;
     // records: F, y, r, Q per record; ckpt slots nck, segment slots ck
     float *recF, *recY, *recR, *recQ, *segF, *segY, *segR, *segQ;
@@ -605,9 +605,10 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     BOAC_TRY(ensure_t(ctx, "gtmp", (size_t)Cc * 8, &gtmp));
     BOAC_TRY(ensure_t(ctx, "yK", (size_t)Cc * Y, &yK));
     BOAC_TRY(ensure_t(ctx, "ybar", (size_t)Cc * Y, &ybar));
+    BOAC_TRY(ensure_t(ctx, "ybar2", (size_t)Cc * Y, &ybar2));
     BOAC_TRY(ensure_t(ctx, "Ftmp", (size_t)Cc * I, &Ftmp));
     BOAC_TRY(ensure_t(ctx, "Fwork", (size_t)2 * Cc * I, &Fwork));
-    BOAC_TRY(ensure_t(ctx, "bbarF", (size_t)Cc * I, &bbarF));
+    BOAC_TRY(ensure_t(ctx, "pair", (size_t)Cc * I, &pair));
     BOAC_TRY(ensure_t(ctx, "partial", (size_t)Cc * p.ray1.chunks, &partial));
     BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
     BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
@@ -684,28 +685,18 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
             }));
         }
         // ---- reverse sweep
-        // d/dy (y - S ln y) at y^K: ybar^K = 1 - S / y^K where y^K > 0 (1 where S = 0)
+        // d/dy (y - S ln y) at y^K: ybar^K = 1 - S / y^K where y^K > 0 (1 where S = 0). It stays
+        // pending (its att_bar term is added by the first reverse step's sweep, or by the tail).
+        float *ypend = ybar, *ynext = ybar2;
         HIP_TRY(launch_fill(sbar, nI, 0.f, st));
         BOAC_TRY(timed(ctx, BOAC_K_OTHER, 12.0 * nY, st,
-                       [&] { return launch_ybar_final(meas, yK, ybar, n, (int)Y, Y, st); }));
-        {
-            AttbarArgs aa{};
-            aa.attbar = attbar;
-            aa.img2 = Fcur;
-            aa.ybar = ybar;
-            aa.att_cs = z.V;
-            aa.img_cs = I;
-            aa.sino_cs = Y;
-            aa.accumulate = 0;
-            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (z.V + I + Y), st,
-                           [&] { return launch_attbar(1, dg, p.ray1, p.bands1, aa, n, st); }));
-        }
+                       [&] { return launch_ybar_final(meas, yK, ypend, n, (int)Y, Y, st); }));
         if (K > 0) {
-            BackArgs b = back_args(z, att, ybar, fbar, n);
+            BackArgs b = back_args(z, att, ypend, fbar, n);
             BOAC_TRY(run_back(ctx, BACK_PLAIN, dg, p, z, b, st));
         }
-        const int nseg = nck;
-        for (int sg = nseg - 1; sg >= 0; --sg) {
+        bool first = true;
+        for (int sg = nck - 1; sg >= 0; --sg) {
             const int n0 = sg * ck, n1 = std::min(n0 + ck, K);
             // segment slot j holds record n0 + j
             std::vector<float *> sF(ck), sY(ck), sR(ck), sQ(ck);
@@ -724,49 +715,58 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
             }
             for (int j = n1 - n0 - 1; j >= 0; --j) {
                 const int it = n0 + j;
+                // F^{n+1} = F^n Q^n:  bbar^n, s_bar, direct part of F_bar^n; pair (bbar^n, F^{n+1})
                 AdjElemArgs e{};
                 e.fbar = fbar;
                 e.F = sF[j];
                 e.Q = sQ[j];
                 e.s = s;
                 e.sbar = sbar;
-                e.bbarF = bbarF;
+                e.pair = pair;
                 e.fbar_direct = fdir;
                 e.img_cs = I;
                 e.npix = (int)I;
                 e.C = n;
                 BOAC_TRY(timed(ctx, BOAC_K_OTHER, 4.0 * n * 8.0 * I, st, [&] { return launch_adj_elem(e, st); }));
-                // ybar^n = -(A bbar^n) r^n / y^n
-                FwdArgs a = fwd_args(z, att, (const float *)bbarF, meas);
-                a.img_comps = 2;
-                a.img_cs = 2 * I;
-                a.y_in = sY[j];
-                a.r_in = sR[j];
-                a.r_out = ybar;
-                BOAC_TRY(run_fwd(ctx, FWD_YBAR, dg, p, z, a, n, st));
-                AttbarArgs aa{};
-                aa.attbar = attbar;
-                aa.img2 = (const float *)bbarF;
-                aa.r = sR[j];
-                aa.ybar = ybar;
-                aa.att_cs = z.V;
-                aa.img_cs = 2 * I;
-                aa.sino_cs = Y;
-                aa.accumulate = 1;
-                BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (2.0 * z.V + 2 * I + 2 * Y), st,
-                               [&] { return launch_attbar(2, dg, p.ray2, p.bands2, aa, n, st); }));
+                // one sweep: ybar^n and att_bar += dx (r^n W bbar^n + ybar^{n+1} W F^{n+1})
+                SweepArgs sa{};
+                sa.att = att;
+                sa.attbar = attbar;
+                sa.pair = (const float *)pair;
+                sa.r = sR[j];
+                sa.y = sY[j];
+                sa.ybar_in = ypend;
+                sa.ybar_out = ynext;
+                sa.att_cs = z.V;
+                sa.img_cs = 2 * I;
+                sa.sino_cs = Y;
+                sa.accumulate = first ? 0 : 1;
+                BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * ((first ? 2.0 : 3.0) * z.V + 2 * I + 4 * Y), st,
+                               [&] { return launch_adj_sweep(dg, p.ray2, p.bands2, sa, n, st); }));
+                first = false;
+                std::swap(ypend, ynext);
                 if (it > 0) {
-                    BackArgs b = back_args(z, att, ybar, fbar, n);
+                    BackArgs b = back_args(z, att, ypend, fbar, n);
                     b.aux = fdir;
                     BOAC_TRY(run_back(ctx, BACK_ADJ, dg, p, z, b, st));
                 }
             }
         }
-        // ---- tail: sensitivity adjoint, exp and scan transposes, mu_bar, raster adjoint
+        // ---- tail: sensitivity adjoint and the pending projection adjoint (with F^0 = 1), exp and
+        // scan transposes, mu_bar, raster adjoint
         {
-            TailArgs ta{att, attbar, sbar, z.V, I};
-            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (3.0 * z.V + I), st,
-                           [&] { return launch_tail(dg, p.ray1, p.bands1, ta, n, st); }));
+            HIP_TRY(launch_pack_pair(sbar, 1.f, pair, nI, st));
+            TailArgs ta{};
+            ta.att = att;
+            ta.attbar = attbar;
+            ta.pair = (const float *)pair;
+            ta.rho = ypend;
+            ta.att_cs = z.V;
+            ta.img_cs = 2 * I;
+            ta.sino_cs = Y;
+            ta.accumulate = first ? 0 : 1;
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (3.0 * z.V + 2 * I + Y), st,
+                           [&] { return launch_tail(dg, p.ray2, p.bands2, ta, n, st); }));
             BackArgs b = back_args(z, att, attbar, mubar, n);
             BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
             BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * I, st,
