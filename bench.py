@@ -84,7 +84,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-cands", type=int, default=2)
+    ap.add_argument("--cpu-cands", type=int, default=32)
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 48-slice uneven batch line")
     ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -221,6 +222,37 @@ def main():
                        "ms_per_batch": round(grad_ms, 3), "forward_ms_per_batch": round(fwd_ms, 3),
                        "grad_over_forward": round(grad_ms / fwd_ms, 3),
                        "what": "64 candidates, 20 iterations, checkpoint every 5"}
+
+    if not args.only_main and not args.no_uneven:
+        # ---- uneven batch: 48 slices (N 96-256, 64-256 angles) x 32 candidates, 40 iterations,
+        # objective + gradient (checkpoint every 5), one captured batch over concurrent stream lanes
+        du = np.load(os.path.join(ROOT, "tests", "golden", "uneven48.npz"))
+        wu = synth.workload("uneven48")
+        cu = synth.workload_candidates(wu)
+        slices = []
+        for s in range(int(du["n_slices"])):
+            n, na, nb, nt = (int(v) for v in du[f"s{s:02d}_geometry"])
+            gs = Geometry(n, na, nb, nt, float(du[f"s{s:02d}_pixel"]))
+            slices.append(SliceBatch.make(gs, torch.as_tensor(du[f"s{s:02d}_meas"].astype(np.float32), device=dev),
+                                          torch.as_tensor(cu[s].astype(np.float32), device=dev), with_grad=True))
+        ustream = torch.cuda.Stream(dev)
+        with torch.cuda.stream(ustream):
+            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # runs eagerly, then captures
+            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # graph replay (warm)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ustream)
+            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)
+            e1.record(ustream)
+        ustream.synchronize()
+        ums = e0.elapsed_time(e1)
+        n_eval = sum(sb.cand.shape[0] for sb in slices)
+        ok = all(bool(torch.isfinite(sb.obj).all()) and bool(torch.isfinite(sb.grad).all()) for sb in slices)
+        out["uneven48"] = {"value": round(n_eval * wu.n_iter / (ums / 1e3), 1), "unit": "cand·it/s",
+                           "obj_grad_evals_per_s": round(n_eval / (ums / 1e3), 1), "ms_per_batch": round(ums, 2),
+                           "finite": ok,
+                           "what": "48 slices N in {96,128,192,256}, 64-256 angles, 32 candidates each, 40 "
+                                   "iterations, objective + gradient, checkpoint 5, one graph replay"}
 
     if not args.no_cpu and not args.only_main:
         out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K)

@@ -24,8 +24,7 @@ ROOT = os.path.dirname(HERE)
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 
 RAY_CONFIGS = [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4)]
-BACK_CONFIGS = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (32, 16, 1), (32, 16, 2), (32, 16, 4), (32, 32, 1),
-                (32, 32, 2)]
+BACK_CONFIGS = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (16, 16, 8), (32, 16, 2), (32, 16, 4), (32, 32, 2)]
 
 
 def key(kind, g, C, extra):

@@ -47,6 +47,23 @@ struct Vec<4> {
     }
 };
 
+template <>
+struct Vec<8> {
+    float v[8];
+    __device__ __forceinline__ void load(const float *p) {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        v[3] = a.w;
+        v[4] = b.x;
+        v[5] = b.y;
+        v[6] = b.z;
+        v[7] = b.w;
+    }
+};
+
 __device__ __forceinline__ float hat1(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
 
 // Rows of the footprint rectangle a wave stages per angle (waves take rows wave, wave + 4, ...).
@@ -173,7 +190,10 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
                 const int e = threadIdx.x + 256 * m;
                 if (e >= npe) break;
                 float *dst = lds + e * CG;
-                if constexpr (CG == 4) {
+                if constexpr (CG == 8) {
+                    reinterpret_cast<float4 *>(dst)[0] = make_float4(pre[m][0], pre[m][1], pre[m][2], pre[m][3]);
+                    reinterpret_cast<float4 *>(dst)[1] = make_float4(pre[m][4], pre[m][5], pre[m][6], pre[m][7]);
+                } else if constexpr (CG == 4) {
                     reinterpret_cast<float4 *>(dst)[0] = make_float4(pre[m][0], pre[m][1], pre[m][2], pre[m][3]);
                 } else if constexpr (CG == 2) {
                     reinterpret_cast<float2 *>(dst)[0] = make_float2(pre[m][0], pre[m][1]);
@@ -305,6 +325,9 @@ hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const Back
             case 1: return back_tile<1, 1>(g, bc, a, mode, st);
             case 2: return back_tile<2, 1>(g, bc, a, mode, st);
             case 4: return back_tile<4, 1>(g, bc, a, mode, st);
+            case 8:
+                if (bc.tw == 16 && bc.th == 16) return back_go<8, 16, 16, 1>(g, bc, a, mode, st);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }

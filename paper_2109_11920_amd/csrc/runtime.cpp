@@ -2,6 +2,7 @@
 // cache), kernel-time instrumentation, HIP-graph capture of batched evaluations, and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -122,10 +123,14 @@ struct boac_ctx {
     std::vector<GraphEntry> graphs;
     bool capturing = false;
     bool scratch_changed = false;
+    std::string ns;                    // scratch namespace of the work being emitted (batch lane)
+    std::vector<hipStream_t> lanes;    // concurrent streams of the batch scheduler
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t fork = nullptr;
 };
 
 static boac_status ensure(boac_ctx *ctx, const char *name, size_t bytes, void **out) {
-    DevBuf &b = ctx->bufs[name];
+    DevBuf &b = ctx->bufs[ctx->ns + name];
     if (b.bytes < bytes) {
         if (ctx->capturing) return fail(BOAC_EDEVICE, "scratch '%s' must grow during graph capture", name);
         if (b.p) {
@@ -349,7 +354,7 @@ static int back_stage_rows(const BackCfg &b) {
 
 static bool back_cfg_ok(const BackCfg &b) {
     const bool tile = (b.tw == 16 && b.th == 16) || (b.tw == 32 && b.th == 16) || (b.tw == 32 && b.th == 32);
-    const bool cg = b.cg == 1 || b.cg == 2 || b.cg == 4;
+    const bool cg = b.cg == 1 || b.cg == 2 || b.cg == 4 || (b.cg == 8 && b.tw == 16 && b.th == 16);
     if (!tile || !cg || b.lds > kLdsBudget) return false;
     if (b.wbmax > 64 || b.wkmax > back_stage_rows(b)) return false;
     if (b.hb > 1) return b.tw == 16 && b.th == 16 && b.cg == 1;
@@ -359,7 +364,7 @@ static bool back_cfg_ok(const BackCfg &b) {
 static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
     // preference order: big tiles and many candidates per workgroup amortise the footprint staging
     // and the window weights; fall back while the grid would not fill the GPU twice over
-    static const int prefs[][3] = {{32, 16, 4}, {16, 16, 4}, {16, 16, 2}, {16, 16, 1}};
+    static const int prefs[][3] = {{16, 16, 8}, {16, 16, 4}, {16, 16, 2}, {16, 16, 1}};
     const long target = 2L * ctx->n_cu;
     bool set = false;
     for (const auto &pf : prefs) {
@@ -862,6 +867,9 @@ void boac_ctx_destroy(boac_ctx *ctx) {
         (void)hipEventDestroy(p.e1);
     }
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    for (auto st : ctx->lanes) (void)hipStreamDestroy(st);
+    for (auto e : ctx->lane_done) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
 }
 
@@ -1028,18 +1036,77 @@ boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const floa
                      d_status, (hipStream_t)stream);
 }
 
+// Relative cost of a slice (algorithmic attenuation-tensor passes x tensor size x candidates).
+static double slice_cost(const boac_slice &s, int K, int ck) {
+    const double V = (double)s.geom.n_angles * s.geom.n_bins * s.geom.n_samples;
+    double passes = 2.0 * K + 3.0;
+    if (s.d_grad) passes += 2.0 * K * (ck - 1) / std::max(ck, 1) + 4.0 * K + 6.0;
+    return V * passes * s.C;
+}
+
+static int batch_lanes() {
+    const char *e = std::getenv("BOAC_BATCH_LANES");
+    int n = e ? std::atoi(e) : 4;
+    return std::min(std::max(n, 1), 16);
+}
+
+static boac_status eval_slice(boac_ctx *ctx, const boac_slice &s, float delta_r, int K, int ck, hipStream_t st) {
+    if (s.d_grad)
+        return eval_grad(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, ck, s.d_obj, s.d_grad,
+                         s.d_status, st);
+    return eval_forward(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, s.d_obj, nullptr,
+                        s.d_status, st);
+}
+
+// Batch scheduler: slices are assigned longest-first to the least-loaded of L concurrent stream
+// lanes (each with its own scratch namespace); the lanes fork from and join back into the caller's
+// stream through events, so a captured batch is one graph with L parallel branches.
 static boac_status batch_body(boac_ctx *ctx, const boac_slice *h, int32_t ns, float delta_r, int32_t K, int32_t ck,
                               hipStream_t st) {
-    for (int i = 0; i < ns; ++i) {
-        const boac_slice &s = h[i];
-        if (s.d_grad)
-            BOAC_TRY(eval_grad(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, ck, s.d_obj, s.d_grad,
-                               s.d_status, st));
-        else
-            BOAC_TRY(eval_forward(ctx, s.geom, s.d_meas, (const float *)s.d_cand, s.C, delta_r, K, s.d_obj, nullptr,
-                                  s.d_status, st));
+    const int L = std::min(batch_lanes(), (int)ns);
+    if (L <= 1) {
+        ctx->ns.clear();
+        for (int i = 0; i < ns; ++i) BOAC_TRY(eval_slice(ctx, h[i], delta_r, K, ck, st));
+        return BOAC_OK;
     }
-    return BOAC_OK;
+    while ((int)ctx->lanes.size() < L) {
+        if (ctx->capturing) return fail(BOAC_EDEVICE, "lane streams must exist before graph capture");
+        hipStream_t s2 = nullptr;
+        hipEvent_t e2 = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+        ctx->lanes.push_back(s2);
+        ctx->lane_done.push_back(e2);
+    }
+    if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return slice_cost(h[a], K, ck) > slice_cost(h[b], K, ck); });
+    std::vector<double> load(L, 0.0);
+    std::vector<std::vector<int>> assign(L);
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        assign[l].push_back(i);
+        load[l] += slice_cost(h[i], K, ck);
+    }
+    HIP_TRY(hipEventRecord(ctx->fork, st));
+    boac_status rs = BOAC_OK;
+    for (int l = 0; l < L && rs == BOAC_OK; ++l) {
+        HIP_TRY(hipStreamWaitEvent(ctx->lanes[l], ctx->fork, 0));
+        ctx->ns = "L" + std::to_string(l) + ":";
+        for (int i : assign[l]) {
+            rs = eval_slice(ctx, h[i], delta_r, K, ck, ctx->lanes[l]);
+            if (rs != BOAC_OK) break;
+        }
+        ctx->ns.clear();
+    }
+    // join every lane back into the caller's stream (also after a failure, so no branch dangles)
+    for (int l = 0; l < L; ++l) {
+        HIP_TRY(hipEventRecord(ctx->lane_done[l], ctx->lanes[l]));
+        HIP_TRY(hipStreamWaitEvent(st, ctx->lane_done[l], 0));
+    }
+    return rs;
 }
 
 boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,

@@ -320,3 +320,30 @@ def test_evaluate_batch_uneven_and_graph_replay(ctx):
             else:
                 Jr = oracle.evaluate(og, S, th[c], DR, 4)[0]
             report(f"batch slice {i} n={og.n} J cand {c}", s.obj[c:c + 1].cpu().numpy(), np.array([Jr]), TOL)
+
+
+def test_launch_configurations_agree(slice64, tmp_path):
+    # every tile shape / candidates-per-workgroup / ray blocking the autotuner may choose gives the
+    # same objective and gradient (the per-candidate arithmetic does not depend on the launch shape)
+    import json
+    from paper_2109_11920_amd.api import Context
+    from paper_2109_11920_amd.autotune import BACK_CONFIGS, RAY_CONFIGS, key
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = dev(slice64["meas"].astype(np.float64))
+    C = 16
+    th = dev(cands(22, C))
+    results = []
+    configs = [(r, b) for r in RAY_CONFIGS[:3] for b in BACK_CONFIGS] + [(r, BACK_CONFIGS[0]) for r in RAY_CONFIGS[3:]]
+    for (blk, rpt), (tw, th_, cg) in configs:
+        path = tmp_path / f"tune_{blk}_{rpt}_{tw}_{th_}_{cg}.json"
+        path.write_text(json.dumps({key("ray", g, C, 1): [blk, rpt], key("ray", g, C, 2): [blk, rpt],
+                                    key("back", g, C, 0): [tw, th_, cg]}))
+        with Context(0, tune_cache=str(path)) as c2:
+            J, G, _ = c2.objective_grad(g, S, th, DR, 3, 2)
+            results.append(((blk, rpt, tw, th_, cg), J.cpu().numpy(), G.cpu().numpy()))
+    ref = results[0]
+    for cfg, J, G in results[1:]:
+        assert np.array_equal(J, ref[1]) and np.array_equal(G, ref[2]), cfg
+    Jr, Gr = oracle.objective_and_grad(og, slice64["meas"].astype(np.float64), cands(22, C)[0], DR, 3)
+    report("launch configs J cand 0", ref[1][:1], np.array([Jr]), TOL)
+    report("launch configs dJ cand 0", ref[2][0], Gr, TOL_GRAD)
