@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--cpu-cands", type=int, default=32)
     ap.add_argument("--no-uneven", action="store_true", help="skip the 48-slice uneven batch line")
     ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: candidates are independent and this build has no multi-GPU "
@@ -112,6 +114,12 @@ def main():
     C, K = cand.shape[0], w.n_iter
     ctx = Context(0)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calib:
+        src = torch.ones(1 << 28, device=dev)          # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- main timed region: the 256-candidate batch, eager launches with per-kernel HIP events
     obj = torch.empty(C, device=dev)

@@ -9,7 +9,7 @@ this file by default):
     python -m paper_2109_11920_amd.autotune [--out PATH] [--workloads batch256_n128,grad64_n128,...]
 
 Keys follow the library: "ray:<n>x<na>x<nb>x<nt>:<C>:<image components>" -> [block, rays per thread]
-and "back:<n>x<na>x<nb>x<nt>:<C>:0" -> [tile width, tile height, candidates per workgroup].
+and "back:<n>x<na>x<nb>x<nt>:<C>:0" -> [tile width, tile height, candidates per workgroup, XCD remap].
 """
 from __future__ import annotations
 
@@ -109,6 +109,14 @@ def tune_workload(name: str, cache: dict, log=print):
             log(f"[tune] {name} {shape} back tile={tw}x{th} cg={cg}: {t * 1e3:.1f} us/launch")
             if best is None or t < best[0]:
                 best = (t, [tw, th, cg])
+        for remap in (0, 1):
+            cfg = best[1][:3] + [remap]
+            e = dict(cache)
+            e[key("back", g, C, 0)] = cfg
+            t = _time(g, meas, cand, e, "back", K)
+            log(f"[tune] {name} {shape} back tile={cfg[0]}x{cfg[1]} cg={cfg[2]} xcd_remap={remap}: {t * 1e3:.1f} us/launch")
+            if t < best[0]:
+                best = (t, cfg)
         cache[key("back", g, C, 0)] = best[1]
         log(f"[tune] {name} {shape} -> ray {cache[key('ray', g, C, 1)]} back {best[1]}")
     return cache

@@ -80,9 +80,15 @@ struct StageSlots {
     static constexpr int value = (HB > 1) ? 8 : (TW == 16 && TH == 16) ? 4 : (TW == 32 && TH == 16) ? 8 : 11;
 };
 
-// Load with a uniform base and a 32-bit byte offset (lets the compiler use the scalar-base form).
-__device__ __forceinline__ float ld_off(const float *__restrict__ base, unsigned byte_off) {
-    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+// Raw buffer resource over `bytes` bytes at p (gfx9 descriptor word 3): loads take a 32-bit byte offset
+// from the uniform base. Every load below is predicated to in-range offsets; elements that must read
+// as zero are zeroed in registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const float *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    // the b32 load yields the raw 32-bit word: reinterpret it, do not convert it
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
 template <int CG, int TW, int TH, int HB>
@@ -94,8 +100,9 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
     const int ngroups = (A.C + CG - 1) / CG;
     const int total = ntiles * ngroups;
     int id = blockIdx.x;
-    // the tiles of one candidate group run on one XCD: their footprints overlap in L2
-    if ((total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
+    // the tiles of one candidate group run on one XCD (workgroups are dealt round-robin to the 8
+    // XCDs): their footprints overlap in L2. A plan option, chosen by the autotuner.
+    if (T.xcd_remap && (total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
     const int grp = id / ntiles;
     const int tile = id - grp * ntiles;
     const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
@@ -110,17 +117,17 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
     float *zl = lds + (size_t)T.wkmax * T.wbmax * CG;
     const int4 *rects = T.rects + (size_t)tile * g.na;
 
-    // per-candidate bases (uniform); candidates past the batch end re-read the last one, unused
-    const float *srcq[CG];
-    const float *zq_base[CG];
+    // per-candidate buffer resources (uniform); candidates past the batch end read as zero
+    __amdgpu_buffer_rsrc_t srcq[CG], zq[CG];
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
+        const bool live = q < ncg;
         const int cq = c0 + min(q, ncg - 1);
-        srcq[q] = src + (size_t)cq * A.att_cs;
-        zq_base[q] = weighted ? A.z + (size_t)cq * A.sino_cs : nullptr;
+        srcq[q] = buffer_rsrc(src + (size_t)cq * A.att_cs, live ? (unsigned)(4 * A.att_cs) : 0u);
+        zq[q] = buffer_rsrc(weighted ? A.z + (size_t)cq * A.sino_cs : src, (live && weighted) ? (unsigned)(4 * A.sino_cs) : 0u);
     }
 
-    float xj[PPT], yj[PPT];
+    float xj[PPT], yj[PPT], xcj[PPT], ycj[PPT];
     bool pv[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -129,6 +136,8 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
         pv[j] = (l0 + px < g.n) && (i0 + py < g.n);
         xj[j] = (float)(l0 + px);
         yj[j] = (float)(i0 + py);
+        xcj[j] = xj[j] - g.cN;
+        ycj[j] = yj[j] - g.cN;
     }
     Comp acc[PPT][CG];
     float blk[PPT][CG];
@@ -142,37 +151,62 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
 
     const unsigned nb4 = 4u * (unsigned)g.nb;
     const unsigned a_stride4 = 4u * (unsigned)(g.nt * g.nb);
-    // register prefetch of one angle's rectangle, flattened: element e = kk * wb + bb of the
-    // rectangle goes to thread e % 256, slot e / 256 (every loading lane carries a needed sample)
+    // The footprint rectangle is staged with a fixed pitch P = wbmax (height wkmax), so each thread's
+    // prefetch slots e = tid + 256 m have fixed rectangle coordinates (kk, bb) for the whole tile.
+    const int P = T.wbmax;
+    const int PH = T.wbmax * T.wkmax;
+    int skk[ME], sbb[ME];
+    float fkk[ME], fbb[ME];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) {
+        const int e = threadIdx.x + 256 * m;
+        skk[m] = e / P;
+        sbb[m] = e - skk[m] * P;
+        if (e >= PH) skk[m] = 1 << 20;  // never inside a rectangle
+        fkk[m] = (float)skk[m];
+        fbb[m] = (float)sbb[m];
+    }
+    // union of the tile pixels' bilinear supports (open): samples outside it have zero weight for
+    // every pixel of the tile, so they are neither loaded nor gathered (their LDS slot holds 0)
+    const float sup_l0 = (float)l0 - 1.f - 1e-3f, sup_l1 = (float)min(l0 + TW - 1, g.n - 1) + 1.f + 1e-3f;
+    const float sup_i0 = (float)i0 - 1.f - 1e-3f, sup_i1 = (float)min(i0 + TH - 1, g.n - 1) + 1.f + 1e-3f;
     float pre[ME][CG];
     float prez[CG];
     auto prefetch = [&](int a, int4 r) {
-        const int npe = r.z * r.w;
-        const float inv_wb = 1.f / (float)r.z;
         const unsigned abase = (unsigned)a * a_stride4;
+        const float2 cs = g.trig[a];
+        // image position of the rectangle's corner sample and its steps per bin / per sample
+        float Ur, Vr;
+        {
+            float Ub, Vb;
+            ray_base(g, sigma_of(g, r.x), cs.x, cs.y, Ub, Vb);
+            sample_uv(Ub, Vb, tau_of(g, r.y), cs.x, cs.y, Ur, Vr);
+        }
+        const float ubs = cs.x * g.bscale, vbs = cs.y * g.bscale;
 #pragma unroll
         for (int m = 0; m < ME; ++m) {
-            const int e = threadIdx.x + 256 * m;
-            // e / wb by an exact float reciprocal (e < 2^16, wb <= 64)
-            const int kk = (int)(((float)e + 0.5f) * inv_wb);
-            const int bb = e - kk * r.z;
+            const int kk = skk[m], bb = sbb[m];
             const int b = r.x + bb, k = r.y + kk;
-            const bool ok = (e < npe) && (b >= 0) && (b < g.nb) && (k >= 0) && (k < g.nt);
-            const unsigned off = abase + (unsigned)k * nb4 + 4u * (unsigned)b;
+            const float U = fmaf(fkk[m], -cs.y, fmaf(fbb[m], ubs, Ur));
+            const float V = fmaf(fkk[m], cs.x, fmaf(fbb[m], vbs, Vr));
+            const bool ok = (U > sup_l0) && (U < sup_l1) && (V > sup_i0) && (V < sup_i1) && (kk < r.w) &&
+                            (bb < r.z) && ((unsigned)b < (unsigned)g.nb) && ((unsigned)k < (unsigned)g.nt);
+            const unsigned off = abase + __umul24((unsigned)k, nb4) + 4u * (unsigned)b;
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
                 float v = 0.f;
-                if (ok) v = ld_off(srcq[q], off);
+                if (ok) v = buffer_ld(srcq[q], off);
                 pre[m][q] = v;
             }
         }
-        // ray weights of the rectangle's bins: the first wave, one bin per lane
+        // ray weights of the rectangle's bins: one bin per lane (first wave)
         const int b = r.x + lane;
-        const bool bin_ok = (lane < r.z) && (b >= 0) && (b < g.nb);
+        const bool bin_ok = (lane < r.z) && ((unsigned)b < (unsigned)g.nb);
+        const unsigned zoff = 4u * (unsigned)(a * g.nb + b);
 #pragma unroll
         for (int q = 0; q < CG; ++q) {
             float z = bin_ok ? 1.f : 0.f;
-            if (weighted && bin_ok && wave == 0) z = ld_off(zq_base[q], 4u * (unsigned)(a * g.nb + b));
+            if (weighted && bin_ok) z = buffer_ld(zq[q], zoff);
             prez[q] = z;
         }
     };
@@ -184,11 +218,10 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
         __syncthreads();  // previous gather done with the LDS
         // ---- write the prefetched rectangle (CG candidates interleaved) and the ray weights
         {
-            const int npe = cur.z * cur.w;
 #pragma unroll
             for (int m = 0; m < ME; ++m) {
                 const int e = threadIdx.x + 256 * m;
-                if (e >= npe) break;
+                if (e >= PH) break;
                 float *dst = lds + e * CG;
                 if constexpr (CG == 8) {
                     reinterpret_cast<float4 *>(dst)[0] = make_float4(pre[m][0], pre[m][1], pre[m][2], pre[m][3]);
@@ -198,11 +231,10 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
                 } else if constexpr (CG == 2) {
                     reinterpret_cast<float2 *>(dst)[0] = make_float2(pre[m][0], pre[m][1]);
                 } else {
-#pragma unroll
-                    for (int q = 0; q < CG; ++q) dst[q] = pre[m][q];
+                    dst[0] = pre[m][0];
                 }
             }
-            if (wave == 0 && lane < cur.z) {
+            if (wave == 0 && lane < P) {
 #pragma unroll
                 for (int q = 0; q < CG; ++q) zl[lane * CG + q] = prez[q];
             }
@@ -221,13 +253,13 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
         const float2 cs = g.trig[a];
         const float c = cs.x, s = cs.y;
         const float ub = c * g.bscale, vb = s * g.bscale;
-        const float fbl = (float)r.x, fkl = (float)r.y, fwb = (float)r.z;
+        const float fbl = (float)r.x, fkl = (float)r.y, fP = (float)P;
         const float bmin = fbl + (float)HB, bmax = fbl + (float)(r.z - 1 - HB);
         const float kmin = fkl + 1.f, kmax = fkl + (float)(r.w - 2);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (!pv[j]) continue;
-            const float xc = xj[j] - g.cN, yc = yj[j] - g.cN;
+            const float xc = xcj[j], yc = ycj[j];
             const float Sj = fmaf(xc, c, yc * s) * inv_bscale + g.cB;
             const float Tj = fmaf(yc, c, -xc * s) + g.cT;
             // window centre (nearest sample), kept inside the staged rectangle
@@ -238,10 +270,10 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
             ray_base(g, (bcf - g.cB) * g.bscale, c, s, Ub, Vb);
             sample_uv(Ub, Vb, kcf - g.cT, c, s, U0, V0);
             const float du0 = U0 - xj[j], dv0 = V0 - yj[j];
-            const int row = (int)fmaf(kcf - fkl, fwb, bcf - fbl);  // exact small integers
+            const int row = (int)fmaf(kcf - fkl, fP, bcf - fbl);  // exact small integers
             const float *base = lds + row * CG;
             const float *zb = zl + (int)(bcf - fbl) * CG;
-            const int rstep = r.z * CG;
+            const int rstep = P * CG;
 #pragma unroll
             for (int db = -HB; db <= HB; ++db) {
                 const float dub = fmaf((float)db, ub, du0);

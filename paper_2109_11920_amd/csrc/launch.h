@@ -71,6 +71,7 @@ struct BackCfg {
     int tiles_x, tiles_y; // tiles per image
     size_t lds;
     const int4 *rects;    // [tiles][n_angles] footprint rectangles (b_lo, k_lo, wb, wk)
+    int xcd_remap;        // keep a candidate group's tiles on one XCD
 };
 
 struct BackArgs {

@@ -357,6 +357,9 @@ static bool back_cfg_ok(const BackCfg &b) {
     const bool cg = b.cg == 1 || b.cg == 2 || b.cg == 4 || (b.cg == 8 && b.tw == 16 && b.th == 16);
     if (!tile || !cg || b.lds > kLdsBudget) return false;
     if (b.wbmax > 64 || b.wkmax > back_stage_rows(b)) return false;
+    // the kernel's per-thread prefetch slots cover the fixed-pitch rectangle
+    const int slots = (b.hb > 1) ? 8 : (b.tw == 16 && b.th == 16) ? 4 : (b.tw == 32 && b.th == 16) ? 8 : 11;
+    if (b.wbmax * b.wkmax > 256 * slots) return false;
     if (b.hb > 1) return b.tw == 16 && b.th == 16 && b.cg == 1;
     return b.hb == 1;
 }
@@ -372,6 +375,7 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         t.tw = pf[0];
         t.th = pf[1];
         t.cg = pf[2];
+        t.xcd_remap = 1;
         back_fill(g, &t);
         if (!back_cfg_ok(t)) continue;
         *bc = t;
@@ -383,6 +387,7 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         t.tw = 16;
         t.th = 16;
         t.cg = 1;
+        t.xcd_remap = 1;
         back_fill(g, &t);
         *bc = t;
     }
@@ -392,6 +397,7 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         t.tw = it->second[0];
         t.th = it->second[1];
         t.cg = it->second[2];
+        t.xcd_remap = it->second.size() >= 4 ? (it->second[3] != 0) : 1;
         back_fill(g, &t);
         if (back_cfg_ok(t)) *bc = t;
     }
