@@ -9,7 +9,8 @@ this file by default):
     python -m paper_2109_11920_amd.autotune [--out PATH] [--workloads batch256_n128,grad64_n128,...]
 
 Keys follow the library: "ray:<n>x<na>x<nb>x<nt>:<C>:<image components>" -> [block, rays per thread]
-and "back:<n>x<na>x<nb>x<nt>:<C>:0" -> [tile width, tile height, candidates per workgroup, XCD remap].
+and "back:<n>x<na>x<nb>x<nt>:<C>:0" -> [tile width, tile height, candidates per workgroup, XCD remap,
+slid-block kernel]. A slid-block entry the geometry does not admit falls back to the library's default.
 """
 from __future__ import annotations
 
@@ -24,7 +25,9 @@ ROOT = os.path.dirname(HERE)
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 
 RAY_CONFIGS = [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4)]
-BACK_CONFIGS = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (16, 16, 8), (32, 16, 2), (32, 16, 4), (32, 32, 2)]
+# (tile width, tile height, candidates per workgroup, slid-block kernel)
+BACK_CONFIGS = [(16, 16, 1, 0), (16, 16, 2, 0), (16, 16, 4, 0), (16, 16, 8, 0), (32, 16, 2, 0), (32, 16, 4, 0),
+                (32, 32, 2, 0), (16, 16, 1, 1), (16, 16, 2, 1), (16, 16, 4, 1), (16, 16, 8, 1)]
 
 
 def key(kind, g, C, extra):
@@ -100,21 +103,22 @@ def tune_workload(name: str, cache: dict, log=print):
                     best = (t, [blk, rpt])
             cache[key("ray", g, C, 2)] = best[1]
         best = None
-        for tw, th, cg in BACK_CONFIGS:
+        for tw, th, cg, slid in BACK_CONFIGS:
             if cg > C:
                 continue
             e = dict(cache)
-            e[key("back", g, C, 0)] = [tw, th, cg]
+            e[key("back", g, C, 0)] = [tw, th, cg, 1, slid]
             t = _time(g, meas, cand, e, "back", K)
-            log(f"[tune] {name} {shape} back tile={tw}x{th} cg={cg}: {t * 1e3:.1f} us/launch")
+            log(f"[tune] {name} {shape} back tile={tw}x{th} cg={cg} slid={slid}: {t * 1e3:.1f} us/launch")
             if best is None or t < best[0]:
-                best = (t, [tw, th, cg])
+                best = (t, [tw, th, cg, 1, slid])
         for remap in (0, 1):
-            cfg = best[1][:3] + [remap]
+            cfg = best[1][:3] + [remap, best[1][4]]
             e = dict(cache)
             e[key("back", g, C, 0)] = cfg
             t = _time(g, meas, cand, e, "back", K)
-            log(f"[tune] {name} {shape} back tile={cfg[0]}x{cfg[1]} cg={cfg[2]} xcd_remap={remap}: {t * 1e3:.1f} us/launch")
+            log(f"[tune] {name} {shape} back tile={cfg[0]}x{cfg[1]} cg={cfg[2]} slid={cfg[4]} xcd_remap={remap}: "
+                f"{t * 1e3:.1f} us/launch")
             if t < best[0]:
                 best = (t, cfg)
         cache[key("back", g, C, 0)] = best[1]

@@ -64,7 +64,9 @@ struct Vec<8> {
     }
 };
 
-__device__ __forceinline__ float hat1(float x) { return fmaxf(1.f - fabsf(x), 0.f); }
+// hat(x) = max(0, 1 - |x|); since 1 - |x| <= 1 this equals clamp(1 - |x|, 0, 1), which is one VALU
+// instruction (subtract with the clamp bit).
+__device__ __forceinline__ float hat1(float x) { return __builtin_amdgcn_fmed3f(1.f - fabsf(x), 0.f, 1.f); }
 
 // Rows of the footprint rectangle a wave stages per angle (waves take rows wave, wave + 4, ...).
 template <int TW, int TH>
@@ -89,6 +91,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const float *p, un
 __device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
     // the b32 load yields the raw 32-bit word: reinterpret it, do not convert it
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+// Same with a uniform (scalar) byte offset added to the per-lane one.
+__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, uniform_off, 0));
 }
 
 template <int CG, int TW, int TH, int HB>
@@ -335,6 +341,245 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
     }
 }
 
+// ---------------------------------------------------------------------------------------------------
+// Slid-block variant (16 x 16 pixel tiles, one-bin half window, at least 32 bins and samples).
+//
+// The staged footprint is a fixed 32 x 32 block of (sample, bin) whose corner (b0, k0) the host slides
+// inside the sinogram so that it contains the tile's footprint rectangle clipped to the sinogram. Every
+// staged position is then a real sample: no range tests. Thread t stages bin column b0 + (t & 31) of
+// sample rows k0 + (t >> 5) + 8 m, m = 0..3, so its four slots share one per-lane byte offset and
+// differ by uniform row steps. The ray weight z_ab is folded in while staging, so LDS holds att * z
+// and every window tap is an immediate offset from one LDS address.
+//
+// A sample outside the union of the tile pixels' open supports is not loaded: it is gathered only
+// with weight hat() = 0, so its value need only be finite, and the lane keeps its register's previous
+// (finite, initially zero) contents.
+//
+// Window centres are clamped to [b0 + 1, b0 + 30] x [k0 + 1, k0 + 30]. Inside the sinogram this never
+// moves the centre of a pixel whose nearest sample is a real one (the host's rectangle has one sample
+// of margin beyond every window); at the sinogram's edges it moves the window only away from bins or
+// samples that do not exist, so every tap with a non-zero weight is still gathered.
+//
+// LDS layout: rows of kSlidPitch slots, each slot 4 candidates wide (one 16-byte read) or narrower;
+// 8 candidates use two such planes. A wave's 64 pixels are grouped 4 x 2 per 8 lanes, and the pitch
+// of 34 slots spreads the window taps of those 8 pixels over the LDS banks better than a pitch of 32
+// (which maps every row of a column to the same banks) or a 16 x 1 row of pixels.
+template <int CG>
+struct SlidLayout {
+    static constexpr int V = CG < 4 ? CG : 4;   // candidates per slot (per plane)
+    static constexpr int PLANES = CG / V;
+    static constexpr int PLANE = kSlidBlock * kSlidPitch * V;  // floats per plane
+};
+
+template <int CG, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArgs A, int mode) {
+    constexpr int P = kSlidBlock;
+    constexpr int PL = kSlidPitch;
+    constexpr int V = SlidLayout<CG>::V;
+    constexpr int PLANES = SlidLayout<CG>::PLANES;
+    constexpr int PLANE = SlidLayout<CG>::PLANE;
+    extern __shared__ float lds[];   // [PLANES][P sample rows][PL slots][V]
+    const int ntiles = T.tiles_x * T.tiles_y;
+    const int ngroups = (A.C + CG - 1) / CG;
+    const int total = ntiles * ngroups;
+    int id = blockIdx.x;
+    if (T.xcd_remap && (total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
+    const int grp = id / ntiles;
+    const int tile = id - grp * ntiles;
+    const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
+    const int l0 = tx * 16, i0 = ty * 16;
+    const int c0 = grp * CG;
+    const int ncg = min(CG, A.C - c0);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+
+    // this thread's pixel: each 8 lanes of a wave take a 4 x 2 block, a wave a 16 x 4 band
+    const int l = l0 + ((lane >> 3) & 3) * 4 + (lane & 3);
+    const int i = i0 + (tid >> 6) * 4 + (lane >> 5) * 2 + ((lane >> 2) & 1);
+    const bool pv = (l < g.n) && (i < g.n);
+    const float xc = (float)l - g.cN, yc = (float)i - g.cN;
+    const float cB5 = g.cB + 0.5f, cT5 = g.cT + 0.5f;
+    const float inv_bscale = 1.f / g.bscale;
+
+    // open support box of the tile's pixels, as half widths around the box centre (the host stores the
+    // staged corner sample's position relative to that centre)
+    const int l1 = min(l0 + 15, g.n - 1), i1 = min(i0 + 15, g.n - 1);
+    const float hu = 0.5f * (float)(l1 - l0) + 1.f + 1e-3f;
+    const float hv = 0.5f * (float)(i1 - i0) + 1.f + 1e-3f;
+
+    // staging slots: bin column bb, sample rows kk0 + 8 m
+    constexpr int ME = P * P / 256;
+    const int bb = tid & (P - 1), kk0 = tid >> 5;
+    const float fbb = (float)bb;
+    float fkk[ME];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) fkk[m] = (float)(kk0 + 8 * m);
+    const unsigned slot_off = 4u * (unsigned)(kk0 * g.nb + bb);
+    const unsigned row8 = 32u * (unsigned)g.nb;  // bytes of 8 sample rows
+    const unsigned a_stride = 4u * (unsigned)(g.nt * g.nb);
+    const unsigned cand_src = 4u * (unsigned)A.att_cs, cand_z = 4u * (unsigned)A.sino_cs;
+    const float *src = (mode == BACK_FIELD) ? A.z : A.att;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src + (size_t)c0 * A.att_cs, (unsigned)ncg * cand_src);
+    const __amdgpu_buffer_rsrc_t rz =
+        buffer_rsrc(WEIGHTED ? A.z + (size_t)c0 * A.sino_cs : src, WEIGHTED ? (unsigned)ncg * cand_z : 0u);
+    const int4 *rects = T.rects + (size_t)tile * g.na;
+    // uniform byte offset of each candidate slot's data; slots past the batch end re-read the last live
+    // candidate (in bounds, never written out), so no load needs a branch
+    unsigned qs[CG], qz[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
+        qz[q] = (unsigned)min(q, ncg - 1) * cand_z;
+    }
+
+    Comp acc[CG];
+    float blk[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        acc[q] = Comp{0.f, 0.f};
+        blk[q] = 0.f;
+    }
+
+    float pre[ME][CG], zv[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        zv[q] = 1.f;
+#pragma unroll
+        for (int m = 0; m < ME; ++m) pre[m][q] = 0.f;
+    }
+    auto prefetch = [&](int a, int4 r) {
+        const float2 cs = g.trig[a];
+        const float iu = fmaf(fbb, cs.x * g.bscale, __int_as_float(r.z));
+        const float iv = fmaf(fbb, cs.y * g.bscale, __int_as_float(r.w));
+        const unsigned sbase = (unsigned)a * a_stride + 4u * (unsigned)(r.y * g.nb + r.x);
+#pragma unroll
+        for (int m = 0; m < ME; ++m) {
+            const float U = fmaf(fkk[m], -cs.y, iu);
+            const float V = fmaf(fkk[m], cs.x, iv);
+            if (fabsf(U) < hu && fabsf(V) < hv) {
+#pragma unroll
+                for (int q = 0; q < CG; ++q) pre[m][q] = buffer_ld(rs, slot_off, sbase + (unsigned)m * row8 + qs[q]);
+            }
+        }
+        if constexpr (WEIGHTED) {
+            const unsigned zbase = 4u * (unsigned)(a * g.nb + r.x);
+#pragma unroll
+            for (int q = 0; q < CG; ++q) zv[q] = buffer_ld(rz, 4u * (unsigned)bb, zbase + qz[q]);
+        }
+    };
+
+    int4 cur = rects[0];
+    prefetch(0, cur);
+
+    for (int a = 0; a < g.na; ++a) {
+        __syncthreads();  // previous gather done with the LDS
+        {
+            float v[ME][CG];
+#pragma unroll
+            for (int m = 0; m < ME; ++m)
+#pragma unroll
+                for (int q = 0; q < CG; ++q) v[m][q] = WEIGHTED ? pre[m][q] * zv[q] : pre[m][q];
+#pragma unroll
+            for (int t = 0; t < ME; ++t) {
+                float *d = lds + ((kk0 + 8 * t) * PL + bb) * V;
+                if constexpr (CG == 8) {
+                    reinterpret_cast<float4 *>(d)[0] = make_float4(v[t][0], v[t][1], v[t][2], v[t][3]);
+                    reinterpret_cast<float4 *>(d + PLANE)[0] = make_float4(v[t][4], v[t][5], v[t][6], v[t][7]);
+                } else if constexpr (CG == 4) {
+                    reinterpret_cast<float4 *>(d)[0] = make_float4(v[t][0], v[t][1], v[t][2], v[t][3]);
+                } else if constexpr (CG == 2) {
+                    reinterpret_cast<float2 *>(d)[0] = make_float2(v[t][0], v[t][1]);
+                } else {
+                    d[0] = v[t][0];
+                }
+            }
+        }
+        __syncthreads();
+        const int4 r = cur;
+        if (a + 1 < g.na) {
+            cur = rects[a + 1];
+            prefetch(a + 1, cur);
+        }
+
+        // ---- gather
+        const float2 cs = g.trig[a];
+        const float c = cs.x, s = cs.y;
+        const float ub = c * g.bscale, vb = s * g.bscale;
+        const float fb1 = (float)(r.x + 1), fk1 = (float)(r.y + 1);
+        if (pv) {
+            // nearest sample (bin, sample index) of the pixel, clamped into the staged block
+            const float Sj5 = fmaf(xc, c * inv_bscale, fmaf(yc, s * inv_bscale, cB5));
+            const float Tj5 = fmaf(yc, c, fmaf(xc, -s, cT5));
+            const float bcf = __builtin_amdgcn_fmed3f(floorf(Sj5), fb1, fb1 + (float)(P - 3));
+            const float kcf = __builtin_amdgcn_fmed3f(floorf(Tj5), fk1, fk1 + (float)(P - 3));
+            // offset of that sample from the pixel: U - x = sigma c - tau s - xc, V - y = sigma s + tau c - yc
+            const float sig = (bcf - g.cB) * g.bscale, tau = kcf - g.cT;
+            const float du0 = fmaf(sig, c, fmaf(tau, -s, -xc));
+            const float dv0 = fmaf(sig, s, fmaf(tau, c, -yc));
+            const int corner = (int)(kcf - fk1) * PL + (int)(bcf - fb1);  // window tap (-1, -1)
+            const float *base = lds + corner * V;
+#pragma unroll
+            for (int db = -1; db <= 1; ++db) {
+                const float dub = (db == 0) ? du0 : (db < 0 ? du0 - ub : du0 + ub);
+                const float dvb = (db == 0) ? dv0 : (db < 0 ? dv0 - vb : dv0 + vb);
+#pragma unroll
+                for (int dk = -1; dk <= 1; ++dk) {
+                    const float du = (dk == 0) ? dub : (dk < 0 ? dub + s : dub - s);
+                    const float dv = (dk == 0) ? dvb : (dk < 0 ? dvb - c : dvb + c);
+                    const float w = hat1(du) * hat1(dv);
+#pragma unroll
+                    for (int h = 0; h < PLANES; ++h) {
+                        Vec<V> gv;
+                        gv.load(base + h * PLANE + ((dk + 1) * PL + (db + 1)) * V);
+#pragma unroll
+                        for (int q = 0; q < V; ++q) blk[h * V + q] = fmaf(w, gv.v[q], blk[h * V + q]);
+                    }
+                }
+            }
+        }
+        if ((a & 7) == 7 || a == g.na - 1) {
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                comp_add(acc[q], blk[q]);
+                blk[q] = 0.f;
+            }
+        }
+    }
+
+    if (!pv) return;
+    const size_t pix = (size_t)i * g.n + l;
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        if (q >= ncg) break;
+        const size_t o = (size_t)(c0 + q) * A.img_cs + pix;
+        const float v = comp_value(acc[q]);
+        if (mode == BACK_FIELD) {
+            A.out[o] = v;
+        } else if (mode == BACK_MLEM) {
+            const float b = g.dx * v;
+            const float sv = A.s[o];
+            const float Q = (sv > 0.f) ? b / sv : 0.f;
+            A.out[o] = A.F[o] * Q;
+            if (A.q_out) A.q_out[o] = Q;
+        } else if (mode == BACK_ADJ) {
+            A.out[o] = fmaf(g.dx, v, A.aux[o]);
+        } else {
+            A.out[o] = g.dx * v;
+        }
+    }
+}
+
+template <int CG>
+static hipError_t back_slid(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
+    const int ngroups = (a.C + CG - 1) / CG;
+    const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
+    if (mode == BACK_SENS || mode == BACK_FIELD)
+        hipLaunchKernelGGL((k_back_slid<CG, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    else
+        hipLaunchKernelGGL((k_back_slid<CG, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    return hipGetLastError();
+}
+
 template <int CG, int TW, int TH, int HB>
 static hipError_t back_go(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
@@ -352,6 +597,16 @@ static hipError_t back_tile(const DevGeom &g, const BackCfg &bc, const BackArgs 
 }
 
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
+    if (bc.slid) {
+        if (bc.tw != 16 || bc.th != 16 || bc.hb != 1) return hipErrorInvalidValue;
+        switch (bc.cg) {
+            case 1: return back_slid<1>(g, bc, a, mode, st);
+            case 2: return back_slid<2>(g, bc, a, mode, st);
+            case 4: return back_slid<4>(g, bc, a, mode, st);
+            case 8: return back_slid<8>(g, bc, a, mode, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (bc.hb == 1) {
         switch (bc.cg) {
             case 1: return back_tile<1, 1>(g, bc, a, mode, st);

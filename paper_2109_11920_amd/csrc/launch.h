@@ -72,7 +72,12 @@ struct BackCfg {
     size_t lds;
     const int4 *rects;    // [tiles][n_angles] footprint rectangles (b_lo, k_lo, wb, wk)
     int xcd_remap;        // keep a candidate group's tiles on one XCD
+    int slid;             // 16 x 16 tiles, one-bin half window: fixed 32 x 32 staging block slid inside
+                          // the sinogram; rects then hold (b0, k0, u0 bits, v0 bits)
 };
+
+constexpr int kSlidBlock = 32;  // staged bins and samples of the slid-block backprojection
+constexpr int kSlidPitch = 34;  // its LDS row pitch, in slots
 
 struct BackArgs {
     const float *att;     // [C][na][nt][nb]

@@ -212,7 +212,7 @@ static boac_status host_trig(int na, std::vector<float2> &h) {
 // window can reach a pixel of the tile, with one sample of margin on every side (the kernel's window
 // centres, computed in FP32, stay inside). Computed in double from the same FP32 angle table.
 static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
-    std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb};
+    std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb, bc->slid};
     auto it = ctx->rects.find(key);
     if (it != ctx->rects.end()) {
         bc->rects = it->second;
@@ -249,6 +249,23 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
             const int k_lo = (int)std::floor(Tmin + 0.5) - 2;
             const int k_hi = (int)std::floor(Tmax + 0.5) + 2;
             const int wb = b_hi - b_lo + 1, wk = k_hi - k_lo + 1;
+            if (bc->slid) {
+                // slide the fixed block inside the sinogram; it still holds the clipped rectangle
+                if (wb > kSlidBlock || wk > kSlidBlock)
+                    return fail(BOAC_EDEVICE, "internal: footprint %dx%d exceeds the %d-block", wb, wk, kSlidBlock);
+                const int b0 = std::min(std::max(b_lo, 0), g.n_bins - kSlidBlock);
+                const int k0 = std::min(std::max(k_lo, 0), g.n_samples - kSlidBlock);
+                // image position of sample (b0, k0), relative to the centre of the tile's support box
+                const double sig = ((double)b0 - cB) * ((double)g.n / (double)g.n_bins), tau = (double)k0 - cT;
+                const double u = sig * c - tau * s - 0.5 * (xl[0] + xl[1]);
+                const double v = sig * s + tau * c - 0.5 * (yi[0] + yi[1]);
+                float uf = (float)u, vf = (float)v;
+                int ub, vb;
+                std::memcpy(&ub, &uf, 4);
+                std::memcpy(&vb, &vf, 4);
+                h[(size_t)t * g.n_angles + a] = make_int4(b0, k0, ub, vb);
+                continue;
+            }
             const int slots = (bc->hb > 1) ? 8 : (bc->tw == 16 && bc->th == 16) ? 4 : (bc->tw == 32 && bc->th == 16) ? 8 : 11;
             if (wb > wb_cap || wk > wk_cap || wb * wk > 256 * slots)
                 return fail(BOAC_EDEVICE, "internal: footprint %dx%d exceeds the staged bound %dx%d", wb, wk, wb_cap,
@@ -342,7 +359,8 @@ static void back_fill(const boac_geom &g, BackCfg *bc) {
     bc->wkmax = (int)std::ceil(diag) + 8;
     bc->tiles_x = (g.n + bc->tw - 1) / bc->tw;
     bc->tiles_y = (g.n + bc->th - 1) / bc->th;
-    bc->lds = (size_t)bc->cg * (bc->wbmax * bc->wkmax + bc->wbmax) * sizeof(float);
+    bc->lds = bc->slid ? (size_t)bc->cg * kSlidBlock * kSlidPitch * sizeof(float)
+                       : (size_t)bc->cg * (bc->wbmax * bc->wkmax + bc->wbmax) * sizeof(float);
 }
 
 // rows of the footprint rectangle the back kernel can stage per angle (4 waves x rows per wave)
@@ -353,6 +371,7 @@ static int back_stage_rows(const BackCfg &b) {
 }
 
 static bool back_cfg_ok(const BackCfg &b) {
+    if (b.slid) return false;  // checked by slid_ok, which needs the geometry
     const bool tile = (b.tw == 16 && b.th == 16) || (b.tw == 32 && b.th == 16) || (b.tw == 32 && b.th == 32);
     const bool cg = b.cg == 1 || b.cg == 2 || b.cg == 4 || (b.cg == 8 && b.tw == 16 && b.th == 16);
     if (!tile || !cg || b.lds > kLdsBudget) return false;
@@ -364,22 +383,42 @@ static bool back_cfg_ok(const BackCfg &b) {
     return b.hb == 1;
 }
 
+// The slid-block kernel: 16 x 16 tiles, one-bin half window, a footprint within the 32 x 32 block, a
+// sinogram at least one block wide and tall, and 32-bit buffer offsets that cannot wrap (the kernel's
+// largest offset is below 2 cg bytes-per-candidate).
+static bool slid_ok(const boac_geom &g, const BackCfg &b) {
+    if (b.slid != 1 || b.tw != 16 || b.th != 16 || b.hb != 1) return false;
+    if (!(b.cg == 1 || b.cg == 2 || b.cg == 4 || b.cg == 8) || b.lds > kLdsBudget) return false;
+    if (b.wbmax > kSlidBlock || b.wkmax > kSlidBlock) return false;
+    if (g.n_bins < kSlidBlock || g.n_samples < kSlidBlock) return false;
+    const double att_bytes = 4.0 * g.n_angles * g.n_samples * g.n_bins;
+    return 2.0 * b.cg * att_bytes < 4294967296.0;
+}
+
+static bool plan_ok(const boac_geom &g, const BackCfg &b) { return b.slid ? slid_ok(g, b) : back_cfg_ok(b); }
+
 static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
-    // preference order: big tiles and many candidates per workgroup amortise the footprint staging
-    // and the window weights; fall back while the grid would not fill the GPU twice over
-    static const int prefs[][3] = {{16, 16, 8}, {16, 16, 4}, {16, 16, 2}, {16, 16, 1}};
+    // preference order: the slid-block kernel where it applies, then the general one; big candidate
+    // groups amortise the footprint staging and the window weights, and the choice falls back while
+    // the grid would not fill the GPU twice over
+    static const int prefs[][4] = {{16, 16, 8, 1}, {16, 16, 4, 1}, {16, 16, 2, 1}, {16, 16, 1, 1},
+                                   {16, 16, 8, 0}, {16, 16, 4, 0}, {16, 16, 2, 0}, {16, 16, 1, 0}};
     const long target = 2L * ctx->n_cu;
     bool set = false;
+    int slid_seen = -1;
     for (const auto &pf : prefs) {
+        if (set && pf[3] != slid_seen) break;  // stay within the first kernel family that applies
         BackCfg t{};
         t.tw = pf[0];
         t.th = pf[1];
         t.cg = pf[2];
+        t.slid = pf[3];
         t.xcd_remap = 1;
         back_fill(g, &t);
-        if (!back_cfg_ok(t)) continue;
+        if (!plan_ok(g, t)) continue;
         *bc = t;
         set = true;
+        slid_seen = t.slid;
         if (C >= t.cg && (long)t.tiles_x * t.tiles_y * ((C + t.cg - 1) / t.cg) >= target) break;
     }
     if (!set || bin_half_window(g) > 1) {
@@ -391,6 +430,7 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         back_fill(g, &t);
         *bc = t;
     }
+    // plan cache entry: [tile width, tile height, candidates per workgroup, XCD remap, slid block]
     auto it = ctx->tune.find(shape_key("back", g, C, 0));
     if (it != ctx->tune.end() && it->second.size() >= 3) {
         BackCfg t{};
@@ -398,8 +438,9 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         t.th = it->second[1];
         t.cg = it->second[2];
         t.xcd_remap = it->second.size() >= 4 ? (it->second[3] != 0) : 1;
+        t.slid = it->second.size() >= 5 ? (it->second[4] != 0) : 0;
         back_fill(g, &t);
-        if (back_cfg_ok(t)) *bc = t;
+        if (plan_ok(g, t)) *bc = t;
     }
 }
 
