@@ -23,7 +23,23 @@ struct DevGeom {
     float cT;       // (nt-1)/2
     float bscale;   // n / nb: bin spacing in pixels
     const float2 *trig;  // [na] (cos phi_a, sin phi_a)
+    int nb8;        // attenuation layout: 8-bin blocks per block row, ceil(nb / 8)
+    int slab;       // attenuation layout: elements per angle, 4 ceil(nt / 4) x 8 nb8
 };
+
+// Attenuation-tensor layout. Per candidate, na slabs (one per angle) of the samples (k, b); a slab is
+// tiled in 4 x 8 blocks (4 consecutive samples of 8 consecutive bins, one 128-byte line), blocks
+// running bin-block fastest, and within a block sample-row major. Element (a, k, b) is at
+// a slab + att_row(k) + att_col(b). A ray's samples keep a fixed bin part (att_col) and a row part
+// (att_row) that depends on k only; a pixel tile's footprint in the slab covers about half as many
+// partly used lines as in a row-major slab.
+__device__ __forceinline__ unsigned att_col(int b) { return (unsigned)(((b >> 3) << 5) + (b & 7)); }
+__device__ __forceinline__ unsigned att_row(const DevGeom &g, int k) {
+    return (unsigned)((k >> 2) * (g.nb8 << 5) + ((k & 3) << 3));
+}
+__device__ __forceinline__ size_t att_base(const DevGeom &g, int a, int b) {
+    return (size_t)a * (size_t)g.slab + att_col(b);
+}
 
 // Row band of an image staged in LDS: samples whose clamped row floor lies in [alo, ahi) use it;
 // rows alo..ahi (inclusive) are staged, columns -1..n+1, zero outside the image.
@@ -252,15 +268,35 @@ __device__ __forceinline__ void band_k_range(const DevGeom &g, const Band &band,
 }
 
 // Bilinear read at (U, V) from a whole-image stage (rows -1..n+1, columns -1..n+1, pitch n+3):
-// the clamp to [-1, n] keeps every tap inside the zero border.
+// the clamp to [-1, n] keeps every tap inside the zero border. The tap's index floor(V) pitch +
+// floor(U) is formed in float (exact: small integers) and converted once, which is cheaper than an
+// integer multiply.
 __device__ __forceinline__ float bilinear_whole(const float *lds, float U, float V, float nf, int pitch) {
     const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
     const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
     const float fu = __builtin_amdgcn_fractf(Uc);
     const float fv = __builtin_amdgcn_fractf(Vc);
-    const int l0 = __float2int_rd(Uc);
-    const int i0 = __float2int_rd(Vc);
-    return lerp2(lds + (i0 + 1) * pitch + (l0 + 1), pitch, fu, fv);
+    const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
+    return lerp2(lds + idx + (pitch + 1), pitch, fu, fv);
+}
+
+// Raw buffer resource over `bytes` bytes at p (gfx9 descriptor word 3): loads take a 32-bit byte offset
+// from the uniform base. Every load below is predicated to in-range offsets; elements that must read
+// as zero are zeroed in registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const float *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    // the b32 load yields the raw 32-bit word: reinterpret it, do not convert it
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+// Same with a uniform (scalar) byte offset added to the per-lane one.
+__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, uniform_off, 0));
+}
+// Vector store of one float at a per-lane plus a uniform byte offset.
+__device__ __forceinline__ void buffer_st(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, uniform_off, 0);
 }
 
 // hat(x) = max(0, 1 - |x|)

@@ -82,21 +82,6 @@ struct StageSlots {
     static constexpr int value = (HB > 1) ? 8 : (TW == 16 && TH == 16) ? 4 : (TW == 32 && TH == 16) ? 8 : 11;
 };
 
-// Raw buffer resource over `bytes` bytes at p (gfx9 descriptor word 3): loads take a 32-bit byte offset
-// from the uniform base. Every load below is predicated to in-range offsets; elements that must read
-// as zero are zeroed in registers.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const float *p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
-    // the b32 load yields the raw 32-bit word: reinterpret it, do not convert it
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
-}
-// Same with a uniform (scalar) byte offset added to the per-lane one.
-__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, uniform_off, 0));
-}
-
 template <int CG, int TW, int TH, int HB>
 __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int PPT = (TW * TH) / 256;
@@ -155,8 +140,7 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
             blk[j][q] = 0.f;
         }
 
-    const unsigned nb4 = 4u * (unsigned)g.nb;
-    const unsigned a_stride4 = 4u * (unsigned)(g.nt * g.nb);
+    const unsigned a_stride4 = 4u * (unsigned)g.slab;
     // The footprint rectangle is staged with a fixed pitch P = wbmax (height wkmax), so each thread's
     // prefetch slots e = tid + 256 m have fixed rectangle coordinates (kk, bb) for the whole tile.
     const int P = T.wbmax;
@@ -197,7 +181,7 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
             const float V = fmaf(fkk[m], cs.x, fmaf(fbb[m], vbs, Vr));
             const bool ok = (U > sup_l0) && (U < sup_l1) && (V > sup_i0) && (V < sup_i1) && (kk < r.w) &&
                             (bb < r.z) && ((unsigned)b < (unsigned)g.nb) && ((unsigned)k < (unsigned)g.nt);
-            const unsigned off = abase + __umul24((unsigned)k, nb4) + 4u * (unsigned)b;
+            const unsigned off = abase + 4u * (att_row(g, k) + att_col(b));
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
                 float v = 0.f;
@@ -414,9 +398,8 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
     float fkk[ME];
 #pragma unroll
     for (int m = 0; m < ME; ++m) fkk[m] = (float)(kk0 + 8 * m);
-    const unsigned slot_off = 4u * (unsigned)(kk0 * g.nb + bb);
-    const unsigned row8 = 32u * (unsigned)g.nb;  // bytes of 8 sample rows
-    const unsigned a_stride = 4u * (unsigned)(g.nt * g.nb);
+    const unsigned row8 = 4u * (unsigned)(g.nb8 << 6);  // bytes of 8 sample rows (2 block rows)
+    const unsigned a_stride = 4u * (unsigned)g.slab;
     const unsigned cand_src = 4u * (unsigned)A.att_cs, cand_z = 4u * (unsigned)A.sino_cs;
     const float *src = (mode == BACK_FIELD) ? A.z : A.att;
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src + (size_t)c0 * A.att_cs, (unsigned)ncg * cand_src);
@@ -451,7 +434,10 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
         const float2 cs = g.trig[a];
         const float iu = fmaf(fbb, cs.x * g.bscale, __int_as_float(r.z));
         const float iv = fmaf(fbb, cs.y * g.bscale, __int_as_float(r.w));
-        const unsigned sbase = (unsigned)a * a_stride + 4u * (unsigned)(r.y * g.nb + r.x);
+        // this thread's samples (r.y + kk0 + 8 m, r.x + bb): a per-lane offset for m = 0, and uniform
+        // steps of two block rows for m > 0
+        const unsigned sbase = (unsigned)a * a_stride;
+        const unsigned slot_off = 4u * (att_row(g, r.y + kk0) + att_col(r.x + bb));
 #pragma unroll
         for (int m = 0; m < ME; ++m) {
             const float U = fmaf(fkk[m], -cs.y, iu);

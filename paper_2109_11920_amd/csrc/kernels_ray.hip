@@ -29,7 +29,7 @@ constexpr int kMaxRpt = 4;
 
 // ------------------------------------------------------------------ attenuation
 template <bool SINGLE>
-__global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
+__global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
                                              const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
                                              size_t att_cs) {
     extern __shared__ float lds[];
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, in
             const float2 cs = g.trig[a];
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
-            float *col = out + (size_t)a * g.nt * g.nb + b;
+            float *col = out + att_base(g, a, b);
             if constexpr (SINGLE) {
                 // single pass from the detector end: running suffix sum T = sum_{k'>k} m_k'
                 Comp T{0.f, 0.f};
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, in
                     const Tap t = make_tap<true>(U, V, nf, pitch, band);
                     const float m = lerp2(lds + t.off, pitch, t.fu, t.fv);
                     const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                    col[(size_t)k * g.nb] = expf(-L);
+                    col[att_row(g, k)] = expf(-L);
                     comp_add(T, m);
                 }
             } else {
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, in
                     sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
                     const Tap t = make_tap<false>(U, V, nf, pitch, band);
                     if (!t.mine) continue;
-                    col[(size_t)k * g.nb] = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                    col[att_row(g, k)] = lerp2(lds + t.off, pitch, t.fu, t.fv);
                 }
             }
         }
@@ -90,12 +90,12 @@ __global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, in
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            float *col = out + (size_t)a * g.nt * g.nb + b;
+            float *col = out + att_base(g, a, b);
             Comp T{0.f, 0.f};
             for (int k = g.nt - 1; k >= 0; --k) {
-                const float m = col[(size_t)k * g.nb];
+                const float m = col[att_row(g, k)];
                 const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                col[(size_t)k * g.nb] = expf(-L);
+                col[att_row(g, k)] = expf(-L);
                 comp_add(T, m);
             }
         }
@@ -104,9 +104,9 @@ __global__ __launch_bounds__(512) void k_att(DevGeom g, Bands bands, int rpt, in
 
 // ------------------------------------------------------------------ forward projection
 template <int MODE, bool SINGLE>
-__global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+__global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
     extern __shared__ float lds[];
-    __shared__ float red[16];
+    __shared__ float red[32];  // two floats per wave, up to 16 waves
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
     const int nrays = g.na * g.nb;
@@ -136,31 +136,37 @@ __global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, in
             const float2 cs = g.trig[a];
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
-            const float *col = att + (size_t)a * g.nt * g.nb + b;
+            const float *col = att + att_base(g, a, b);
             Comp c = acc[j];
             if constexpr (SINGLE) {
                 // att is streamed 16 samples ahead of use: the loads of chunk k0 + 16 are in flight
-                // while chunk k0 is computed
+                // while chunk k0 is computed. The loads go through a buffer resource: a per-lane ray
+                // offset plus a uniform offset of the sample row. Each chunk is summed with FMAs and
+                // added to the compensated total.
                 constexpr int KC = 16;
+                const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)att_base(g, a, b);
                 float cur[KC], nxt[KC];
 #pragma unroll
-                for (int q = 0; q < KC; ++q) cur[q] = (q < g.nt) ? col[(size_t)q * g.nb] : 0.f;
+                for (int q = 0; q < KC; ++q) cur[q] = (q < g.nt) ? buffer_ld(rs, roff, 4u * att_row(g, q)) : 0.f;
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + KC + q;
-                        nxt[q] = (k < g.nt) ? col[(size_t)k * g.nb] : 0.f;
+                        nxt[q] = (k < g.nt) ? buffer_ld(rs, roff, 4u * att_row(g, k)) : 0.f;
                     }
+                    float part = 0.f;
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         if (k0 + q < g.nt) {
                             float U, V;
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
-                            kahan_add(c, cur[q] * bilinear_whole(lds, U, V, nf, pitch));
+                            part = fmaf(cur[q], bilinear_whole(lds, U, V, nf, pitch), part);
                         }
                         tau += 1.f;
                     }
+                    kahan_add(c, part);
 #pragma unroll
                     for (int q = 0; q < KC; ++q) cur[q] = nxt[q];
                 }
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, in
                     const Tap t = make_tap<false>(U, V, nf, pitch, band);
                     if (!t.mine) continue;
                     const float v = lerp2(lds + t.off, pitch, t.fu, t.fv);
-                    kahan_add(c, col[(size_t)k * g.nb] * v);
+                    kahan_add(c, col[att_row(g, k)] * v);
                 }
             }
             acc[j] = c;
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(512) void k_fwd(DevGeom g, Bands bands, int rpt, in
 // The ybar^{n+1} term is the y^{n+1} = A F^{n+1} adjoint left pending by the previous step (or the
 // objective's adjoint for the first step), so each step sweeps the rays once.
 template <bool SINGLE>
-__global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
+__global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
@@ -264,26 +270,33 @@ __global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int r
             const size_t si = cand * A.sino_cs + ray;
             const float rr = g.dx * A.r[si];
             const float yp = g.dx * A.ybar_in[si];
-            const size_t col0 = (size_t)a * g.nt * g.nb + b;
+            const size_t col0 = att_base(g, a, b);
             const float *cat = att + col0;
             float *cab = ab + col0;
             Comp c = acc[j];
             if constexpr (SINGLE) {
+                // as in the forward projection: att and att_bar streamed 16 samples ahead through
+                // buffer resources (per-lane ray offset + uniform sample-row offset), chunked
+                // compensated sum, tap index formed in float
                 constexpr int KC = 16;
+                const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+                const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)col0;
                 float at[KC], an[KC], bt[KC], bn[KC];
 #pragma unroll
                 for (int q = 0; q < KC; ++q) {
-                    at[q] = (q < g.nt) ? cat[(size_t)q * g.nb] : 0.f;
-                    bt[q] = (A.accumulate && q < g.nt) ? cab[(size_t)q * g.nb] : 0.f;
+                    at[q] = (q < g.nt) ? buffer_ld(ra, roff, 4u * att_row(g, q)) : 0.f;
+                    bt[q] = (A.accumulate && q < g.nt) ? buffer_ld(rb, roff, 4u * att_row(g, q)) : 0.f;
                 }
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + KC + q;
-                        an[q] = (k < g.nt) ? cat[(size_t)k * g.nb] : 0.f;
-                        bn[q] = (A.accumulate && k < g.nt) ? cab[(size_t)k * g.nb] : 0.f;
+                        an[q] = (k < g.nt) ? buffer_ld(ra, roff, 4u * att_row(g, k)) : 0.f;
+                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld(rb, roff, 4u * att_row(g, k)) : 0.f;
                     }
+                    float part = 0.f;
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + q;
@@ -292,14 +305,15 @@ __global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int r
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
                             const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
                             const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
-                            const int l0 = __float2int_rd(Uc), i0 = __float2int_rd(Vc);
-                            const float2 w = lerp2x2(lds2 + (i0 + 1) * pitch + (l0 + 1), pitch,
-                                                     __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
-                            kahan_add(c, at[q] * w.x);
-                            cab[(size_t)k * g.nb] = bt[q] + fmaf(rr, w.x, yp * w.y);
+                            const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
+                            const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
+                                                     __builtin_amdgcn_fractf(Vc));
+                            part = fmaf(at[q], w.x, part);
+                            buffer_st(rb, roff, 4u * att_row(g, k), bt[q] + fmaf(rr, w.x, yp * w.y));
                         }
                         tau += 1.f;
                     }
+                    kahan_add(c, part);
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         at[q] = an[q];
@@ -315,8 +329,8 @@ __global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int r
                     const Tap t = make_tap<false>(U, V, nf, pitch, band);
                     if (!t.mine) continue;
                     const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                    kahan_add(c, cat[(size_t)k * g.nb] * w.x);
-                    float *p = cab + (size_t)k * g.nb;
+                    kahan_add(c, cat[att_row(g, k)] * w.x);
+                    float *p = cab + att_row(g, k);
                     const float add = fmaf(rr, w.x, yp * w.y);
                     *p = A.accumulate ? (*p + add) : add;
                 }
@@ -342,7 +356,7 @@ __global__ __launch_bounds__(512) void k_adj_sweep(DevGeom g, Bands bands, int r
 // L_bar = -att * att_bar and m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k') (the scan's transpose),
 // written in place of att_bar.
 template <bool SINGLE>
-__global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
+__global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
@@ -369,7 +383,7 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
             const float rho = A.rho[cand * A.sino_cs + ray];
-            const size_t off = (size_t)a * g.nt * g.nb + b;
+            const size_t off = att_base(g, a, b);
             const float *cat = att + off;
             float *cab = ab + off;
             if constexpr (SINGLE) {
@@ -377,8 +391,8 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
                 float at[KC], an[KC], bt[KC], bn[KC];
 #pragma unroll
                 for (int q = 0; q < KC; ++q) {
-                    at[q] = (q < g.nt) ? cat[(size_t)q * g.nb] : 0.f;
-                    bt[q] = (A.accumulate && q < g.nt) ? cab[(size_t)q * g.nb] : 0.f;
+                    at[q] = (q < g.nt) ? cat[att_row(g, q)] : 0.f;
+                    bt[q] = (A.accumulate && q < g.nt) ? cab[att_row(g, q)] : 0.f;
                 }
                 Comp P{0.f, 0.f};
                 float tau = -g.cT;
@@ -386,8 +400,8 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + KC + q;
-                        an[q] = (k < g.nt) ? cat[(size_t)k * g.nb] : 0.f;
-                        bn[q] = (A.accumulate && k < g.nt) ? cab[(size_t)k * g.nb] : 0.f;
+                        an[q] = (k < g.nt) ? cat[att_row(g, k)] : 0.f;
+                        bn[q] = (A.accumulate && k < g.nt) ? cab[att_row(g, k)] : 0.f;
                     }
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
@@ -402,7 +416,7 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
                                                      __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
                             const float abar = bt[q] + g.dx * fmaf(rho, w.y, w.x);
                             const float Lbar = -at[q] * abar;
-                            cab[(size_t)k * g.nb] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                            cab[att_row(g, k)] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
                             comp_add(P, Lbar);
                         }
                         tau += 1.f;
@@ -423,7 +437,7 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
                     const Tap t = make_tap<false>(U, V, nf, pitch, band);
                     if (!t.mine) continue;
                     const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                    float *p = cab + (size_t)k * g.nb;
+                    float *p = cab + att_row(g, k);
                     const float add = g.dx * fmaf(rho, w.y, w.x);
                     *p = A.accumulate ? (*p + add) : add;
                 }
@@ -438,10 +452,10 @@ __global__ __launch_bounds__(512) void k_tail(DevGeom g, Bands bands, int rpt, i
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            const size_t off = (size_t)a * g.nt * g.nb + b;
+            const size_t off = att_base(g, a, b);
             Comp P{0.f, 0.f};
             for (int k = 0; k < g.nt; ++k) {
-                const size_t idx = off + (size_t)k * g.nb;
+                const size_t idx = off + att_row(g, k);
                 const float Lbar = -att[idx] * ab[idx];
                 ab[idx] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
                 comp_add(P, Lbar);

@@ -47,6 +47,11 @@ static boac_status fail(boac_status st, const char *fmt, ...) {
 // ------------------------------------------------------------------ validation (no HIP calls)
 static constexpr size_t kLdsBudget = 160 * 1024 - 256;  // gfx950: 160 KiB of LDS per workgroup
 
+// Elements per angle of an attenuation tensor stored in 4 x 8 (sample x bin) blocks.
+static size_t att_slab(const boac_geom &g) {
+    return (size_t)((g.n_samples + 3) / 4 * 4) * (size_t)((g.n_bins + 7) / 8 * 8);
+}
+
 static int bin_half_window(const boac_geom &g) {
     const double rho = (double)g.n_bins / (double)g.n;
     return (int)std::ceil(std::sqrt(2.0) * rho - 0.5);
@@ -62,7 +67,7 @@ static boac_status check_geom(const boac_geom *g) {
         return fail(BOAC_ESHAPE, "n_samples = %d outside [2, 1024]", g->n_samples);
     if (!(g->pixel_cm > 0.f) || !std::isfinite(g->pixel_cm))
         return fail(BOAC_ESHAPE, "pixel_cm = %g must be positive and finite", (double)g->pixel_cm);
-    if ((double)g->n_angles * g->n_bins * g->n_samples * 4.0 >= 4294967296.0)
+    if ((double)g->n_angles * att_slab(*g) * 4.0 >= 4294967296.0)
         return fail(BOAC_ESHAPE, "n_angles * n_bins * n_samples = %.0f samples: above 2^30 per candidate",
                     (double)g->n_angles * g->n_bins * g->n_samples);
     const int hb = bin_half_window(*g);
@@ -291,6 +296,8 @@ static boac_status dev_geom(boac_ctx *ctx, const boac_geom &g, DevGeom *dg) {
     dg->cB = 0.5f * (float)(g.n_bins - 1);
     dg->cT = 0.5f * (float)(g.n_samples - 1);
     dg->bscale = (float)g.n / (float)g.n_bins;
+    dg->nb8 = (g.n_bins + 7) / 8;
+    dg->slab = (int)att_slab(g);
     return trig_table(ctx, g.n_angles, &dg->trig);
 }
 
@@ -342,7 +349,7 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
     auto it = ctx->tune.find(shape_key("ray", g, C, comps));
     if (it != ctx->tune.end() && it->second.size() >= 2) {
         const int blk = it->second[0], rpt = it->second[1];
-        if ((blk == 64 || blk == 128 || blk == 256 || blk == 512) && rpt >= 1 && rpt <= 4) {
+        if ((blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024) && rpt >= 1 && rpt <= 4) {
             rc->block = blk;
             rc->rpt = rpt;
         }
@@ -391,7 +398,7 @@ static bool slid_ok(const boac_geom &g, const BackCfg &b) {
     if (!(b.cg == 1 || b.cg == 2 || b.cg == 4 || b.cg == 8) || b.lds > kLdsBudget) return false;
     if (b.wbmax > kSlidBlock || b.wkmax > kSlidBlock) return false;
     if (g.n_bins < kSlidBlock || g.n_samples < kSlidBlock) return false;
-    const double att_bytes = 4.0 * g.n_angles * g.n_samples * g.n_bins;
+    const double att_bytes = 4.0 * g.n_angles * (double)att_slab(g);
     return 2.0 * b.cg * att_bytes < 4294967296.0;
 }
 
@@ -498,10 +505,12 @@ static boac_status drain_timings(boac_ctx *ctx) {
 
 // ------------------------------------------------------------------ evaluation pipeline
 struct Sizes {
-    size_t I, Y, V;  // elements per candidate: image, sinogram, attenuation tensor
+    size_t I, Y, V;  // elements per candidate: image, sinogram, attenuation tensor (algorithmic)
+    size_t VS;       // attenuation tensor stride per candidate (4 x 8-block slabs, padded)
 };
 static Sizes sizes_of(const boac_geom &g) {
-    return Sizes{(size_t)g.n * g.n, (size_t)g.n_angles * g.n_bins, (size_t)g.n_angles * g.n_bins * g.n_samples};
+    return Sizes{(size_t)g.n * g.n, (size_t)g.n_angles * g.n_bins, (size_t)g.n_angles * g.n_bins * g.n_samples,
+                 (size_t)g.n_angles * att_slab(g)};
 }
 
 // Bytes models (algorithmic HBM traffic per launch) used by the instrumentation.
@@ -519,7 +528,7 @@ static double bytes_back(const Sizes &z, int C, int mode) {
 static boac_status run_att(boac_ctx *ctx, const DevGeom &dg, const Plan &p, const Sizes &z, const float *mu,
                            float *att, int C, hipStream_t st) {
     return timed(ctx, BOAC_K_ATT, bytes_att(z, C), st,
-                 [&] { return launch_att(dg, p.ray1, p.bands1, mu, att, z.I, z.V, C, st); });
+                 [&] { return launch_att(dg, p.ray1, p.bands1, mu, att, z.I, z.VS, C, st); });
 }
 
 static boac_status run_fwd(boac_ctx *ctx, int mode, const DevGeom &dg, const Plan &p, const Sizes &z,
@@ -539,7 +548,7 @@ static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, cons
     a.att = att;
     a.img = img;
     a.meas = meas;
-    a.att_cs = z.V;
+    a.att_cs = z.VS;
     a.img_cs = z.I;
     a.sino_cs = z.Y;
     a.img_comps = 1;
@@ -550,7 +559,7 @@ static BackArgs back_args(const Sizes &z, const float *att, const float *zz, flo
     a.att = att;
     a.z = zz;
     a.out = out;
-    a.att_cs = z.V;
+    a.att_cs = z.VS;
     a.sino_cs = z.Y;
     a.img_cs = z.I;
     a.C = C;
@@ -560,7 +569,7 @@ static BackArgs back_args(const Sizes &z, const float *att, const float *zz, flo
 // Maximum candidates whose attenuation tensors are resident at once (device scratch bound).
 static int cand_chunk(const Sizes &z, int C, int tensors) {
     const double budget = 48.0 * (1ull << 30);  // of 288 GB HBM
-    const double per = 4.0 * (double)z.V * tensors + 64.0 * (double)z.I;
+    const double per = 4.0 * (double)z.VS * tensors + 64.0 * (double)z.I;
     int m = (int)std::max(1.0, std::floor(budget / per));
     return std::min(m, C);
 }
@@ -578,7 +587,7 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     float2 *partial, *lg;
     uint32_t *flag, *st_int;
     BOAC_TRY(ensure_t(ctx, "mu", (size_t)Cc * z.I, &mu));
-    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.V, &att));
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.VS, &att));
     BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * z.I, &s));
     BOAC_TRY(ensure_t(ctx, "F0", (size_t)Cc * z.I, &F0));
     BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &F1));
@@ -647,8 +656,8 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     // records: F, y, r, Q per record; ckpt slots nck, segment slots ck
     float *recF, *recY, *recR, *recQ, *segF, *segY, *segR, *segQ;
     BOAC_TRY(ensure_t(ctx, "mu", (size_t)Cc * I, &mu));
-    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.V, &att));
-    BOAC_TRY(ensure_t(ctx, "attbar", (size_t)Cc * z.V, &attbar));
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)Cc * z.VS, &att));
+    BOAC_TRY(ensure_t(ctx, "attbar", (size_t)Cc * z.VS, &attbar));
     BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * I, &s));
     BOAC_TRY(ensure_t(ctx, "sbar", (size_t)Cc * I, &sbar));
     BOAC_TRY(ensure_t(ctx, "fbar", (size_t)Cc * I, &fbar));
@@ -789,7 +798,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
                 sa.y = sY[j];
                 sa.ybar_in = ypend;
                 sa.ybar_out = ynext;
-                sa.att_cs = z.V;
+                sa.att_cs = z.VS;
                 sa.img_cs = 2 * I;
                 sa.sino_cs = Y;
                 sa.accumulate = first ? 0 : 1;
@@ -813,7 +822,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
             ta.attbar = attbar;
             ta.pair = (const float *)pair;
             ta.rho = ypend;
-            ta.att_cs = z.V;
+            ta.att_cs = z.VS;
             ta.img_cs = 2 * I;
             ta.sino_cs = Y;
             ta.accumulate = first ? 0 : 1;
@@ -948,7 +957,7 @@ static boac_status build_att(boac_ctx *ctx, const boac_geom &g, const DevGeom &d
                              int n, float **att_out, hipStream_t st) {
     const Sizes z = sizes_of(g);
     float *att;
-    BOAC_TRY(ensure_t(ctx, "att", (size_t)n * z.V, &att));
+    BOAC_TRY(ensure_t(ctx, "att", (size_t)n * z.VS, &att));
     BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
     *att_out = att;
     return BOAC_OK;
