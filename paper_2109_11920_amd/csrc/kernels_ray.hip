@@ -26,6 +26,7 @@ __device__ __forceinline__ void ray_block(int chunks, int C, int &cand, int &chu
 }
 
 constexpr int kMaxRpt = 4;
+constexpr int kBandChunk = 16;  // samples per load batch in the row-band paths
 
 // ------------------------------------------------------------------ attenuation
 template <bool SINGLE>
@@ -90,13 +91,25 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            float *col = out + att_base(g, a, b);
+            // 16 samples at a time from the detector end: the chunk's loads precede its stores
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(out, (unsigned)(4 * att_cs));
+            const unsigned roff = 4u * (unsigned)att_base(g, a, b);
             Comp T{0.f, 0.f};
-            for (int k = g.nt - 1; k >= 0; --k) {
-                const float m = col[att_row(g, k)];
-                const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                col[att_row(g, k)] = expf(-L);
-                comp_add(T, m);
+            for (int kc = g.nt - 1; kc >= 0; kc -= kBandChunk) {
+                float mv[kBandChunk];
+#pragma unroll
+                for (int q = 0; q < kBandChunk; ++q) {
+                    const int k = kc - q;
+                    mv[q] = (k >= 0) ? buffer_ld(rs, roff + 4u * att_row(g, k)) : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < kBandChunk; ++q) {
+                    const int k = kc - q;
+                    if (k < 0) break;
+                    const float L = g.dx * (fmaf(0.5f, mv[q], T.s) + T.e);
+                    buffer_st(rs, roff + 4u * att_row(g, k), 0u, expf(-L));
+                    comp_add(T, mv[q]);
+                }
             }
         }
     }
@@ -171,16 +184,30 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                     for (int q = 0; q < KC; ++q) cur[q] = nxt[q];
                 }
             } else {
+                // the ray's samples in this band, 16 at a time: the chunk's att loads are issued
+                // together, then used (one memory latency per chunk instead of per sample)
                 int k0 = 0, k1 = g.nt - 1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
-#pragma unroll 4
-                for (int k = k0; k <= k1; ++k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                    if (!t.mine) continue;
-                    const float v = lerp2(lds + t.off, pitch, t.fu, t.fv);
-                    kahan_add(c, col[att_row(g, k)] * v);
+                const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+                for (int kc = k0; kc <= k1; kc += kBandChunk) {
+                    float av[kBandChunk];
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        av[q] = (k <= k1) ? buffer_ld(rs, roff + 4u * att_row(g, k)) : 0.f;
+                    }
+                    float part = 0.f;
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        if (k > k1) break;
+                        float U, V;
+                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                        if (t.mine) part = fmaf(av[q], lerp2(lds + t.off, pitch, t.fu, t.fv), part);
+                    }
+                    kahan_add(c, part);
                 }
             }
             acc[j] = c;
@@ -321,19 +348,36 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                     }
                 }
             } else {
+                // the ray's samples in this band, 16 at a time (loads of att, and of att_bar when
+                // accumulating, issued together per chunk)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
-                for (int k = k0; k <= k1; ++k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                    if (!t.mine) continue;
-                    const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                    kahan_add(c, cat[att_row(g, k)] * w.x);
-                    float *p = cab + att_row(g, k);
-                    const float add = fmaf(rr, w.x, yp * w.y);
-                    *p = A.accumulate ? (*p + add) : add;
-                }
+                const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+                const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)col0;
+                for (int kc = k0; kc <= k1; kc += kBandChunk) {
+                    float av[kBandChunk], bv[kBandChunk];
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        const unsigned o = roff + 4u * att_row(g, k);
+                        av[q] = (k <= k1) ? buffer_ld(ra, o) : 0.f;
+                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld(rb, o) : 0.f;
+                    }
+                    float part = 0.f;
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        if (k > k1) break;
+                        float U, V;
+                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                        if (!t.mine) continue;
+                        const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                        part = fmaf(av[q], w.x, part);
+                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, bv[q] + fmaf(rr, w.x, yp * w.y));
+                    }
+                    kahan_add(c, part);                }
             }
             acc[j] = c;
         }
@@ -428,18 +472,29 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                     }
                 }
             } else {
-                // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2)
+                // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2), 16 samples at a time
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
-                for (int k = k0; k <= k1; ++k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                    if (!t.mine) continue;
-                    const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                    float *p = cab + att_row(g, k);
-                    const float add = g.dx * fmaf(rho, w.y, w.x);
-                    *p = A.accumulate ? (*p + add) : add;
+                const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+                for (int kc = k0; kc <= k1; kc += kBandChunk) {
+                    float bv[kBandChunk];
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld(rb, roff + 4u * att_row(g, k)) : 0.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kBandChunk; ++q) {
+                        const int k = kc + q;
+                        if (k > k1) break;
+                        float U, V;
+                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                        if (!t.mine) continue;
+                        const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, bv[q] + g.dx * fmaf(rho, w.y, w.x));
+                    }
                 }
             }
         }
@@ -452,13 +507,28 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            const size_t off = att_base(g, a, b);
+            // 16 samples at a time: the chunk's loads are issued before any of its stores
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+            const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
+            const unsigned roff = 4u * (unsigned)att_base(g, a, b);
             Comp P{0.f, 0.f};
-            for (int k = 0; k < g.nt; ++k) {
-                const size_t idx = off + att_row(g, k);
-                const float Lbar = -att[idx] * ab[idx];
-                ab[idx] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
-                comp_add(P, Lbar);
+            for (int kc = 0; kc < g.nt; kc += kBandChunk) {
+                float av[kBandChunk], bv[kBandChunk];
+#pragma unroll
+                for (int q = 0; q < kBandChunk; ++q) {
+                    const int k = kc + q;
+                    const unsigned o = roff + 4u * att_row(g, k);
+                    av[q] = (k < g.nt) ? buffer_ld(ra, o) : 0.f;
+                    bv[q] = (k < g.nt) ? buffer_ld(rb, o) : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < kBandChunk; ++q) {
+                    const int k = kc + q;
+                    if (k >= g.nt) break;
+                    const float Lbar = -av[q] * bv[q];
+                    buffer_st(rb, roff + 4u * att_row(g, k), 0u, g.dx * (fmaf(0.5f, Lbar, P.s) + P.e));
+                    comp_add(P, Lbar);
+                }
             }
         }
     }

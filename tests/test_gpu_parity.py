@@ -27,11 +27,16 @@ def dev(x, dtype=None):
 
 
 GEOMS = [
-    # (n, n_angles, n_bins, n_samples): ragged tiles (40 = 32 + 8), ragged ray chunks, nb != n, nt != n
+    # (n, n_angles, n_bins, n_samples): ragged tiles (40 = 32 + 8), ragged ray chunks, nb != n, nt != n;
+    # bins and samples off the attenuation blocks (not multiples of 8 and 4); the slid-block gather
+    # (one-bin window, >= 32 bins and samples) with its block slid to the sinogram edges, and the
+    # general gather for a two-bin window (62 bins on 48 pixels) and for a sinogram narrower than the
+    # 32-bin block (26 bins, 30 samples)
     (40, 24, 40, 40),
     (70, 30, 70, 70),
     (48, 20, 62, 48),
     (36, 16, 36, 50),
+    (28, 12, 26, 30),
 ]
 
 
