@@ -336,13 +336,17 @@ static std::string shape_key(const char *kind, const boac_geom &g, int C, int ex
 static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands) {
     make_bands(g.n, comps, rc, bands);
     const int nrays = g.n_angles * g.n_bins;
+    // default: the largest workgroups (the image stage is shared by more waves, and a stage that
+    // fills the LDS still gives 16 waves per CU) and the most rays per thread that still give every
+    // CU a workgroup
+    static const int prefs[][2] = {{1024, 4}, {1024, 2}, {1024, 1}, {512, 1}, {256, 1}};
     rc->block = 256;
     rc->rpt = 1;
-    const int target = 2 * ctx->n_cu;
-    for (int rpt : {4, 2, 1}) {
-        const int chunks = (nrays + 256 * rpt - 1) / (256 * rpt);
-        if ((long)chunks * C >= target || rpt == 1) {
-            rc->rpt = rpt;
+    for (const auto &pf : prefs) {
+        const long chunks = (nrays + pf[0] * pf[1] - 1) / (pf[0] * pf[1]);
+        if (chunks * C >= ctx->n_cu) {
+            rc->block = pf[0];
+            rc->rpt = pf[1];
             break;
         }
     }
@@ -408,8 +412,8 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
     // preference order: the slid-block kernel where it applies, then the general one; big candidate
     // groups amortise the footprint staging and the window weights, and the choice falls back while
     // the grid would not fill the GPU twice over
-    static const int prefs[][4] = {{16, 16, 8, 1}, {16, 16, 4, 1}, {16, 16, 2, 1}, {16, 16, 1, 1},
-                                   {16, 16, 8, 0}, {16, 16, 4, 0}, {16, 16, 2, 0}, {16, 16, 1, 0}};
+    static const int prefs[][4] = {{16, 16, 4, 1}, {16, 16, 2, 1}, {16, 16, 1, 1},
+                                   {16, 16, 4, 0}, {16, 16, 2, 0}, {16, 16, 1, 0}};
     const long target = 2L * ctx->n_cu;
     bool set = false;
     int slid_seen = -1;
