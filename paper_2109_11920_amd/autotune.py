@@ -8,7 +8,8 @@ this file by default):
 
     python -m paper_2109_11920_amd.autotune [--out PATH] [--workloads batch256_n128,grad64_n128,...]
 
-Keys follow the library: "ray:<n>x<na>x<nb>x<nt>:<C>:<image components>" -> [block, rays per thread]
+Keys follow the library: "ray:<n>x<na>x<nb>x<nt>:<C>:<image components>" -> [block, rays per thread,
+paired forward projection (one-component entries)]
 and "back:<n>x<na>x<nb>x<nt>:<C>:0" -> [tile width, tile height, candidates per workgroup, XCD remap,
 slid-block kernel]. A slid-block entry the geometry does not admit falls back to the library's default.
 """
@@ -84,13 +85,14 @@ def tune_workload(name: str, cache: dict, log=print):
         K = 2
         grad = w.ckpt_every > 0
         best = None
-        for blk, rpt in RAY_CONFIGS:
-            e = dict(cache)
-            e[key("ray", g, C, 1)] = [blk, rpt]
-            t = _time(g, meas, cand, e, "fwd", K)
-            log(f"[tune] {name} {shape} ray block={blk} rpt={rpt}: {t * 1e3:.1f} us/launch")
-            if best is None or t < best[0]:
-                best = (t, [blk, rpt])
+        for pair in ((0, 1) if C >= 2 else (0,)):
+            for blk, rpt in RAY_CONFIGS:
+                e = dict(cache)
+                e[key("ray", g, C, 1)] = [blk, rpt, pair]
+                t = _time(g, meas, cand, e, "fwd", K)
+                log(f"[tune] {name} {shape} ray block={blk} rpt={rpt} pair={pair}: {t * 1e3:.1f} us/launch")
+                if best is None or t < best[0]:
+                    best = (t, [blk, rpt, pair])
         cache[key("ray", g, C, 1)] = best[1]
         if grad:
             best = None

@@ -170,6 +170,33 @@ __device__ __forceinline__ void stage_band(const float *__restrict__ img, int n,
     }
 }
 
+// Two images staged interleaved (float2: first image, second image) with the same zero border.
+__device__ __forceinline__ void stage_band_pair(const float *__restrict__ img0, const float *__restrict__ img1, int n,
+                                                const Band &band, float *lds) {
+    constexpr int U = 8;
+    const int pitch = n + 3;
+    const int rows = band.ahi - band.alo + 1;
+    const int total = rows * pitch;
+    const float inv_pitch = 1.f / (float)pitch;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int rr = (int)(((float)idx + 0.5f) * inv_pitch);
+            const int i = band.alo + rr;
+            const int l = idx - rr * pitch - 1;
+            const bool in = (idx < total) && (i >= 0) && (i < n) && (l >= 0) && (l < n);
+            v[u] = in ? make_float2(img0[(size_t)i * n + l], img1[(size_t)i * n + l]) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) reinterpret_cast<float2 *>(lds)[idx] = v[u];
+        }
+    }
+}
+
 // Component `comp` of an image with `stride` floats per pixel (one plane of an interleaved image).
 __device__ __forceinline__ void stage_band_strided(const float *__restrict__ img, int n, int stride, const Band &band,
                                                    float *lds) {

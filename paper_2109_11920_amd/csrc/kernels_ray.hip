@@ -256,6 +256,134 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
     }
 }
 
+// Forward projection of two candidates per workgroup, both images staged at once (interleaved as
+// float2): each sample's position, clamp, tap index and bilinear fractions are computed once and
+// serve both candidates (one pair lerp, two FMAs), about half the vector work per candidate-sample of
+// k_fwd. Single-stage images only (the pair stage is twice the size). An odd batch's last pair
+// repeats its candidate and writes it once.
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+    extern __shared__ float lds[];
+    __shared__ float red[32];  // two floats per wave, up to 16 waves
+    const int npairs = (C + 1) >> 1;
+    int pr, chunk;
+    ray_block(chunks, npairs, pr, chunk);
+    const int c0 = 2 * pr;
+    const bool two = (c0 + 1 < C);
+    const int c1 = two ? c0 + 1 : c0;
+    const int nrays = g.na * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    stage_band_pair(A.img + c0 * A.img_cs, A.img + c1 * A.img_cs, g.n, bands.b[0], lds);
+    __syncthreads();
+    const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
+    const __amdgpu_buffer_rsrc_t r0 = buffer_rsrc(A.att + c0 * A.att_cs, (unsigned)(4 * A.att_cs));
+    const __amdgpu_buffer_rsrc_t r1 = buffer_rsrc(A.att + c1 * A.att_cs, (unsigned)(4 * A.att_cs));
+
+    Comp acc0[kMaxRpt], acc1[kMaxRpt];
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) acc0[j] = acc1[j] = Comp{0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) {
+        if (j >= rpt) break;
+        const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+        if (ray >= nrays) continue;
+        const int a = ray / g.nb, b = ray - a * g.nb;
+        const float2 cs = g.trig[a];
+        float Ub, Vb;
+        ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+        const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+        constexpr int KC = 16;
+        float u0[KC], u1[KC], n0[KC], n1[KC];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            u0[q] = (q < g.nt) ? buffer_ld(r0, roff, 4u * att_row(g, q)) : 0.f;
+            u1[q] = (q < g.nt) ? buffer_ld(r1, roff, 4u * att_row(g, q)) : 0.f;
+        }
+        Comp s0 = acc0[j], s1 = acc1[j];
+        float tau = -g.cT;
+        for (int k0 = 0; k0 < g.nt; k0 += KC) {
+#pragma unroll
+            for (int q = 0; q < KC; ++q) {
+                const int k = k0 + KC + q;
+                n0[q] = (k < g.nt) ? buffer_ld(r0, roff, 4u * att_row(g, k)) : 0.f;
+                n1[q] = (k < g.nt) ? buffer_ld(r1, roff, 4u * att_row(g, k)) : 0.f;
+            }
+            float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+            for (int q = 0; q < KC; ++q) {
+                if (k0 + q < g.nt) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
+                    const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
+                    const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
+                    const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
+                    const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
+                                             __builtin_amdgcn_fractf(Vc));
+                    p0 = fmaf(u0[q], w.x, p0);
+                    p1 = fmaf(u1[q], w.y, p1);
+                }
+                tau += 1.f;
+            }
+            kahan_add(s0, p0);
+            kahan_add(s1, p1);
+#pragma unroll
+            for (int q = 0; q < KC; ++q) {
+                u0[q] = n0[q];
+                u1[q] = n1[q];
+            }
+        }
+        acc0[j] = s0;
+        acc1[j] = s1;
+    }
+
+    // epilogues, candidate by candidate
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int cand = h ? c1 : c0;
+        const bool live = (h == 0) || two;
+        Comp nll{0.f, 0.f};
+        bool zero_proj = false;
+#pragma unroll
+        for (int j = 0; j < kMaxRpt; ++j) {
+            if (j >= rpt) break;
+            const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
+            if (ray >= nrays || !live) continue;
+            const size_t si = cand * A.sino_cs + ray;
+            const float y = g.dx * comp_value(h ? acc1[j] : acc0[j]);
+            if constexpr (MODE == FWD_PROJ) {
+                A.y_out[si] = y;
+            } else if constexpr (MODE == FWD_RATIO) {
+                const float S = A.meas[ray];
+                A.r_out[si] = (y > 0.f) ? S / y : 0.f;
+                if (A.y_out) A.y_out[si] = y;
+            } else {  // FWD_NLL
+                const float S = A.meas[ray];
+                if (A.y_out) A.y_out[si] = y;
+                float term;
+                if (S > 0.f) {
+                    if (y > 0.f) {
+                        term = y - S * logf(y);
+                    } else if (y <= 0.f) {
+                        term = __builtin_inff();
+                        zero_proj = true;
+                    } else {
+                        term = y;  // NaN propagates (flagged as non-finite at the end)
+                    }
+                } else {
+                    term = y;
+                }
+                comp_add(nll, term);
+            }
+        }
+        if constexpr (MODE == FWD_NLL) {
+            if (zero_proj && A.status) atomicOr(A.status + cand, 1u);
+            const Comp r = block_reduce(nll, red);
+            if (threadIdx.x == 0 && live) A.partial[(size_t)cand * chunks + chunk] = make_float2(r.s, r.e);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ fused reverse sweep
 // One reverse MLEM step n, per ray i (pair image = (bbar^n, F^{n+1}) staged in LDS):
 //   rbar_i   = dx sum_k att_ik (W bbar^n)_ik                          (adjoint of b^n = A^T r^n)
@@ -551,7 +679,10 @@ hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, co
 template <int MODE>
 static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                      hipStream_t st) {
-    if (rc.single)
+    if (rc.pair && rc.single && a.img_comps == 1 && C >= 2)
+        hipLaunchKernelGGL((k_fwd_pair<MODE>), dim3((unsigned)(rc.chunks * ((C + 1) / 2))), dim3(rc.block),
+                           2 * rc.lds, st, g, bands, rc.rpt, rc.chunks, C, a);
+    else if (rc.single)
         hipLaunchKernelGGL((k_fwd<MODE, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
                            rc.chunks, C, a);
     else

@@ -18,11 +18,12 @@ struct Bands {
 // A ray-kernel launch covers `cand` candidates of one slice, each with n_angles * n_bins rays split
 // in chunks of block * rpt rays.
 struct RayCfg {
-    int block;   // threads per workgroup (64..256, multiple of 64)
+    int block;   // threads per workgroup (64..1024, multiple of 64)
     int rpt;     // rays per thread (1..4)
-    int chunks;  // workgroups per candidate
-    size_t lds;  // dynamic LDS bytes
+    int chunks;  // workgroups per candidate (per candidate pair when pair)
+    size_t lds;  // dynamic LDS bytes of one image stage
     bool single; // whole image staged at once
+    bool pair;   // forward projection of two candidates per workgroup (single stage, 2 lds bytes)
 };
 
 enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2 };

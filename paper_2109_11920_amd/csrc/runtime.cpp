@@ -350,6 +350,10 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
             break;
         }
     }
+    // the paired forward projection where both images fit one stage (default on)
+    const bool pair_fits = comps == 1 && rc->single && 2 * rc->lds <= kLdsBudget && C >= 2;
+    rc->pair = pair_fits;
+    // plan cache entry: [threads per workgroup, rays per thread, paired forward projection]
     auto it = ctx->tune.find(shape_key("ray", g, C, comps));
     if (it != ctx->tune.end() && it->second.size() >= 2) {
         const int blk = it->second[0], rpt = it->second[1];
@@ -357,6 +361,7 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
             rc->block = blk;
             rc->rpt = rpt;
         }
+        if (it->second.size() >= 3) rc->pair = pair_fits && it->second[2] != 0;
     }
     rc->chunks = (nrays + rc->block * rc->rpt - 1) / (rc->block * rc->rpt);
 }

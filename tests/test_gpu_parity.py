@@ -341,9 +341,10 @@ def test_launch_configurations_agree(slice64, tmp_path):
     th = dev(cands(22, C))
     results = []
     configs = [(r, b) for r in RAY_CONFIGS[:3] for b in BACK_CONFIGS] + [(r, BACK_CONFIGS[0]) for r in RAY_CONFIGS[3:]]
-    for (blk, rpt), (tw, th_, cg, slid) in configs:
+    for i, ((blk, rpt), (tw, th_, cg, slid)) in enumerate(configs):
+        pair = i % 2  # the paired forward projection must give the same bits as one candidate per workgroup
         path = tmp_path / f"tune_{blk}_{rpt}_{tw}_{th_}_{cg}_{slid}.json"
-        path.write_text(json.dumps({key("ray", g, C, 1): [blk, rpt], key("ray", g, C, 2): [blk, rpt],
+        path.write_text(json.dumps({key("ray", g, C, 1): [blk, rpt, pair], key("ray", g, C, 2): [blk, rpt],
                                     key("back", g, C, 0): [tw, th_, cg, 1, slid]}))
         with Context(0, tune_cache=str(path)) as c2:
             J, G, _ = c2.objective_grad(g, S, th, DR, 3, 2)
