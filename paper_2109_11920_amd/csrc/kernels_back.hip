@@ -7,9 +7,9 @@
 // (hat(x) = max(0, 1 - |x|)), i.e. the forward projector's bilinear weight of that pixel.
 //
 // A workgroup owns a TW x TH tile of pixels of CG candidates of one slice and loops over every angle:
-//   1. stage the tile's footprint rectangle of att * z (bin fastest in memory, one row per wave,
-//      coalesced) into LDS with the CG candidates interleaved, so that one wide LDS read returns a
-//      window sample for every candidate;
+//   1. stage the tile's footprint in (sample, bin) of att into LDS with the CG candidates
+//      interleaved, so that one wide LDS read returns a window sample for every candidate (k_back
+//      applies the ray weights z per window column; k_back_slid folds them into the staged values);
 //   2. each thread computes the window weights of its pixels once (incrementally from the window
 //      centre) and applies them to all CG candidates.
 // Angle sums run in blocks of 8 angles, each block added to a compensated total. Because the

@@ -5,12 +5,15 @@
 //             att = exp(-L), scanned from the detector end with a compensated running sum.
 //   k_fwd     attenuated projection, Eq. (2): y = dx sum_k att (W f), compensated; epilogues give the
 //             MLEM ratio S/y or the Poisson NLL terms of Eq. (5).
+//   k_fwd_pair  the same for two candidates per workgroup, sharing each sample's geometry.
 //   k_adj_sweep  one reverse MLEM step along every ray: the projection adjoint of the ratio and the
 //             attenuation adjoint accumulation, in one sweep.
 //   k_tail    sensitivity adjoint, att = exp(-L) and the scan's transpose (a prefix sum).
 //
-// Layout: att and its adjoint are [cand][angle][k][bin] (bin fastest), so the threads of a wave
-// (consecutive bins of one angle) read and write consecutive addresses at each k.
+// Layout: att and its adjoint are per-angle slabs in 4 x 8 (sample x bin) blocks (att_row / att_col
+// in device_common.h). The threads of a wave take consecutive bins of one angle, so at each k a
+// wave's loads cover whole 32-byte block rows, and a ray's offset splits into a per-lane bin part and
+// a uniform sample-row part.
 #include "launch.h"
 
 namespace boac {

@@ -29,7 +29,7 @@ struct RayCfg {
 enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2 };
 
 struct FwdArgs {
-    const float *att;     // [C][na][nt][nb]
+    const float *att;     // [C] attenuation tensors (4 x 8-block slabs, att_row / att_col)
     const float *img;     // [C][n][n] x img_comps interleaved (component 0 is sampled)
     const float *meas;    // [na][nb]
     float *y_out;         // [C][na][nb] or null
@@ -41,8 +41,8 @@ struct FwdArgs {
 };
 
 struct SweepArgs {
-    const float *att;     // [C][na][nt][nb]
-    float *attbar;        // [C][na][nt][nb], written (accumulate = 0) or accumulated
+    const float *att;     // [C] attenuation tensors (4 x 8-block slabs)
+    float *attbar;        // [C] adjoint tensors, same layout; written (accumulate = 0) or accumulated
     const float *pair;    // [C][n][n] float2: (bbar^n, F^{n+1})
     const float *r;       // r^n [C][na][nb]
     const float *y;       // y^n
@@ -81,8 +81,8 @@ constexpr int kSlidBlock = 32;  // staged bins and samples of the slid-block bac
 constexpr int kSlidPitch = 34;  // its LDS row pitch, in slots
 
 struct BackArgs {
-    const float *att;     // [C][na][nt][nb]
-    const float *z;       // PLAIN/MLEM/ADJ: per-ray weights [C][na][nb]; FIELD: [C][na][nt][nb]
+    const float *att;     // [C] attenuation tensors (4 x 8-block slabs)
+    const float *z;       // PLAIN/MLEM/ADJ: per-ray weights [C][na][nb]; FIELD: [C] per-sample field, att layout
     const float *F;       // MLEM: current image
     const float *s;       // MLEM: sensitivity
     const float *aux;     // ADJ: direct part of F_bar
