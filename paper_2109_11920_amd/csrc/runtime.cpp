@@ -1126,8 +1126,33 @@ static boac_status eval_slice(boac_ctx *ctx, const boac_slice &s, float delta_r,
 // Batch scheduler: slices are assigned longest-first to the least-loaded of L concurrent stream
 // lanes (each with its own scratch namespace); the lanes fork from and join back into the caller's
 // stream through events, so a captured batch is one graph with L parallel branches.
-static boac_status batch_body(boac_ctx *ctx, const boac_slice *h, int32_t ns, float delta_r, int32_t K, int32_t ck,
-                              hipStream_t st) {
+// A slice of at least this many candidates is evaluated as two halves on two lanes: a projection of
+// one half (bandwidth-bound) then overlaps a gather of the other (compute-bound). Per-candidate
+// arithmetic does not depend on the grouping, so the results are unchanged.
+constexpr int kSplitMinCand = 128;
+
+static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_in, float delta_r, int32_t K,
+                              int32_t ck, hipStream_t st) {
+    std::vector<boac_slice> parts;
+    for (int i = 0; i < ns_in; ++i) {
+        const boac_slice &s = h_in[i];
+        if (s.C < kSplitMinCand || batch_lanes() < 2) {
+            parts.push_back(s);
+            continue;
+        }
+        const int c0 = (s.C / 2) & ~3;  // keeps the second half's pointers 16-byte aligned
+        boac_slice a = s, b = s;
+        a.C = c0;
+        b.C = s.C - c0;
+        b.d_cand = s.d_cand + c0;
+        b.d_obj = s.d_obj + c0;
+        if (s.d_grad) b.d_grad = s.d_grad + (size_t)8 * c0;
+        if (s.d_status) b.d_status = s.d_status + c0;
+        parts.push_back(a);
+        parts.push_back(b);
+    }
+    const boac_slice *h = parts.data();
+    const int32_t ns = (int32_t)parts.size();
     const int L = std::min(batch_lanes(), (int)ns);
     if (L <= 1) {
         ctx->ns.clear();
