@@ -327,6 +327,30 @@ def test_evaluate_batch_uneven_and_graph_replay(ctx):
             report(f"batch slice {i} n={og.n} J cand {c}", s.obj[c:c + 1].cpu().numpy(), np.array([Jr]), TOL)
 
 
+def test_evaluate_batch_split_slice_matches_eager(ctx, slice64):
+    # a slice of >= 128 candidates runs as two halves on two lanes (130 = 64 + 66: the split point is
+    # rounded for alignment); objective, status and gradient equal the eager entry points bit for bit
+    from paper_2109_11920_amd.api import SliceBatch
+    g, og = geom_pair(64, 64, pixel=0.4)
+    S = dev(slice64["meas"].astype(np.float64))
+    th = dev(cands(50, 130))
+    sb = SliceBatch.make(g, S, th, with_grad=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx.evaluate_batch([sb], DR, 3, 2)
+    stream.synchronize()
+    J, G, st = ctx.objective_grad(g, S, th, DR, 3, 2)
+    assert torch.equal(sb.obj, J) and torch.equal(sb.grad, G) and torch.equal(sb.status, st)
+    Jf, _, stf = ctx.objective(g, S, th, DR, 3)
+    sf = SliceBatch.make(g, S, th, with_grad=False)
+    with torch.cuda.stream(stream):
+        ctx.evaluate_batch([sf], DR, 3, 2)
+    stream.synchronize()
+    assert torch.equal(sf.obj, Jf) and torch.equal(sf.status, stf)
+    Jr = oracle.evaluate(og, slice64["meas"].astype(np.float64), cands(50, 130)[129], DR, 3)[0]
+    report("split slice J cand 129", sf.obj[129:130].cpu().numpy(), np.array([Jr]), TOL)
+
+
 def test_launch_configurations_agree(slice64, tmp_path):
     # every tile shape / candidates-per-workgroup / ray blocking the autotuner may choose gives the
     # same objective and gradient within one backprojection kernel family (the per-candidate arithmetic
