@@ -94,6 +94,42 @@ def cpu_baseline(workload_S, n_cand, n_iter):
                       f"FP64 NumPy/SciPy single thread, {dt:.1f} s"}
 
 
+def uneven_line(ctx, dev):
+    """The 48-slice uneven batch: N 96-256, 64-256 angles, 32 candidates each, 40 iterations, objective
+    + gradient (checkpoint every 5), one captured batch over concurrent stream lanes; times one replay."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_11920_amd.api import Geometry, SliceBatch
+    du = np.load(os.path.join(ROOT, "tests", "golden", "uneven48.npz"))
+    wu = synth.workload("uneven48")
+    cu = synth.workload_candidates(wu)
+    slices = []
+    for s in range(int(du["n_slices"])):
+        n, na, nb, nt = (int(v) for v in du[f"s{s:02d}_geometry"])
+        gs = Geometry(n, na, nb, nt, float(du[f"s{s:02d}_pixel"]))
+        slices.append(SliceBatch.make(gs, torch.as_tensor(du[f"s{s:02d}_meas"].astype(np.float32), device=dev),
+                                      torch.as_tensor(cu[s].astype(np.float32), device=dev), with_grad=True))
+    ustream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(ustream):
+        ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # runs eagerly, then captures
+        ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # graph replay (warm)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ustream)
+        ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)
+        e1.record(ustream)
+    ustream.synchronize()
+    ums = e0.elapsed_time(e1)
+    n_eval = sum(sb.cand.shape[0] for sb in slices)
+    ok = all(bool(torch.isfinite(sb.obj).all()) and bool(torch.isfinite(sb.grad).all()) for sb in slices)
+    return {"value": round(n_eval * wu.n_iter / (ums / 1e3), 1), "unit": "cand·it/s",
+            "obj_grad_evals_per_s": round(n_eval / (ums / 1e3), 1), "ms_per_batch": round(ums, 2), "finite": ok,
+            "what": "48 slices N in {96,128,192,256}, 64-256 angles, 32 candidates each, 40 iterations, "
+                    "objective + gradient, checkpoint 5, one graph replay"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +139,7 @@ def main():
     ap.add_argument("--cpu-cands", type=int, default=32)
     ap.add_argument("--no-uneven", action="store_true", help="skip the 48-slice uneven batch line")
     ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
+    ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
     args = ap.parse_args()
@@ -130,6 +167,10 @@ def main():
     C, K = cand.shape[0], w.n_iter
     ctx = Context(0)
     stream = torch.cuda.current_stream(dev)
+    if args.only_uneven:
+        print(json.dumps({"uneven48": uneven_line(ctx, dev)}), flush=True)
+        ctx.close()
+        return
     if args.copy_calib:
         src = torch.ones(1 << 28, device=dev)          # 1 GiB
         dst = torch.empty_like(src)
@@ -248,35 +289,7 @@ def main():
                        "what": "64 candidates, 20 iterations, checkpoint every 5"}
 
     if not args.only_main and not args.no_uneven:
-        # ---- uneven batch: 48 slices (N 96-256, 64-256 angles) x 32 candidates, 40 iterations,
-        # objective + gradient (checkpoint every 5), one captured batch over concurrent stream lanes
-        du = np.load(os.path.join(ROOT, "tests", "golden", "uneven48.npz"))
-        wu = synth.workload("uneven48")
-        cu = synth.workload_candidates(wu)
-        slices = []
-        for s in range(int(du["n_slices"])):
-            n, na, nb, nt = (int(v) for v in du[f"s{s:02d}_geometry"])
-            gs = Geometry(n, na, nb, nt, float(du[f"s{s:02d}_pixel"]))
-            slices.append(SliceBatch.make(gs, torch.as_tensor(du[f"s{s:02d}_meas"].astype(np.float32), device=dev),
-                                          torch.as_tensor(cu[s].astype(np.float32), device=dev), with_grad=True))
-        ustream = torch.cuda.Stream(dev)
-        with torch.cuda.stream(ustream):
-            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # runs eagerly, then captures
-            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # graph replay (warm)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(ustream)
-            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)
-            e1.record(ustream)
-        ustream.synchronize()
-        ums = e0.elapsed_time(e1)
-        n_eval = sum(sb.cand.shape[0] for sb in slices)
-        ok = all(bool(torch.isfinite(sb.obj).all()) and bool(torch.isfinite(sb.grad).all()) for sb in slices)
-        out["uneven48"] = {"value": round(n_eval * wu.n_iter / (ums / 1e3), 1), "unit": "cand·it/s",
-                           "obj_grad_evals_per_s": round(n_eval / (ums / 1e3), 1), "ms_per_batch": round(ums, 2),
-                           "finite": ok,
-                           "what": "48 slices N in {96,128,192,256}, 64-256 angles, 32 candidates each, 40 "
-                                   "iterations, objective + gradient, checkpoint 5, one graph replay"}
+        out["uneven48"] = uneven_line(ctx, dev)
 
     if not args.no_cpu and not args.only_main:
         out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K)
