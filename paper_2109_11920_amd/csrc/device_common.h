@@ -29,13 +29,14 @@ struct DevGeom {
 
 // Attenuation-tensor layout. Per candidate, na slabs (one per angle) of the samples (k, b); a slab is
 // tiled in 4 x 8 blocks (4 consecutive samples of 8 consecutive bins, one 128-byte line), blocks
-// running bin-block fastest, and within a block sample-row major. Element (a, k, b) is at
-// a slab + att_row(k) + att_col(b). A ray's samples keep a fixed bin part (att_col) and a row part
-// (att_row) that depends on k only; a pixel tile's footprint in the slab covers about half as many
-// partly used lines as in a row-major slab.
-__device__ __forceinline__ unsigned att_col(int b) { return (unsigned)(((b >> 3) << 5) + (b & 7)); }
+// running bin-block fastest, and within a block sample fastest: the 4 samples of one bin are 16
+// contiguous bytes. Element (a, k, b) is at a slab + att_row(k) + att_col(b). A ray's samples keep a
+// fixed bin part (att_col) and a row part (att_row) that depends on k only; a pixel tile's footprint
+// in the slab covers about half as many partly used lines as in a row-major slab, and 4 samples of a
+// bin (k a multiple of 4) are one aligned 16-byte load.
+__device__ __forceinline__ unsigned att_col(int b) { return (unsigned)(((b >> 3) << 5) + ((b & 7) << 2)); }
 __device__ __forceinline__ unsigned att_row(const DevGeom &g, int k) {
-    return (unsigned)((k >> 2) * (g.nb8 << 5) + ((k & 3) << 3));
+    return (unsigned)((k >> 2) * (g.nb8 << 5) + (k & 3));
 }
 __device__ __forceinline__ size_t att_base(const DevGeom &g, int a, int b) {
     return (size_t)a * (size_t)g.slab + att_col(b);
@@ -321,10 +322,24 @@ __device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned by
 __device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, uniform_off, 0));
 }
+// 16-byte load (4 consecutive floats) at a per-lane plus a uniform byte offset.
+__device__ __forceinline__ float4 buffer_ld4(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, uniform_off, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+}
 // Vector store of one float at a per-lane plus a uniform byte offset.
 __device__ __forceinline__ void buffer_st(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, uniform_off, 0);
 }
+// Vector store of 4 consecutive floats at a per-lane plus a uniform byte offset.
+__device__ __forceinline__ void buffer_st4(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off, float4 v) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, uniform_off, 0);
+}
+// Component q (0..3, a compile-time constant after unrolling) of v.
+__device__ __forceinline__ float f4at(const float4 &v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
 
 // hat(x) = max(0, 1 - |x|)
 __device__ __forceinline__ float hat(float x) { return fmaxf(1.f - fabsf(x), 0.f); }

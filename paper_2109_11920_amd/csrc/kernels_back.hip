@@ -555,6 +555,209 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
     }
 }
 
+// ---------------------------------------------------------------------------------------------------
+// Column-group variant of the slid-block gather (n_samples a multiple of 4). The host aligns the
+// block's first sample row to a multiple of 4, so the 4 samples k..k+3 (k = first row + 4 j) of a bin
+// are one aligned 16-byte load in the attenuation layout (sample fastest inside a 4 x 8 block): thread
+// t stages bin t % 32 of rows 4 (t / 32) .. + 3 with one 16-byte load per candidate, a quarter of the
+// vector-memory instructions of the slot variant (which is bound by its vector-memory pipeline), and
+// 8 lanes on consecutive bins read one whole 128-byte line. All 4 samples share the bin's ray weight,
+// folded in while staging as in the slot variant. A group is loaded unless all of it lies outside the
+// union of the tile pixels' supports (tested at its centre with half widths grown by 1.5 samples); a
+// skipped group keeps finite values, gathered only with weight 0.
+template <int CG, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_back_seg(DevGeom g, BackCfg T, BackArgs A, int mode) {
+    constexpr int P = kSlidBlock;
+    constexpr int PL = kSlidPitch;
+    constexpr int V = SlidLayout<CG>::V;
+    constexpr int PLANES = SlidLayout<CG>::PLANES;
+    constexpr int PLANE = SlidLayout<CG>::PLANE;
+    extern __shared__ float lds[];  // [PLANES][P rows][PL slots][V]
+    const int ntiles = T.tiles_x * T.tiles_y;
+    const int ngroups = (A.C + CG - 1) / CG;
+    const int total = ntiles * ngroups;
+    int id = blockIdx.x;
+    if (T.xcd_remap && (total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
+    const int grp = id / ntiles;
+    const int tile = id - grp * ntiles;
+    const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
+    const int l0 = tx * 16, i0 = ty * 16;
+    const int c0 = grp * CG;
+    const int ncg = min(CG, A.C - c0);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+
+    // this thread's pixel: each 8 lanes of a wave take a 4 x 2 block, a wave a 16 x 4 band
+    const int l = l0 + ((lane >> 3) & 3) * 4 + (lane & 3);
+    const int i = i0 + (tid >> 6) * 4 + (lane >> 5) * 2 + ((lane >> 2) & 1);
+    const bool pv = (l < g.n) && (i < g.n);
+    const float xc = (float)l - g.cN, yc = (float)i - g.cN;
+    const float cB5 = g.cB + 0.5f, cT5 = g.cT + 0.5f;
+    const float inv_bscale = 1.f / g.bscale;
+
+    // open support box of the tile's pixels (half widths around its centre)
+    const int l1 = min(l0 + 15, g.n - 1), i1 = min(i0 + 15, g.n - 1);
+    const float hu = 0.5f * (float)(l1 - l0) + 1.f + 1e-3f;
+    const float hv = 0.5f * (float)(i1 - i0) + 1.f + 1e-3f;
+
+    // staging group: bin bb, rows 4 kb .. 4 kb + 3
+    const int bb = tid & (P - 1), kb = tid >> 5;
+    const float fbb = (float)bb, fkc = (float)(4 * kb) + 1.5f;  // group centre, in samples
+    const unsigned a_stride = 4u * (unsigned)g.slab;
+    const unsigned cand_src = 4u * (unsigned)A.att_cs, cand_z = 4u * (unsigned)A.sino_cs;
+    const float *src = (mode == BACK_FIELD) ? A.z : A.att;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src + (size_t)c0 * A.att_cs, (unsigned)ncg * cand_src);
+    const __amdgpu_buffer_rsrc_t rz =
+        buffer_rsrc(WEIGHTED ? A.z + (size_t)c0 * A.sino_cs : src, WEIGHTED ? (unsigned)ncg * cand_z : 0u);
+    const int4 *rects = T.rects + (size_t)tile * g.na;
+    unsigned qs[CG], qz[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
+        qz[q] = (unsigned)min(q, ncg - 1) * cand_z;
+    }
+
+    Comp acc[CG];
+    float blk[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        acc[q] = Comp{0.f, 0.f};
+        blk[q] = 0.f;
+    }
+
+    float4 pre[CG];
+    float zv[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        pre[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        zv[q] = 1.f;
+    }
+    auto prefetch = [&](int a, int4 r) {
+        const float2 cs = g.trig[a];
+        const float U = fmaf(fkc, -cs.y, fmaf(fbb, cs.x * g.bscale, __int_as_float(r.z)));
+        const float V = fmaf(fkc, cs.x, fmaf(fbb, cs.y * g.bscale, __int_as_float(r.w)));
+        // a group sample is within 1.5 samples of the group centre; one sample step moves (U, V) by (-s, c)
+        if (fabsf(U) < fmaf(1.5f, fabsf(cs.y), hu) && fabsf(V) < fmaf(1.5f, fabsf(cs.x), hv)) {
+            const unsigned off = 4u * (att_row(g, r.y + 4 * kb) + att_col(r.x + bb));
+#pragma unroll
+            for (int q = 0; q < CG; ++q) pre[q] = buffer_ld4(rs, off, (unsigned)a * a_stride + qs[q]);
+        }
+        if constexpr (WEIGHTED) {
+            const unsigned zbase = 4u * (unsigned)(a * g.nb + r.x);
+#pragma unroll
+            for (int q = 0; q < CG; ++q) zv[q] = buffer_ld(rz, 4u * (unsigned)bb, zbase + qz[q]);
+        }
+    };
+
+    int4 cur = rects[0];
+    prefetch(0, cur);
+
+    for (int a = 0; a < g.na; ++a) {
+        __syncthreads();  // previous gather done with the LDS
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float v[CG];
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
+                v[q] = WEIGHTED ? x * zv[q] : x;
+            }
+            float *d = lds + ((4 * kb + t) * PL + bb) * V;
+            if constexpr (CG == 8) {
+                reinterpret_cast<float4 *>(d)[0] = make_float4(v[0], v[1], v[2], v[3]);
+                reinterpret_cast<float4 *>(d + PLANE)[0] = make_float4(v[4], v[5], v[6], v[7]);
+            } else if constexpr (CG == 4) {
+                reinterpret_cast<float4 *>(d)[0] = make_float4(v[0], v[1], v[2], v[3]);
+            } else if constexpr (CG == 2) {
+                reinterpret_cast<float2 *>(d)[0] = make_float2(v[0], v[1]);
+            } else {
+                d[0] = v[0];
+            }
+        }
+        __syncthreads();
+        const int4 r = cur;
+        if (a + 1 < g.na) {
+            cur = rects[a + 1];
+            prefetch(a + 1, cur);
+        }
+
+        // ---- gather (as in the slot variant)
+        const float2 cs = g.trig[a];
+        const float c = cs.x, s = cs.y;
+        const float ub = c * g.bscale, vb = s * g.bscale;
+        const float fb1 = (float)(r.x + 1), fk1 = (float)(r.y + 1);
+        if (pv) {
+            const float Sj5 = fmaf(xc, c * inv_bscale, fmaf(yc, s * inv_bscale, cB5));
+            const float Tj5 = fmaf(yc, c, fmaf(xc, -s, cT5));
+            const float bcf = __builtin_amdgcn_fmed3f(floorf(Sj5), fb1, fb1 + (float)(P - 3));
+            const float kcf = __builtin_amdgcn_fmed3f(floorf(Tj5), fk1, fk1 + (float)(P - 3));
+            const float sig = (bcf - g.cB) * g.bscale, tau = kcf - g.cT;
+            const float du0 = fmaf(sig, c, fmaf(tau, -s, -xc));
+            const float dv0 = fmaf(sig, s, fmaf(tau, c, -yc));
+            const int corner = (int)(kcf - fk1) * PL + (int)(bcf - fb1);  // window tap (-1, -1)
+            const float *base = lds + corner * V;
+#pragma unroll
+            for (int db = -1; db <= 1; ++db) {
+                const float dub = (db == 0) ? du0 : (db < 0 ? du0 - ub : du0 + ub);
+                const float dvb = (db == 0) ? dv0 : (db < 0 ? dv0 - vb : dv0 + vb);
+#pragma unroll
+                for (int dk = -1; dk <= 1; ++dk) {
+                    const float du = (dk == 0) ? dub : (dk < 0 ? dub + s : dub - s);
+                    const float dv = (dk == 0) ? dvb : (dk < 0 ? dvb - c : dvb + c);
+                    const float w = hat1(du) * hat1(dv);
+#pragma unroll
+                    for (int h = 0; h < PLANES; ++h) {
+                        Vec<V> gv;
+                        gv.load(base + h * PLANE + ((dk + 1) * PL + (db + 1)) * V);
+#pragma unroll
+                        for (int q = 0; q < V; ++q) blk[h * V + q] = fmaf(w, gv.v[q], blk[h * V + q]);
+                    }
+                }
+            }
+        }
+        if ((a & 7) == 7 || a == g.na - 1) {
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                comp_add(acc[q], blk[q]);
+                blk[q] = 0.f;
+            }
+        }
+    }
+
+    if (!pv) return;
+    const size_t pix = (size_t)i * g.n + l;
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        if (q >= ncg) break;
+        const size_t o = (size_t)(c0 + q) * A.img_cs + pix;
+        const float v = comp_value(acc[q]);
+        if (mode == BACK_FIELD) {
+            A.out[o] = v;
+        } else if (mode == BACK_MLEM) {
+            const float b = g.dx * v;
+            const float sv = A.s[o];
+            const float Q = (sv > 0.f) ? b / sv : 0.f;
+            A.out[o] = A.F[o] * Q;
+            if (A.q_out) A.q_out[o] = Q;
+        } else if (mode == BACK_ADJ) {
+            A.out[o] = fmaf(g.dx, v, A.aux[o]);
+        } else {
+            A.out[o] = g.dx * v;
+        }
+    }
+}
+
+template <int CG>
+static hipError_t back_seg(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
+    const int ngroups = (a.C + CG - 1) / CG;
+    const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
+    if (mode == BACK_SENS || mode == BACK_FIELD)
+        hipLaunchKernelGGL((k_back_seg<CG, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    else
+        hipLaunchKernelGGL((k_back_seg<CG, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    return hipGetLastError();
+}
+
 template <int CG>
 static hipError_t back_slid(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
@@ -583,6 +786,16 @@ static hipError_t back_tile(const DevGeom &g, const BackCfg &bc, const BackArgs 
 }
 
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
+    if (bc.slid == 2) {
+        if (bc.tw != 16 || bc.th != 16 || bc.hb != 1) return hipErrorInvalidValue;
+        switch (bc.cg) {
+            case 1: return back_seg<1>(g, bc, a, mode, st);
+            case 2: return back_seg<2>(g, bc, a, mode, st);
+            case 4: return back_seg<4>(g, bc, a, mode, st);
+            case 8: return back_seg<8>(g, bc, a, mode, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (bc.slid) {
         if (bc.tw != 16 || bc.th != 16 || bc.hb != 1) return hipErrorInvalidValue;
         switch (bc.cg) {

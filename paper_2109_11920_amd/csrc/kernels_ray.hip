@@ -61,16 +61,26 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
             float *col = out + att_base(g, a, b);
             if constexpr (SINGLE) {
-                // single pass from the detector end: running suffix sum T = sum_{k'>k} m_k'
+                // single pass from the detector end: running suffix sum T = sum_{k'>k} m_k'; the 4
+                // samples of a group (k a multiple of 4) are one 16-byte store, padding rows get 0
                 Comp T{0.f, 0.f};
-                for (int k = g.nt - 1; k >= 0; --k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<true>(U, V, nf, pitch, band);
-                    const float m = lerp2(lds + t.off, pitch, t.fu, t.fv);
-                    const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                    col[att_row(g, k)] = expf(-L);
-                    comp_add(T, m);
+                for (int kg = (g.nt - 1) >> 2; kg >= 0; --kg) {
+                    float e[4];
+#pragma unroll
+                    for (int q = 3; q >= 0; --q) {
+                        const int k = 4 * kg + q;
+                        e[q] = 0.f;
+                        if (k < g.nt) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                            const Tap t = make_tap<true>(U, V, nf, pitch, band);
+                            const float m = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                            const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
+                            e[q] = expf(-L);
+                            comp_add(T, m);
+                        }
+                    }
+                    *reinterpret_cast<float4 *>(col + att_row(g, 4 * kg)) = make_float4(e[0], e[1], e[2], e[3]);
                 }
             } else {
                 // pass 1 of 2: store m_k of the samples in this band
@@ -159,18 +169,20 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                 // while chunk k0 is computed. The loads go through a buffer resource: a per-lane ray
                 // offset plus a uniform offset of the sample row. Each chunk is summed with FMAs and
                 // added to the compensated total.
-                constexpr int KC = 16;
+                // Each 16-byte load brings 4 consecutive samples of the ray (one group of the layout).
+                constexpr int KC = 16, KG = KC / 4;
                 const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
-                float cur[KC], nxt[KC];
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 cur[KG], nxt[KG];
 #pragma unroll
-                for (int q = 0; q < KC; ++q) cur[q] = (q < g.nt) ? buffer_ld(rs, roff, 4u * att_row(g, q)) : 0.f;
+                for (int q = 0; q < KG; ++q) cur[q] = (4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, 4 * q)) : z4;
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) {
-                        const int k = k0 + KC + q;
-                        nxt[q] = (k < g.nt) ? buffer_ld(rs, roff, 4u * att_row(g, k)) : 0.f;
+                    for (int q = 0; q < KG; ++q) {
+                        const int k = k0 + KC + 4 * q;
+                        nxt[q] = (k < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, k)) : z4;
                     }
                     float part = 0.f;
 #pragma unroll
@@ -178,13 +190,13 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                         if (k0 + q < g.nt) {
                             float U, V;
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
-                            part = fmaf(cur[q], bilinear_whole(lds, U, V, nf, pitch), part);
+                            part = fmaf(f4at(cur[q >> 2], q & 3), bilinear_whole(lds, U, V, nf, pitch), part);
                         }
                         tau += 1.f;
                     }
                     kahan_add(c, part);
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) cur[q] = nxt[q];
+                    for (int q = 0; q < KG; ++q) cur[q] = nxt[q];
                 }
             } else {
                 // the ray's samples in this band, 16 at a time: the chunk's att loads are issued
@@ -296,21 +308,22 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
         float Ub, Vb;
         ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
         const unsigned roff = 4u * (unsigned)att_base(g, a, b);
-        constexpr int KC = 16;
-        float u0[KC], u1[KC], n0[KC], n1[KC];
+        constexpr int KC = 16, KG = KC / 4;
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 u0[KG], u1[KG], n0[KG], n1[KG];
 #pragma unroll
-        for (int q = 0; q < KC; ++q) {
-            u0[q] = (q < g.nt) ? buffer_ld(r0, roff, 4u * att_row(g, q)) : 0.f;
-            u1[q] = (q < g.nt) ? buffer_ld(r1, roff, 4u * att_row(g, q)) : 0.f;
+        for (int q = 0; q < KG; ++q) {
+            u0[q] = (4 * q < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, 4 * q)) : z4;
+            u1[q] = (4 * q < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, 4 * q)) : z4;
         }
         Comp s0 = acc0[j], s1 = acc1[j];
         float tau = -g.cT;
         for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
-            for (int q = 0; q < KC; ++q) {
-                const int k = k0 + KC + q;
-                n0[q] = (k < g.nt) ? buffer_ld(r0, roff, 4u * att_row(g, k)) : 0.f;
-                n1[q] = (k < g.nt) ? buffer_ld(r1, roff, 4u * att_row(g, k)) : 0.f;
+            for (int q = 0; q < KG; ++q) {
+                const int k = k0 + KC + 4 * q;
+                n0[q] = (k < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, k)) : z4;
+                n1[q] = (k < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, k)) : z4;
             }
             float p0 = 0.f, p1 = 0.f;
 #pragma unroll
@@ -323,15 +336,15 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
                     const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
                     const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
                                              __builtin_amdgcn_fractf(Vc));
-                    p0 = fmaf(u0[q], w.x, p0);
-                    p1 = fmaf(u1[q], w.y, p1);
+                    p0 = fmaf(f4at(u0[q >> 2], q & 3), w.x, p0);
+                    p1 = fmaf(f4at(u1[q >> 2], q & 3), w.y, p1);
                 }
                 tau += 1.f;
             }
             kahan_add(s0, p0);
             kahan_add(s1, p1);
 #pragma unroll
-            for (int q = 0; q < KC; ++q) {
+            for (int q = 0; q < KG; ++q) {
                 u0[q] = n0[q];
                 u1[q] = n1[q];
             }
@@ -429,35 +442,39 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
             const float rr = g.dx * A.r[si];
             const float yp = g.dx * A.ybar_in[si];
             const size_t col0 = att_base(g, a, b);
-            const float *cat = att + col0;
-            float *cab = ab + col0;
             Comp c = acc[j];
             if constexpr (SINGLE) {
                 // as in the forward projection: att and att_bar streamed 16 samples ahead through
                 // buffer resources (per-lane ray offset + uniform sample-row offset), chunked
                 // compensated sum, tap index formed in float
-                constexpr int KC = 16;
+                // samples move in groups of 4 (one 16-byte load or store); padding rows get 0
+                constexpr int KC = 16, KG = KC / 4;
                 const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)col0;
-                float at[KC], an[KC], bt[KC], bn[KC];
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 at[KG], an[KG], bt[KG], bn[KG];
 #pragma unroll
-                for (int q = 0; q < KC; ++q) {
-                    at[q] = (q < g.nt) ? buffer_ld(ra, roff, 4u * att_row(g, q)) : 0.f;
-                    bt[q] = (A.accumulate && q < g.nt) ? buffer_ld(rb, roff, 4u * att_row(g, q)) : 0.f;
+                for (int q = 0; q < KG; ++q) {
+                    const unsigned o = 4u * att_row(g, 4 * q);
+                    at[q] = (4 * q < g.nt) ? buffer_ld4(ra, roff, o) : z4;
+                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                 }
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) {
-                        const int k = k0 + KC + q;
-                        an[q] = (k < g.nt) ? buffer_ld(ra, roff, 4u * att_row(g, k)) : 0.f;
-                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld(rb, roff, 4u * att_row(g, k)) : 0.f;
+                    for (int q = 0; q < KG; ++q) {
+                        const int k = k0 + KC + 4 * q;
+                        const unsigned o = 4u * att_row(g, k);
+                        an[q] = (k < g.nt) ? buffer_ld4(ra, roff, o) : z4;
+                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                     }
                     float part = 0.f;
+                    float ov[4];
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + q;
+                        ov[q & 3] = 0.f;
                         if (k < g.nt) {
                             float U, V;
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
@@ -466,14 +483,16 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                             const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
                             const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
                                                      __builtin_amdgcn_fractf(Vc));
-                            part = fmaf(at[q], w.x, part);
-                            buffer_st(rb, roff, 4u * att_row(g, k), bt[q] + fmaf(rr, w.x, yp * w.y));
+                            part = fmaf(f4at(at[q >> 2], q & 3), w.x, part);
+                            ov[q & 3] = f4at(bt[q >> 2], q & 3) + fmaf(rr, w.x, yp * w.y);
                         }
                         tau += 1.f;
+                        if ((q & 3) == 3 && k - 3 < g.nt)
+                            buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     kahan_add(c, part);
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) {
+                    for (int q = 0; q < KG; ++q) {
                         at[q] = an[q];
                         bt[q] = bn[q];
                     }
@@ -559,28 +578,35 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
             const float rho = A.rho[cand * A.sino_cs + ray];
             const size_t off = att_base(g, a, b);
-            const float *cat = att + off;
-            float *cab = ab + off;
             if constexpr (SINGLE) {
-                constexpr int KC = 16;
-                float at[KC], an[KC], bt[KC], bn[KC];
+                // samples move in groups of 4 (one 16-byte load or store); padding rows get 0
+                constexpr int KC = 16, KG = KC / 4;
+                const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
+                const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
+                const unsigned roff = 4u * (unsigned)off;
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 at[KG], an[KG], bt[KG], bn[KG];
 #pragma unroll
-                for (int q = 0; q < KC; ++q) {
-                    at[q] = (q < g.nt) ? cat[att_row(g, q)] : 0.f;
-                    bt[q] = (A.accumulate && q < g.nt) ? cab[att_row(g, q)] : 0.f;
+                for (int q = 0; q < KG; ++q) {
+                    const unsigned o = 4u * att_row(g, 4 * q);
+                    at[q] = (4 * q < g.nt) ? buffer_ld4(ra, roff, o) : z4;
+                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                 }
                 Comp P{0.f, 0.f};
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) {
-                        const int k = k0 + KC + q;
-                        an[q] = (k < g.nt) ? cat[att_row(g, k)] : 0.f;
-                        bn[q] = (A.accumulate && k < g.nt) ? cab[att_row(g, k)] : 0.f;
+                    for (int q = 0; q < KG; ++q) {
+                        const int k = k0 + KC + 4 * q;
+                        const unsigned o = 4u * att_row(g, k);
+                        an[q] = (k < g.nt) ? buffer_ld4(ra, roff, o) : z4;
+                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                     }
+                    float ov[4];
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + q;
+                        ov[q & 3] = 0.f;
                         if (k < g.nt) {
                             float U, V;
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
@@ -589,15 +615,17 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                             const int l0 = __float2int_rd(Uc), i0 = __float2int_rd(Vc);
                             const float2 w = lerp2x2(lds2 + (i0 + 1) * pitch + (l0 + 1), pitch,
                                                      __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
-                            const float abar = bt[q] + g.dx * fmaf(rho, w.y, w.x);
-                            const float Lbar = -at[q] * abar;
-                            cab[att_row(g, k)] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                            const float abar = f4at(bt[q >> 2], q & 3) + g.dx * fmaf(rho, w.y, w.x);
+                            const float Lbar = -f4at(at[q >> 2], q & 3) * abar;
+                            ov[q & 3] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
                             comp_add(P, Lbar);
                         }
                         tau += 1.f;
+                        if ((q & 3) == 3 && k - 3 < g.nt)
+                            buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
 #pragma unroll
-                    for (int q = 0; q < KC; ++q) {
+                    for (int q = 0; q < KG; ++q) {
                         at[q] = an[q];
                         bt[q] = bn[q];
                     }

@@ -74,7 +74,8 @@ struct BackCfg {
     const int4 *rects;    // [tiles][n_angles] footprint rectangles (b_lo, k_lo, wb, wk)
     int xcd_remap;        // keep a candidate group's tiles on one XCD
     int slid;             // 16 x 16 tiles, one-bin half window: fixed 32 x 32 staging block slid inside
-                          // the sinogram; rects then hold (b0, k0, u0 bits, v0 bits)
+                          // the sinogram; rects then hold (b0, k0, u0 bits, v0 bits). 1: staging by
+                          // 4-byte slots; 2: by aligned 4-sample column groups (k0 a multiple of 4)
 };
 
 constexpr int kSlidBlock = 32;  // staged bins and samples of the slid-block backprojection

@@ -259,7 +259,15 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
                 if (wb > kSlidBlock || wk > kSlidBlock)
                     return fail(BOAC_EDEVICE, "internal: footprint %dx%d exceeds the %d-block", wb, wk, kSlidBlock);
                 const int b0 = std::min(std::max(b_lo, 0), g.n_bins - kSlidBlock);
-                const int k0 = std::min(std::max(k_lo, 0), g.n_samples - kSlidBlock);
+                int k0 = std::min(std::max(k_lo, 0), g.n_samples - kSlidBlock);
+                if (bc->slid == 2) {
+                    // column-group variant: the first sample row a multiple of 4 (n_samples is one, so
+                    // the block still ends inside the sinogram); it must still reach the clipped
+                    // footprint's last row
+                    k0 &= ~3;
+                    if (std::min(k_hi, g.n_samples - 1) >= k0 + kSlidBlock)
+                        return fail(BOAC_EDEVICE, "internal: aligned footprint exceeds the %d-block", kSlidBlock);
+                }
                 // image position of sample (b0, k0), relative to the centre of the tile's support box
                 const double sig = ((double)b0 - cB) * ((double)g.n / (double)g.n_bins), tau = (double)k0 - cT;
                 const double u = sig * c - tau * s - 0.5 * (xl[0] + xl[1]);
@@ -403,7 +411,8 @@ static bool back_cfg_ok(const BackCfg &b) {
 // sinogram at least one block wide and tall, and 32-bit buffer offsets that cannot wrap (the kernel's
 // largest offset is below 2 cg bytes-per-candidate).
 static bool slid_ok(const boac_geom &g, const BackCfg &b) {
-    if (b.slid != 1 || b.tw != 16 || b.th != 16 || b.hb != 1) return false;
+    if (!(b.slid == 1 || b.slid == 2) || b.tw != 16 || b.th != 16 || b.hb != 1) return false;
+    if (b.slid == 2 && g.n_samples % 4 != 0) return false;
     if (!(b.cg == 1 || b.cg == 2 || b.cg == 4 || b.cg == 8) || b.lds > kLdsBudget) return false;
     if (b.wbmax > kSlidBlock || b.wkmax > kSlidBlock) return false;
     if (g.n_bins < kSlidBlock || g.n_samples < kSlidBlock) return false;
@@ -417,7 +426,8 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
     // preference order: the slid-block kernel where it applies, then the general one; big candidate
     // groups amortise the footprint staging and the window weights, and the choice falls back while
     // the grid would not fill the GPU twice over
-    static const int prefs[][4] = {{16, 16, 4, 1}, {16, 16, 2, 1}, {16, 16, 1, 1},
+    static const int prefs[][4] = {{16, 16, 4, 2}, {16, 16, 2, 2}, {16, 16, 1, 2},
+                                   {16, 16, 4, 1}, {16, 16, 2, 1}, {16, 16, 1, 1},
                                    {16, 16, 4, 0}, {16, 16, 2, 0}, {16, 16, 1, 0}};
     const long target = 2L * ctx->n_cu;
     bool set = false;
@@ -446,7 +456,8 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         back_fill(g, &t);
         *bc = t;
     }
-    // plan cache entry: [tile width, tile height, candidates per workgroup, XCD remap, slid block]
+    // plan cache entry: [tile width, tile height, candidates per workgroup, XCD remap, slid block
+    // (0: general kernel, 1: slot staging, 2: column-group staging)]
     auto it = ctx->tune.find(shape_key("back", g, C, 0));
     if (it != ctx->tune.end() && it->second.size() >= 3) {
         BackCfg t{};
@@ -454,7 +465,7 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         t.th = it->second[1];
         t.cg = it->second[2];
         t.xcd_remap = it->second.size() >= 4 ? (it->second[3] != 0) : 1;
-        t.slid = it->second.size() >= 5 ? (it->second[4] != 0) : 0;
+        t.slid = it->second.size() >= 5 ? it->second[4] : 0;
         back_fill(g, &t);
         if (plan_ok(g, t)) *bc = t;
     }
