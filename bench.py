@@ -68,6 +68,8 @@ def kernel_name(kind, C):
             e = json.load(f).get(f"back:128x128x128x128:{C}:0")
     except (OSError, ValueError):
         e = None
+    if e and len(e) >= 5 and e[4] == 2:
+        return f"k_back_col4<{e[2]}, true> (MLEM gather)"
     if e and len(e) >= 5 and e[4]:
         return f"k_back_slid<{e[2]}, true> (MLEM gather)"
     if e:

@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
 // union of the tile pixels' supports (tested at its centre with half widths grown by 1.5 samples); a
 // skipped group keeps finite values, gathered only with weight 0.
 template <int CG, bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_back_seg(DevGeom g, BackCfg T, BackArgs A, int mode) {
+__global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
     constexpr int PL = kSlidPitch;
     constexpr int V = SlidLayout<CG>::V;
@@ -748,13 +748,13 @@ __global__ __launch_bounds__(256) void k_back_seg(DevGeom g, BackCfg T, BackArgs
 }
 
 template <int CG>
-static hipError_t back_seg(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
+static hipError_t back_col4(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
     const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
     if (mode == BACK_SENS || mode == BACK_FIELD)
-        hipLaunchKernelGGL((k_back_seg<CG, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+        hipLaunchKernelGGL((k_back_col4<CG, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
     else
-        hipLaunchKernelGGL((k_back_seg<CG, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+        hipLaunchKernelGGL((k_back_col4<CG, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
     return hipGetLastError();
 }
 
@@ -789,10 +789,10 @@ hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const Back
     if (bc.slid == 2) {
         if (bc.tw != 16 || bc.th != 16 || bc.hb != 1) return hipErrorInvalidValue;
         switch (bc.cg) {
-            case 1: return back_seg<1>(g, bc, a, mode, st);
-            case 2: return back_seg<2>(g, bc, a, mode, st);
-            case 4: return back_seg<4>(g, bc, a, mode, st);
-            case 8: return back_seg<8>(g, bc, a, mode, st);
+            case 1: return back_col4<1>(g, bc, a, mode, st);
+            case 2: return back_col4<2>(g, bc, a, mode, st);
+            case 4: return back_col4<4>(g, bc, a, mode, st);
+            case 8: return back_col4<8>(g, bc, a, mode, st);
             default: return hipErrorInvalidValue;
         }
     }

@@ -104,24 +104,37 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            // 16 samples at a time from the detector end: the chunk's loads precede its stores
+            // 16 samples (4 groups of 4, one 16-byte access each) at a time from the detector end:
+            // the chunk's loads precede its stores; padding rows get 0
+            constexpr int KG = kBandChunk / 4;
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(out, (unsigned)(4 * att_cs));
             const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
             Comp T{0.f, 0.f};
-            for (int kc = g.nt - 1; kc >= 0; kc -= kBandChunk) {
-                float mv[kBandChunk];
+            for (int kg0 = (g.nt - 1) >> 2; kg0 >= 0; kg0 -= KG) {
+                float4 mv[KG];
 #pragma unroll
-                for (int q = 0; q < kBandChunk; ++q) {
-                    const int k = kc - q;
-                    mv[q] = (k >= 0) ? buffer_ld(rs, roff + 4u * att_row(g, k)) : 0.f;
+                for (int j = 0; j < KG; ++j) {
+                    const int kg = kg0 - j;
+                    mv[j] = (kg >= 0) ? buffer_ld4(rs, roff + 4u * att_row(g, 4 * kg), 0u) : z4;
                 }
 #pragma unroll
-                for (int q = 0; q < kBandChunk; ++q) {
-                    const int k = kc - q;
-                    if (k < 0) break;
-                    const float L = g.dx * (fmaf(0.5f, mv[q], T.s) + T.e);
-                    buffer_st(rs, roff + 4u * att_row(g, k), 0u, expf(-L));
-                    comp_add(T, mv[q]);
+                for (int j = 0; j < KG; ++j) {
+                    const int kg = kg0 - j;
+                    if (kg < 0) break;
+                    float e[4];
+#pragma unroll
+                    for (int q = 3; q >= 0; --q) {
+                        const int k = 4 * kg + q;
+                        e[q] = 0.f;
+                        if (k < g.nt) {
+                            const float m = f4at(mv[j], q);
+                            const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
+                            e[q] = expf(-L);
+                            comp_add(T, m);
+                        }
+                    }
+                    buffer_st4(rs, roff + 4u * att_row(g, 4 * kg), 0u, make_float4(e[0], e[1], e[2], e[3]));
                 }
             }
         }
@@ -199,28 +212,33 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                     for (int q = 0; q < KG; ++q) cur[q] = nxt[q];
                 }
             } else {
-                // the ray's samples in this band, 16 at a time: the chunk's att loads are issued
-                // together, then used (one memory latency per chunk instead of per sample)
+                // the ray's samples in this band, 16 at a time from the 4-aligned group holding the
+                // first: the chunk's att loads (4 samples per 16-byte load) are issued together, then
+                // used; samples before the range are not the band's and fail the ownership test
                 int k0 = 0, k1 = g.nt - 1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
-                for (int kc = k0; kc <= k1; kc += kBandChunk) {
-                    float av[kBandChunk];
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                for (int kc = kstart; kc <= k1; kc += kBandChunk) {
+                    float4 av[kBandChunk / 4];
 #pragma unroll
-                    for (int q = 0; q < kBandChunk; ++q) {
-                        const int k = kc + q;
-                        av[q] = (k <= k1) ? buffer_ld(rs, roff + 4u * att_row(g, k)) : 0.f;
+                    for (int q = 0; q < kBandChunk / 4; ++q) {
+                        const int k = kc + 4 * q;
+                        av[q] = (k <= k1) ? buffer_ld4(rs, roff + 4u * att_row(g, k), 0u) : z4;
                     }
                     float part = 0.f;
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
                         const int k = kc + q;
-                        if (k > k1) break;
-                        float U, V;
-                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                        if (t.mine) part = fmaf(av[q], lerp2(lds + t.off, pitch, t.fu, t.fv), part);
+                        if (k <= k1) {  // a guard, not a break: the loop stays unrolled and av in registers
+                            float U, V;
+                            sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                            const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                            if (t.mine)
+                                part = fmaf(f4at(av[q >> 2], q & 3), lerp2(lds + t.off, pitch, t.fu, t.fv), part);
+                        }
                     }
                     kahan_add(c, part);
                 }
@@ -500,19 +518,23 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
             } else {
                 // the ray's samples in this band, 16 at a time (loads of att, and of att_bar when
                 // accumulating, issued together per chunk)
+                // from the 4-aligned group holding the first sample (16-byte loads); samples before the
+                // range fail the ownership test; stores stay per sample (a group can straddle bands)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)col0;
-                for (int kc = k0; kc <= k1; kc += kBandChunk) {
-                    float av[kBandChunk], bv[kBandChunk];
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                for (int kc = kstart; kc <= k1; kc += kBandChunk) {
+                    float4 av[kBandChunk / 4], bv[kBandChunk / 4];
 #pragma unroll
-                    for (int q = 0; q < kBandChunk; ++q) {
-                        const int k = kc + q;
+                    for (int q = 0; q < kBandChunk / 4; ++q) {
+                        const int k = kc + 4 * q;
                         const unsigned o = roff + 4u * att_row(g, k);
-                        av[q] = (k <= k1) ? buffer_ld(ra, o) : 0.f;
-                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld(rb, o) : 0.f;
+                        av[q] = (k <= k1) ? buffer_ld4(ra, o, 0u) : z4;
+                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld4(rb, o, 0u) : z4;
                     }
                     float part = 0.f;
 #pragma unroll
@@ -524,10 +546,11 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                         const Tap t = make_tap<false>(U, V, nf, pitch, band);
                         if (!t.mine) continue;
                         const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                        part = fmaf(av[q], w.x, part);
-                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, bv[q] + fmaf(rr, w.x, yp * w.y));
+                        part = fmaf(f4at(av[q >> 2], q & 3), w.x, part);
+                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, f4at(bv[q >> 2], q & 3) + fmaf(rr, w.x, yp * w.y));
                     }
-                    kahan_add(c, part);                }
+                    kahan_add(c, part);
+                }
             }
             acc[j] = c;
         }
@@ -632,16 +655,19 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                 }
             } else {
                 // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2), 16 samples at a time
+                // (from the 4-aligned group holding the first sample, 16-byte loads; stores per sample)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
-                for (int kc = k0; kc <= k1; kc += kBandChunk) {
-                    float bv[kBandChunk];
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                for (int kc = kstart; kc <= k1; kc += kBandChunk) {
+                    float4 bv[kBandChunk / 4];
 #pragma unroll
-                    for (int q = 0; q < kBandChunk; ++q) {
-                        const int k = kc + q;
-                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld(rb, roff + 4u * att_row(g, k)) : 0.f;
+                    for (int q = 0; q < kBandChunk / 4; ++q) {
+                        const int k = kc + 4 * q;
+                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld4(rb, roff + 4u * att_row(g, k), 0u) : z4;
                     }
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
@@ -652,7 +678,7 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                         const Tap t = make_tap<false>(U, V, nf, pitch, band);
                         if (!t.mine) continue;
                         const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, bv[q] + g.dx * fmaf(rho, w.y, w.x));
+                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, f4at(bv[q >> 2], q & 3) + g.dx * fmaf(rho, w.y, w.x));
                     }
                 }
             }
@@ -666,27 +692,34 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays) continue;
             const int a = ray / g.nb, b = ray - a * g.nb;
-            // 16 samples at a time: the chunk's loads are issued before any of its stores
+            // 16 samples (4 groups, one 16-byte access each) at a time: the chunk's loads are issued
+            // before any of its stores; padding rows get 0
             const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
             const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
             const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
             Comp P{0.f, 0.f};
             for (int kc = 0; kc < g.nt; kc += kBandChunk) {
-                float av[kBandChunk], bv[kBandChunk];
+                float4 av[kBandChunk / 4], bv[kBandChunk / 4];
 #pragma unroll
-                for (int q = 0; q < kBandChunk; ++q) {
-                    const int k = kc + q;
+                for (int q = 0; q < kBandChunk / 4; ++q) {
+                    const int k = kc + 4 * q;
                     const unsigned o = roff + 4u * att_row(g, k);
-                    av[q] = (k < g.nt) ? buffer_ld(ra, o) : 0.f;
-                    bv[q] = (k < g.nt) ? buffer_ld(rb, o) : 0.f;
+                    av[q] = (k < g.nt) ? buffer_ld4(ra, o, 0u) : z4;
+                    bv[q] = (k < g.nt) ? buffer_ld4(rb, o, 0u) : z4;
                 }
+                float ov[4];
 #pragma unroll
                 for (int q = 0; q < kBandChunk; ++q) {
                     const int k = kc + q;
-                    if (k >= g.nt) break;
-                    const float Lbar = -av[q] * bv[q];
-                    buffer_st(rb, roff + 4u * att_row(g, k), 0u, g.dx * (fmaf(0.5f, Lbar, P.s) + P.e));
-                    comp_add(P, Lbar);
+                    ov[q & 3] = 0.f;
+                    if (k < g.nt) {
+                        const float Lbar = -f4at(av[q >> 2], q & 3) * f4at(bv[q >> 2], q & 3);
+                        ov[q & 3] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
+                        comp_add(P, Lbar);
+                    }
+                    if ((q & 3) == 3 && k - 3 < g.nt)
+                        buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                 }
             }
         }
