@@ -83,15 +83,28 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
                     *reinterpret_cast<float4 *>(col + att_row(g, 4 * kg)) = make_float4(e[0], e[1], e[2], e[3]);
                 }
             } else {
-                // pass 1 of 2: store m_k of the samples in this band
+                // pass 1 of 2: store m_k of the samples in this band, a 4-sample group (one 16-byte
+                // load and store) at a time from the 4-aligned group holding the first. The ray is this
+                // thread's alone and its bands run in order, so a group's samples owned by another band
+                // are written back as loaded (values of an earlier band, or not yet written).
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
-                for (int k = k0; k <= k1; ++k) {
-                    float U, V;
-                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                    const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                    if (!t.mine) continue;
-                    col[att_row(g, k)] = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                for (int kg = kstart; kg <= k1; kg += 4) {
+                    float4 *grp = reinterpret_cast<float4 *>(col + att_row(g, kg));
+                    const float4 old = *grp;
+                    float ov[4] = {old.x, old.y, old.z, old.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = kg + q;
+                        if (k <= k1) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                            const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                            if (t.mine) ov[q] = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                        }
+                    }
+                    *grp = make_float4(ov[0], ov[1], ov[2], ov[3]);
                 }
             }
         }
@@ -518,8 +531,9 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
             } else {
                 // the ray's samples in this band, 16 at a time (loads of att, and of att_bar when
                 // accumulating, issued together per chunk)
-                // from the 4-aligned group holding the first sample (16-byte loads); samples before the
-                // range fail the ownership test; stores stay per sample (a group can straddle bands)
+                // from the 4-aligned group holding the first sample, 16-byte loads and stores; samples
+                // before the range fail the ownership test. The ray is this thread's alone and its bands
+                // run in order, so a group's samples owned by another band are written back as loaded.
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
@@ -534,20 +548,26 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                         const int k = kc + 4 * q;
                         const unsigned o = roff + 4u * att_row(g, k);
                         av[q] = (k <= k1) ? buffer_ld4(ra, o, 0u) : z4;
-                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld4(rb, o, 0u) : z4;
+                        bv[q] = (k <= k1) ? buffer_ld4(rb, o, 0u) : z4;
                     }
                     float part = 0.f;
+                    float ov[4];
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
                         const int k = kc + q;
-                        if (k > k1) break;
-                        float U, V;
-                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                        if (!t.mine) continue;
-                        const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                        part = fmaf(f4at(av[q >> 2], q & 3), w.x, part);
-                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, f4at(bv[q >> 2], q & 3) + fmaf(rr, w.x, yp * w.y));
+                        ov[q & 3] = f4at(bv[q >> 2], q & 3);
+                        if (k <= k1) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                            const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                            if (t.mine) {
+                                const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                                part = fmaf(f4at(av[q >> 2], q & 3), w.x, part);
+                                ov[q & 3] = (A.accumulate ? ov[q & 3] : 0.f) + fmaf(rr, w.x, yp * w.y);
+                            }
+                        }
+                        if ((q & 3) == 3 && k - 3 <= k1)
+                            buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     kahan_add(c, part);
                 }
@@ -655,7 +675,8 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                 }
             } else {
                 // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2), 16 samples at a time
-                // (from the 4-aligned group holding the first sample, 16-byte loads; stores per sample)
+                // (from the 4-aligned group holding the first sample, 16-byte loads and stores; samples of
+                // another band are written back as loaded, as in the sweep)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
                 const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
@@ -667,18 +688,24 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
 #pragma unroll
                     for (int q = 0; q < kBandChunk / 4; ++q) {
                         const int k = kc + 4 * q;
-                        bv[q] = (A.accumulate && k <= k1) ? buffer_ld4(rb, roff + 4u * att_row(g, k), 0u) : z4;
+                        bv[q] = (k <= k1) ? buffer_ld4(rb, roff + 4u * att_row(g, k), 0u) : z4;
                     }
+                    float ov[4];
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
                         const int k = kc + q;
-                        if (k > k1) break;
-                        float U, V;
-                        sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
-                        const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                        if (!t.mine) continue;
-                        const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                        buffer_st(rb, roff + 4u * att_row(g, k), 0u, f4at(bv[q >> 2], q & 3) + g.dx * fmaf(rho, w.y, w.x));
+                        ov[q & 3] = f4at(bv[q >> 2], q & 3);
+                        if (k <= k1) {
+                            float U, V;
+                            sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                            const Tap t = make_tap<false>(U, V, nf, pitch, band);
+                            if (t.mine) {
+                                const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
+                                ov[q & 3] = (A.accumulate ? ov[q & 3] : 0.f) + g.dx * fmaf(rho, w.y, w.x);
+                            }
+                        }
+                        if ((q & 3) == 3 && k - 3 <= k1)
+                            buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                 }
             }
