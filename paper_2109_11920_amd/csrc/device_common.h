@@ -232,18 +232,19 @@ struct Tap {
     float fu, fv;
     bool mine;
 };
+// The tap row floor(Vc) lies in [alo, ahi) exactly when Vc does (integer limits), so ownership is two
+// float compares; the offset (floor(Vc) - alo) pitch + floor(Uc) + 1 is formed exactly in float
+// (|value| < 2^24); fract(x) = x - floor(x) exactly.
 template <bool SINGLE>
 __device__ __forceinline__ Tap make_tap(float U, float V, float nf, int pitch, const Band &band) {
-    const float Uc = fminf(fmaxf(U, -1.f), nf);
-    const float Vc = fminf(fmaxf(V, -1.f), nf);
-    const float fl = floorf(Uc);
-    const float fi = floorf(Vc);
+    const float Uc = __builtin_amdgcn_fmed3f(U, -1.f, nf);
+    const float Vc = __builtin_amdgcn_fmed3f(V, -1.f, nf);
+    const float falo = (float)band.alo;
     Tap t;
-    t.fu = Uc - fl;
-    t.fv = Vc - fi;
-    const int i0 = (int)fi;
-    t.off = (i0 - band.alo) * pitch + ((int)fl + 1);
-    t.mine = SINGLE ? true : (i0 >= band.alo && i0 < band.ahi);
+    t.fu = __builtin_amdgcn_fractf(Uc);
+    t.fv = __builtin_amdgcn_fractf(Vc);
+    t.off = (int)fmaf(floorf(Vc) - falo, (float)pitch, floorf(Uc) + 1.f);
+    t.mine = SINGLE ? true : (Vc >= falo && Vc < (float)band.ahi);
     return t;
 }
 __device__ __forceinline__ float lerp2(const float *p, int pitch, float fu, float fv) {
