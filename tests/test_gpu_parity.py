@@ -28,8 +28,10 @@ def dev(x, dtype=None):
 
 GEOMS = [
     # (n, n_angles, n_bins, n_samples): ragged tiles (40 = 32 + 8), ragged ray chunks, nb != n, nt != n;
-    # bins and samples off the attenuation blocks (not multiples of 8 and 4); the slid-block gather
-    # (one-bin window, >= 32 bins and samples) with its block slid to the sinogram edges, and the
+    # bins and samples off the attenuation blocks (not multiples of 8 and 4: the ray kernels' 4-sample
+    # groups then hold padding rows); the slid-block gather (one-bin window, >= 32 bins and samples)
+    # with its block slid to the sinogram edges, column-group staged where the sample count is a
+    # multiple of 4 (40) and slot staged where it is not (70, 50), and the
     # general gather for a two-bin window (62 bins on 48 pixels) and for a sinogram narrower than the
     # 32-bin block (26 bins, 30 samples)
     (40, 24, 40, 40),
