@@ -10,7 +10,8 @@ Modules:
   head       Legendre outline, partial-volume attenuation map         (Eqs. 3-4)
   projector  attenuation scan, attenuated projector, exact transpose  (Eqs. 1-2)
   mlem       MLEM iterations, Poisson negative log-likelihood         (Eq. 5, BOAC step 3)
-  adjoint    exact reverse-mode gradient of J wrt (c_0..c_5, mu_b, mu_c), finite differences
+  adjoint    exact reverse-mode gradient of J wrt (c_0..c_5, mu_b, mu_c) and dR, the envelope
+             gradient (reconstruction held fixed), finite differences
   phantom    synthetic phantom and noisy sinogram                     (simulation study)
 
 Pins: every function is checked by tests/test_oracle_*.py against closed forms, exact special cases,
@@ -21,4 +22,5 @@ from .geometry import Geometry, angles, sampling_matrix, sample_image, sample_im
 from .head import coverage_fractions, head_radius, legendre_all, rasterize_mu, rasterize_mu_adjoint  # noqa: F401
 from .projector import attenuation, backproject, line_integrals, project, sensitivity  # noqa: F401
 from .mlem import evaluate, mlem, neg_log_likelihood  # noqa: F401
-from .adjoint import central_difference, objective_and_grad  # noqa: F401
+from .adjoint import (central_difference, envelope_objective, objective_and_envelope_grad,  # noqa: F401
+                      objective_and_grad)

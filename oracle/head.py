@@ -87,8 +87,10 @@ def rasterize_mu(g: Geometry, theta, delta_r: float) -> np.ndarray:
     return theta[6] * fb + theta[7] * (fo - fb)
 
 
-def rasterize_mu_adjoint(g: Geometry, theta, delta_r: float, mu_bar: np.ndarray) -> np.ndarray:
-    """Gradient of sum_j mu_bar_j mu_j(theta) with respect to theta (8 values)."""
+def rasterize_mu_adjoint(g: Geometry, theta, delta_r: float, mu_bar: np.ndarray,
+                         with_delta_r: bool = False) -> np.ndarray:
+    """Gradient of sum_j mu_bar_j mu_j(theta) with respect to theta (8 values), followed by its
+    derivative with respect to the cranium thickness dR when with_delta_r is set (9 values)."""
     theta = np.asarray(theta, dtype=np.float64)
     c, mu_b, mu_c = theta[:6], theta[6], theta[7]
     h = g.pixel / SUBSAMPLES
@@ -102,8 +104,11 @@ def rasterize_mu_adjoint(g: Geometry, theta, delta_r: float, mu_bar: np.ndarray)
     dmu_dR = ((mu_b - mu_c) * smooth_coverage_slope(d_b, h)
               + mu_c * smooth_coverage_slope(d_b + delta_r, h)) / d_b.shape[-1]
     weight = mu_bar[:, :, None] * dmu_dR              # [n, n, q]
-    grad = np.empty(8)
+    grad = np.empty(9 if with_delta_r else 8)
     grad[:6] = np.tensordot(P, weight, axes=([1, 2, 3], [0, 1, 2]))
     grad[6] = np.sum(mu_bar * fb)
     grad[7] = np.sum(mu_bar * (fo - fb))
+    if with_delta_r:
+        # dR enters only through fo: d mu_j / d dR = mu_c mean_q H'(d_b + dR)
+        grad[8] = mu_c * np.sum(mu_bar * smooth_coverage_slope(d_b + delta_r, h).mean(axis=-1))
     return grad

@@ -97,3 +97,76 @@ def test_planted_sign_error_in_ratio_adjoint_breaks_fd_pin(monkeypatch):
     monkeypatch.setattr(oracle.adjoint, "ratio", lambda m, y: -real(m, y))
     with pytest.raises(AssertionError):
         _pin_fd(g, S, theta, 2)
+
+
+# ---------------- dR derivative and the envelope gradient ----------------
+
+def test_raster_adjoint_delta_r_matches_central_differences():
+    g = oracle.Geometry(20, 4, 20, 20, 1.0)
+    theta = TRUE + np.array([0.2, 0.3, -0.4, 0.2, 0.1, -0.2, 0.01, 0.03])
+    mu_bar = np.random.default_rng(4).normal(size=(20, 20))
+    grad = oracle.rasterize_mu_adjoint(g, theta, 0.8, mu_bar, with_delta_r=True)
+    assert grad.shape == (9,)
+    np.testing.assert_array_equal(grad[:8], oracle.rasterize_mu_adjoint(g, theta, 0.8, mu_bar))
+    h = 1e-5
+    fd = (np.sum(mu_bar * oracle.rasterize_mu(g, theta, 0.8 + h))
+          - np.sum(mu_bar * oracle.rasterize_mu(g, theta, 0.8 - h))) / (2 * h)
+    assert grad[8] == pytest.approx(fd, rel=1e-6)
+    # dR moves only the outer edge, whose attenuation is mu_c: a zero cranium coefficient removes it
+    th0 = theta.copy()
+    th0[7] = 0.0
+    assert oracle.rasterize_mu_adjoint(g, th0, 0.8, mu_bar, with_delta_r=True)[8] == 0.0
+
+
+@pytest.mark.parametrize("n_iter", [0, 3])
+def test_delta_r_gradient_matches_central_differences(n_iter):
+    g, S, theta = _problem(n=20, na=16, seed=11 + n_iter)
+    J, grad = oracle.objective_and_grad(g, S, theta, 0.8, n_iter, with_delta_r=True)
+    J8, grad8 = oracle.objective_and_grad(g, S, theta, 0.8, n_iter)
+    assert J == J8
+    np.testing.assert_array_equal(grad[:8], grad8)
+    fd = oracle.central_difference(lambda d: oracle.evaluate(g, S, theta, float(d[0]), n_iter)[0],
+                                   np.array([0.8]), rel_step=1e-4, richardson=True)[0]
+    assert grad[8] == pytest.approx(fd, rel=1e-6)
+
+
+def test_envelope_gradient_matches_central_differences_with_image_fixed():
+    g, S, theta = _problem(n=20, na=16, seed=5)
+    n_iter = 3
+    J, grad = oracle.objective_and_envelope_grad(g, S, theta, 0.8, n_iter, with_delta_r=True)
+    J_full, _ = oracle.objective_and_grad(g, S, theta, 0.8, n_iter)
+    assert J == pytest.approx(J_full, rel=1e-14)
+    fK = oracle.evaluate(g, S, theta, 0.8, n_iter)[1]
+    th9 = np.concatenate([theta, [0.8]])
+    fd = oracle.central_difference(
+        lambda t: oracle.envelope_objective(g, S, t[:8], float(t[8]), fK), th9, rel_step=1e-4, richardson=True)
+    assert np.linalg.norm(fd - grad) / np.linalg.norm(grad) < 1e-6, (fd, grad)
+
+
+def test_envelope_gradient_equals_unrolled_gradient_without_iterations():
+    # with K = 0 the reconstruction is F^0 = 1, which does not depend on theta: both gradients agree
+    g, S, theta = _problem(n=16, na=12, seed=6)
+    J1, g1 = oracle.objective_and_grad(g, S, theta, 0.8, 0, with_delta_r=True)
+    J2, g2 = oracle.objective_and_envelope_grad(g, S, theta, 0.8, 0, with_delta_r=True)
+    assert J1 == J2
+    np.testing.assert_allclose(g2, g1, rtol=1e-12, atol=1e-12 * np.linalg.norm(g1))
+
+
+def test_envelope_gradient_differs_from_unrolled_gradient_after_iterations():
+    # the image's own dependence on theta is what the envelope variant drops
+    g, S, theta = _problem(n=16, na=12, seed=6)
+    _, g1 = oracle.objective_and_grad(g, S, theta, 0.8, 4)
+    _, g2 = oracle.objective_and_envelope_grad(g, S, theta, 0.8, 4)
+    assert np.linalg.norm(g2 - g1) / np.linalg.norm(g1) > 1e-3
+
+
+def test_planted_stale_image_breaks_envelope_fd_pin(monkeypatch):
+    # an envelope gradient taken at F^{K-1} instead of F^K must fail the fixed-image FD pin
+    g, S, theta = _problem(n=16, na=12, seed=8)
+    real = oracle.adjoint.mlem
+    monkeypatch.setattr(oracle.adjoint, "mlem", lambda gg, att, m, k: real(gg, att, m, max(k - 1, 0)))
+    _, grad = oracle.objective_and_envelope_grad(g, S, theta, 0.8, 3)
+    fK = oracle.evaluate(g, S, theta, 0.8, 3)[1]
+    fd = oracle.central_difference(lambda t: oracle.envelope_objective(g, S, t, 0.8, fK), theta,
+                                   rel_step=1e-4, richardson=True)
+    assert np.linalg.norm(fd - grad) / np.linalg.norm(grad) > 1e-4
