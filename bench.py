@@ -290,6 +290,21 @@ def main():
                        "grad_over_forward": round(grad_ms / fwd_ms, 3),
                        "what": "64 candidates, 20 iterations, checkpoint every 5"}
 
+        # ---- envelope gradient (reconstruction held fixed) with dJ/d(dR), same 64 candidates
+        ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            _, Ge, _ = ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(Ge).all())
+        env_ms = e0.elapsed_time(e1) / reps
+        out["grad_envelope"] = {"value": round(cg.shape[0] / (env_ms / 1e3), 1), "unit": "obj+grad evals/s",
+                                "ms_per_batch": round(env_ms, 3), "grad_over_forward": round(env_ms / fwd_ms, 3),
+                                "what": "64 candidates, 20 iterations, envelope gradient (F^K held fixed) "
+                                        "with dJ/d(dR)"}
+
     if not args.only_main and not args.no_uneven:
         out["uneven48"] = uneven_line(ctx, dev)
 

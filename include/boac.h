@@ -132,6 +132,24 @@ boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const floa
                                 int32_t ckpt_every, float *d_obj, float *d_grad, uint32_t *d_status,
                                 void *stream);
 
+/* Gradient variants of boac_objective_grad_ex. */
+#define BOAC_GRAD_UNROLLED 0 /* exact derivative through the n_iter unrolled MLEM iterations */
+#define BOAC_GRAD_ENVELOPE 1 /* derivative with the reconstruction F^K held fixed */
+
+/* Objective and a gradient that also covers the cranium thickness dR (the last of 9 components).
+ * grad_mode BOAC_GRAD_UNROLLED: the exact derivative, as boac_objective_grad (ckpt_every as there).
+ * grad_mode BOAC_GRAD_ENVELOPE: the derivative of the joint objective of Eq. (6), -ln P(S | F, A^mu(theta)),
+ *   in theta at F = F^K(theta), with F^K treated as a constant: the envelope-theorem gradient, exact when
+ *   F^K maximises the likelihood for this attenuation map, an approximation of the unrolled gradient after
+ *   finitely many iterations. It costs one projection adjoint after the objective (ckpt_every is
+ *   validated but unused).
+ * d_obj [C] out; d_grad [C][9] out (order c_0..c_5, mu_b, mu_c, dR); d_status [C] or NULL. Any other
+ * grad_mode is BOAC_EINVAL. */
+boac_status boac_objective_grad_ex(boac_ctx *ctx, const boac_geom *geom, const float *d_meas,
+                                   const boac_cand *d_cand, int32_t C, float delta_r_cm, int32_t n_iter,
+                                   int32_t ckpt_every, int32_t grad_mode, float *d_obj, float *d_grad,
+                                   uint32_t *d_status, void *stream);
+
 /* One slice of an uneven batch: its geometry, measured sinogram and candidates, and where results go
  * (all device pointers; d_grad NULL = objective only; d_status may be NULL). */
 typedef struct {

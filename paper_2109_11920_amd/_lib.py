@@ -44,6 +44,8 @@ _SIGNATURES = {
                                  _P]),
     "boac_objective_grad": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, c_int32,
                                       _P, _P, _P, _P]),
+    "boac_objective_grad_ex": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, c_int32,
+                                         c_int32, _P, _P, _P, _P]),
     "boac_evaluate_batch": (c_int32, [_P, ctypes.POINTER(BoacSlice), c_int32, c_float, c_int32, c_int32, _P]),
     "boac_ctx_set_profiling": (c_int32, [_P, c_int32]),
     "boac_ctx_kernel_stats": (c_int32, [_P, c_int32, ctypes.POINTER(ctypes.c_int64),

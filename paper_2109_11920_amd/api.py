@@ -19,6 +19,8 @@ STATUS_NONFINITE = 2
 STATUS_NEGATIVE_RADIUS = 4
 STATUS_NEGATIVE_COUNTS = 8
 
+GRAD_MODES = {"unrolled": 0, "envelope": 1}
+
 
 @dataclass(frozen=True)
 class Geometry:
@@ -154,6 +156,25 @@ class Context:
                                            _ptr(grad, "grad", shape=(C, 8)),
                                            _ptr(status, "status", dtype=torch.int32, shape=(C,)),
                                            _stream(self.device)))
+        return obj, grad, status
+
+    def objective_grad_ex(self, geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, delta_r: float,
+                          n_iter: int, ckpt_every: int = 5, mode: str = "unrolled", obj=None, grad=None, status=None):
+        """Returns (J [C], dJ/d(c_0..c_5, mu_b, mu_c, dR) [C, 9], status [C] int32). mode "unrolled": the
+        exact gradient through the MLEM iterations; "envelope": the reconstruction F^K held fixed."""
+        if mode not in GRAD_MODES:
+            raise ValueError(f"mode must be one of {sorted(GRAD_MODES)}")
+        C = cand.shape[0]
+        obj = obj if obj is not None else torch.empty(C, device=self.device)
+        grad = grad if grad is not None else torch.empty((C, 9), device=self.device)
+        status = status if status is not None else torch.empty(C, device=self.device, dtype=torch.int32)
+        check(self.lib.boac_objective_grad_ex(self.handle, ctypes.byref(geom.c()),
+                                              _ptr(meas, "meas", shape=geom.sino_shape),
+                                              _ptr(cand, "cand", shape=(C, 8)), C, float(delta_r), int(n_iter),
+                                              int(ckpt_every), GRAD_MODES[mode], _ptr(obj, "obj", shape=(C,)),
+                                              _ptr(grad, "grad", shape=(C, 9)),
+                                              _ptr(status, "status", dtype=torch.int32, shape=(C,)),
+                                              _stream(self.device)))
         return obj, grad, status
 
     def evaluate_batch(self, slices: Sequence["SliceBatch"], delta_r: float, n_iter: int, ckpt_every: int = 5):

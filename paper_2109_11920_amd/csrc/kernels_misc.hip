@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restri
     if (status && (neg || !finite)) atomicOr(status + cidx, (neg ? 4u : 0u) | (finite ? 0u : 2u));
 }
 
-// grad_k = sum_j mubar_j dmu_j/dtheta_k, one workgroup per candidate, compensated per component.
+// grad_k = sum_j mubar_j dmu_j/dtheta_k for theta = (c_0..c_5, mu_b, mu_c, dR), one workgroup per
+// candidate, compensated per component; written as 9 values per candidate.
 __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__restrict__ cand, float delta_r,
                                                     const float *__restrict__ mubar, size_t img_cs,
                                                     float *__restrict__ grad) {
@@ -84,15 +85,15 @@ __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__re
     const float *th = cand + (size_t)cidx * 8;
     const float mub = th[6], muc = th[7];
     const float inv_h = 4.f / g.dx;
-    Comp acc[8];
+    Comp acc[kGradComps];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = Comp{0.f, 0.f};
+    for (int k = 0; k < kGradComps; ++k) acc[k] = Comp{0.f, 0.f};
     const float *mb = mubar + (size_t)cidx * img_cs;
     for (int pix = threadIdx.x; pix < g.n * g.n; pix += blockDim.x) {
         const float w = mb[pix];
         const int i = pix / g.n, l = pix - i * g.n;
         float gP[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        float fb = 0.f, fo = 0.f;
+        float fb = 0.f, fo = 0.f, so = 0.f;
 #pragma unroll
         for (int p = 0; p < kSub; ++p)
 #pragma unroll
@@ -106,7 +107,9 @@ __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__re
                 const float db = R - s.r;
                 fb += coverage(db, inv_h);
                 fo += coverage(db + delta_r, inv_h);
-                const float dmu_dR = fmaf(mub - muc, coverage_slope(db, inv_h), muc * coverage_slope(db + delta_r, inv_h));
+                const float slope_o = coverage_slope(db + delta_r, inv_h);
+                so += slope_o;
+                const float dmu_dR = fmaf(mub - muc, coverage_slope(db, inv_h), muc * slope_o);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) gP[k] = fmaf(dmu_dR, P[k], gP[k]);
             }
@@ -114,10 +117,12 @@ __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__re
         for (int k = 0; k < 6; ++k) comp_add(acc[k], w * gP[k] * (1.f / 16.f));
         comp_add(acc[6], w * fb * (1.f / 16.f));
         comp_add(acc[7], w * (fo - fb) * (1.f / 16.f));
+        // dR moves only the outer edge: d mu / d dR = mu_c mean H'(d_b + dR)
+        comp_add(acc[8], w * muc * so * (1.f / 16.f));
     }
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < kGradComps; ++k) {
         const Comp r = block_reduce(acc[k], red);
-        if (threadIdx.x == 0) grad[(size_t)cidx * 8 + k] = comp_value(r);
+        if (threadIdx.x == 0) grad[(size_t)cidx * kGradComps + k] = comp_value(r);
     }
 }
 
@@ -204,19 +209,22 @@ __global__ void k_adj_elem(AdjElemArgs A) {
     }
 }
 
-__global__ void k_pack_pair(const float *a, float b_const, float2 *out, size_t count) {
+// (a, b) pairs; a NULL image stands for its constant
+__global__ void k_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-        out[i] = make_float2(a[i], b_const);
+        out[i] = make_float2(a ? a[i] : a_const, b ? b[i] : b_const);
 }
 
-__global__ void k_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status) {
+// Copies the first ncomp of the kGradComps raster-adjoint components per candidate; status bit 2 if
+// any copied value is not finite.
+__global__ void k_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     bool bad = false;
-    for (int k = 0; k < 8; ++k) {
-        const float v = grad[(size_t)c * 8 + k];
+    for (int k = 0; k < ncomp; ++k) {
+        const float v = grad[(size_t)c * kGradComps + k];
         bad |= !isfinite(v);
-        d_grad[(size_t)c * 8 + k] = v;
+        d_grad[(size_t)c * ncomp + k] = v;
     }
     if (bad && status) status[c] |= 2u;
 }
@@ -280,12 +288,14 @@ hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_elem, dim3(fill_blocks((size_t)a.npix * a.C)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
-hipError_t launch_pack_pair(const float *a, float b_const, float2 *out, size_t count, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack_pair, dim3(fill_blocks(count)), dim3(256), 0, st, a, b_const, out, count);
+hipError_t launch_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_pair, dim3(fill_blocks(count)), dim3(256), 0, st, a, a_const, b, b_const, out, count);
     return hipGetLastError();
 }
-hipError_t launch_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, grad, C, d_grad, status);
+hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, grad, C, ncomp, d_grad,
+                       status);
     return hipGetLastError();
 }
 

@@ -105,9 +105,13 @@ struct AdjElemArgs {
     int npix, C;
 };
 
+// Raster-adjoint components per candidate: c_0..c_5, mu_b, mu_c, dR.
+constexpr int kGradComps = 9;
+
 // ---- launchers (each returns the hipError_t of the launch) ----
 hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta_r, float *mu, size_t img_cs,
                          uint32_t *status, hipStream_t st);
+// grad: [C][kGradComps] partial gradients
 hipError_t launch_raster_adj(const DevGeom &g, const float *cand, int C, float delta_r, const float *mubar,
                              size_t img_cs, float *grad, hipStream_t st);
 hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
@@ -116,7 +120,8 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
                       hipStream_t st);
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
                             hipStream_t st);
-hipError_t launch_pack_pair(const float *a, float b_const, float2 *out, size_t count, hipStream_t st);
+hipError_t launch_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count,
+                            hipStream_t st);
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st);
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st);
@@ -126,7 +131,7 @@ hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t
 hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
                              float *obj, uint32_t *status, hipStream_t st);
 hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st);
-hipError_t launch_grad_finish(const float *grad, int C, float *d_grad, uint32_t *status, hipStream_t st);
+hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status, hipStream_t st);
 hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st);
 hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st);
 hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,

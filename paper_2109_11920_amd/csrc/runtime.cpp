@@ -594,13 +594,16 @@ static int cand_chunk(const Sizes &z, int C, int tensors) {
     return std::min(m, C);
 }
 
-// Forward evaluation of C candidates of one slice (scratch suffix distinguishes concurrent users).
+// Forward evaluation of C candidates of one slice. With env_grad set, also the envelope gradient:
+// dJ/dtheta with the reconstruction F^K held fixed (one projection adjoint after the objective),
+// ncomp components per candidate (8, or 9 with dR).
 static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
-                                float delta_r, int K, float *obj, float *img_out, uint32_t *status, hipStream_t st) {
+                                float delta_r, int K, float *obj, float *img_out, uint32_t *status, hipStream_t st,
+                                float *env_grad = nullptr, int ncomp = 8) {
     const Sizes z = sizes_of(g);
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, g, &dg));
-    const int Cc = cand_chunk(z, C, 1);
+    const int Cc = cand_chunk(z, C, env_grad ? 2 : 1);
     Plan p;
     BOAC_TRY(make_plan(ctx, g, Cc, &p));
     float *mu, *att, *s, *F0, *F1, *r;
@@ -616,6 +619,16 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
     BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
     BOAC_TRY(ensure_t(ctx, "status_int", (size_t)C, &st_int));
+    float *attbar = nullptr, *yK = nullptr, *ybar = nullptr, *mubar = nullptr, *gtmp = nullptr;
+    float2 *pair = nullptr;
+    if (env_grad) {
+        BOAC_TRY(ensure_t(ctx, "attbar", (size_t)Cc * z.VS, &attbar));
+        BOAC_TRY(ensure_t(ctx, "yK", (size_t)Cc * z.Y, &yK));
+        BOAC_TRY(ensure_t(ctx, "ybar", (size_t)Cc * z.Y, &ybar));
+        BOAC_TRY(ensure_t(ctx, "mubar", (size_t)Cc * z.I, &mubar));
+        BOAC_TRY(ensure_t(ctx, "gtmp", (size_t)Cc * kGradComps, &gtmp));
+        BOAC_TRY(ensure_t(ctx, "pair", (size_t)Cc * z.I, &pair));
+    }
     uint32_t *stat = status ? status : st_int;
 
     HIP_TRY(launch_fill_u32(flag, 4, 0u, st));
@@ -648,18 +661,47 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
         FwdArgs a = fwd_args(z, att, Fc, meas);
         a.partial = partial;
         a.status = stat + c0;
+        a.y_out = yK;
         BOAC_TRY(run_fwd(ctx, FWD_NLL, dg, p, z, a, n, st));
         BOAC_TRY(timed(ctx, BOAC_K_REDUCE, 8.0 * n * p.ray1.chunks, st, [&] {
             return launch_nll_finish(partial, p.ray1.chunks, n, lg, flag, obj + c0, stat + c0, st);
         }));
         if (img_out) HIP_TRY(launch_copy(Fc, img_out + (size_t)c0 * z.I, (size_t)n * z.I, st));
+        if (env_grad) {
+            // y = A F^K with F^K constant: att_bar = dx ybar (W F^K), then the scan and exp transposes
+            // (the tail with a zero first image and rho = ybar), mu_bar = W^T m_bar, raster adjoint
+            const size_t nI = (size_t)n * z.I, nY = (size_t)n * z.Y;
+            BOAC_TRY(timed(ctx, BOAC_K_OTHER, 12.0 * nY, st,
+                           [&] { return launch_ybar_final(meas, yK, ybar, n, (int)z.Y, z.Y, st); }));
+            HIP_TRY(launch_pack_pair(nullptr, 0.f, Fc, 0.f, pair, nI, st));
+            TailArgs ta{};
+            ta.att = att;
+            ta.attbar = attbar;
+            ta.pair = (const float *)pair;
+            ta.rho = ybar;
+            ta.att_cs = z.VS;
+            ta.img_cs = 2 * z.I;
+            ta.sino_cs = z.Y;
+            ta.accumulate = 0;
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (2.0 * z.V + 2 * z.I + z.Y), st,
+                           [&] { return launch_tail(dg, p.ray2, p.bands2, ta, n, st); }));
+            BackArgs b = back_args(z, att, attbar, mubar, n);
+            BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * z.I, st,
+                           [&] { return launch_raster_adj(dg, cd, n, delta_r, mubar, z.I, gtmp, st); }));
+            BOAC_TRY(timed(ctx, BOAC_K_OTHER, 4.0 * n * (kGradComps + ncomp), st, [&] {
+                return launch_grad_finish(gtmp, n, ncomp, env_grad + (size_t)c0 * ncomp, stat + c0, st);
+            }));
+        }
     }
     return BOAC_OK;
 }
 
 // Objective and gradient of C candidates of one slice.
+// ncomp gradient components per candidate: 8, or 9 with dR.
 static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
-                             float delta_r, int K, int ck, float *obj, float *grad, uint32_t *status, hipStream_t st) {
+                             float delta_r, int K, int ck, float *obj, float *grad, uint32_t *status, hipStream_t st,
+                             int ncomp = 8) {
     const Sizes z = sizes_of(g);
     DevGeom dg;
     BOAC_TRY(dev_geom(ctx, g, &dg));
@@ -683,7 +725,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     BOAC_TRY(ensure_t(ctx, "fbar", (size_t)Cc * I, &fbar));
     BOAC_TRY(ensure_t(ctx, "fdir", (size_t)Cc * I, &fdir));
     BOAC_TRY(ensure_t(ctx, "mubar", (size_t)Cc * I, &mubar));
-    BOAC_TRY(ensure_t(ctx, "gtmp", (size_t)Cc * 8, &gtmp));
+    BOAC_TRY(ensure_t(ctx, "gtmp", (size_t)Cc * kGradComps, &gtmp));
     BOAC_TRY(ensure_t(ctx, "yK", (size_t)Cc * Y, &yK));
     BOAC_TRY(ensure_t(ctx, "ybar", (size_t)Cc * Y, &ybar));
     BOAC_TRY(ensure_t(ctx, "ybar2", (size_t)Cc * Y, &ybar2));
@@ -836,7 +878,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
         // ---- tail: sensitivity adjoint and the pending projection adjoint (with F^0 = 1), exp and
         // scan transposes, mu_bar, raster adjoint
         {
-            HIP_TRY(launch_pack_pair(sbar, 1.f, pair, nI, st));
+            HIP_TRY(launch_pack_pair(sbar, 0.f, nullptr, 1.f, pair, nI, st));
             TailArgs ta{};
             ta.att = att;
             ta.attbar = attbar;
@@ -852,8 +894,9 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
             BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
             BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * I, st,
                            [&] { return launch_raster_adj(dg, cd, n, delta_r, mubar, I, gtmp, st); }));
-            BOAC_TRY(timed(ctx, BOAC_K_OTHER, 64.0 * n, st,
-                           [&] { return launch_grad_finish(gtmp, n, grad + (size_t)c0 * 8, stat + c0, st); }));
+            BOAC_TRY(timed(ctx, BOAC_K_OTHER, 4.0 * n * (kGradComps + ncomp), st, [&] {
+                return launch_grad_finish(gtmp, n, ncomp, grad + (size_t)c0 * ncomp, stat + c0, st);
+            }));
         }
     }
     return BOAC_OK;
@@ -1110,6 +1153,30 @@ boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const floa
     CTX_CHECK();
     return eval_grad(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, ckpt_every, d_obj, d_grad,
                      d_status, (hipStream_t)stream);
+}
+
+boac_status boac_objective_grad_ex(boac_ctx *ctx, const boac_geom *geom, const float *d_meas,
+                                   const boac_cand *d_cand, int32_t C, float delta_r_cm, int32_t n_iter,
+                                   int32_t ckpt_every, int32_t grad_mode, float *d_obj, float *d_grad,
+                                   uint32_t *d_status, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_meas, "d_meas"));
+    BOAC_TRY(check_ptr(d_cand, "d_cand"));
+    BOAC_TRY(check_ptr(d_obj, "d_obj"));
+    BOAC_TRY(check_ptr(d_grad, "d_grad"));
+    BOAC_TRY(check_ptr(d_status, "d_status", true));
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    if (ckpt_every < 1) return fail(BOAC_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    if (grad_mode != BOAC_GRAD_UNROLLED && grad_mode != BOAC_GRAD_ENVELOPE)
+        return fail(BOAC_EINVAL, "grad_mode = %d is neither BOAC_GRAD_UNROLLED nor BOAC_GRAD_ENVELOPE", grad_mode);
+    CTX_CHECK();
+    if (grad_mode == BOAC_GRAD_ENVELOPE)
+        return eval_forward(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, d_obj, nullptr,
+                            d_status, (hipStream_t)stream, d_grad, 9);
+    return eval_grad(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, ckpt_every, d_obj, d_grad,
+                     d_status, (hipStream_t)stream, 9);
 }
 
 // Relative cost of a slice (algorithmic attenuation-tensor passes x tensor size x candidates).

@@ -63,6 +63,11 @@ def test_bad_counts_and_pointers(lib):
     assert lib.boac_objective_grad(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.8, 5, 0, ALIGNED, ALIGNED,
                                    None, None) == 1
     assert lib.boac_rasterize_mu(None, None, ALIGNED, 1, 0.8, ALIGNED, None) == 1
+    assert lib.boac_objective_grad_ex(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.8, 5, 5, 2, ALIGNED, ALIGNED,
+                                      None, None) == 1
+    assert b"grad_mode" in lib.boac_last_error()
+    assert lib.boac_objective_grad_ex(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.8, 5, 5, 1, ALIGNED, None,
+                                      None, None) == 1
 
 
 def test_null_context_after_valid_arguments(lib):

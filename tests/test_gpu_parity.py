@@ -250,6 +250,59 @@ def test_objective_grad_small(ctx, shape, K):
         report(f"grad {shape} K={K} cand {c} dJ", G[c], Gr, TOL_GRAD)
 
 
+@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 4), ((48, 20, 62, 48), 3), ((70, 30, 70, 70), 2),
+                                     ((192, 12, 192, 192), 2), ((32, 16, 32, 32), 0)])
+def test_envelope_gradient(ctx, shape, K):
+    # reconstruction held fixed at F^K; 9 components (dR last). n = 192 takes the row-band tail.
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=23)
+    th = cands(24, 3)
+    th[1] = f32(th[1] + np.array([0.3, 0.2, -0.2, 0.1, 0.1, -0.1, 0.01, -0.02]))
+    J, G, st = ctx.objective_grad_ex(g, dev(S), dev(th), DR, K, 5, mode="envelope")
+    Jf, _, _ = ctx.objective(g, dev(S), dev(th), DR, K)
+    assert torch.equal(J, Jf)
+    J = J.cpu().numpy()
+    G = G.cpu().numpy()
+    assert G.shape == (3, 9)
+    for c in range(3):
+        Jr, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, K, with_delta_r=True)
+        report(f"envelope {shape} K={K} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        print("   gpu   ", np.array2string(G[c], precision=5), "\n   oracle", np.array2string(Gr, precision=5))
+        report(f"envelope {shape} K={K} cand {c} dJ", G[c], Gr, TOL_GRAD)
+
+
+def test_unrolled_gradient_with_delta_r(ctx):
+    g, og = geom_pair(40, 24)
+    S, _ = make_slice(og, seed=25)
+    th = dev(cands(26, 3))
+    J9, G9, _ = ctx.objective_grad_ex(g, dev(S), th, DR, 3, 2, mode="unrolled")
+    J8, G8, _ = ctx.objective_grad(g, dev(S), th, DR, 3, 2)
+    assert torch.equal(J9, J8) and torch.equal(G9[:, :8], G8)
+    G9 = G9.cpu().numpy()
+    for c in range(3):
+        _, Gr = oracle.objective_and_grad(og, S, th[c].cpu().numpy().astype(np.float64), DR, 3, with_delta_r=True)
+        report(f"unrolled+dR cand {c} dJ", G9[c], Gr, TOL_GRAD)
+        report(f"unrolled+dR cand {c} dJ/d(dR)", G9[c, 8:], Gr[8:], TOL_GRAD)
+    with pytest.raises(Exception):
+        ctx.objective_grad_ex(g, dev(S), th, DR, 3, 2, mode="nope")
+
+
+def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
+    # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
+    g, og = geom_pair(128, 128, pixel=0.2)
+    S = slice128["meas"].astype(np.float64)
+    import synth
+    th = f32(synth.draw_candidates(synth.candidate_stream(1), 64))
+    J, G, st = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 20, 5, mode="envelope")
+    J = J.cpu().numpy()
+    G = G.cpu().numpy()
+    assert np.all(np.isfinite(G))
+    for c in (3, 50):
+        Jr, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 20, with_delta_r=True)
+        report(f"envelope64 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"envelope64 dJ cand {c}", G[c], Gr, TOL_GRAD)
+
+
 def test_checkpoint_interval_does_not_change_results(ctx):
     g, og = geom_pair(40, 24)
     S, _ = make_slice(og, seed=19)
