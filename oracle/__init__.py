@@ -13,6 +13,7 @@ Modules:
   adjoint    exact reverse-mode gradient of J wrt (c_0..c_5, mu_b, mu_c) and dR, the envelope
              gradient (reconstruction held fixed), finite differences
   phantom    synthetic phantom and noisy sinogram                     (simulation study)
+  bo         GP surrogate, expected improvement, chaotic search       (Eqs. 7-10, BOAC steps 4-6)
 
 Pins: every function is checked by tests/test_oracle_*.py against closed forms, exact special cases,
 library routines and brute force. The comparison of BOAC with the paper's own Table I is
