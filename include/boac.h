@@ -169,6 +169,42 @@ typedef struct {
 boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
                                 int32_t n_iter, int32_t ckpt_every, void *stream);
 
+/* ---- Surrogate model of the BOAC outer loop (Eqs. 7-10) ----
+ * The negative log-likelihood J of a candidate is modelled as a Gaussian process (Eq. 7) over unit-box
+ * coordinates u (the search box mapped affinely onto [0,1]^d) with the RBF kernel of Eq. (8) read as
+ * k(u, u') = amp exp(-|u - u'|^2 / (2 length^2)) (the printed names of amplitude and length-scale are
+ * swapped). Targets are standardised, z = (J - m0) / s (sample mean; sample standard deviation, 1 if
+ * it is 0), amp = 1 in those units, and a nugget `noise` is added to the diagonal. Expected improvement
+ * (Eqs. 9-10) is taken for minimisation: gamma = (J_best - mu - xi) / sigma. FP64 throughout. */
+typedef struct {
+    int32_t n, d;   /* observations, input dimension */
+    double length;  /* selected RBF length-scale (unit-box units) */
+    double amp;     /* kernel amplitude (1) */
+    double noise;   /* nugget */
+    double m0, s;   /* target standardisation */
+    double lml;     /* log marginal likelihood of the final fit (all n observations) */
+} boac_gp_info;
+
+/* Host-only (no device work, no context): fit the surrogate to n observations.
+ * h_u [n][d] unit-box inputs, h_y [n] objective values; h_lengths [n_lengths] candidate length-scales,
+ * the selected one maximises the log marginal likelihood (first on ties) over the n_select observations
+ * of smallest y (ties by index; n_select <= 0 or >= n: all); the final factor uses all n.
+ * Outputs: h_linv [n][n] = L^-1 for K = L L^T (row-major, upper triangle zero), h_alpha [n] = K^-1 z,
+ * *info. 1 <= n <= 8192, 1 <= d <= 64, noise >= 0. BOAC_EINVAL if no grid length gives a positive
+ * definite covariance (raise noise). */
+boac_status boac_gp_fit(const double *h_u, const double *h_y, int32_t n, int32_t d, const double *h_lengths,
+                        int32_t n_lengths, int32_t n_select, double noise, double *h_linv, double *h_alpha,
+                        boac_gp_info *info);
+
+/* Device: posterior mean, standard deviation (of J, not z) and expected improvement at M queries.
+ * *info as returned by boac_gp_fit; d_u [n][d], d_linv [n][n], d_alpha [n]: device copies of the fit;
+ * d_q [M][d] queries in unit-box coordinates; best = J_best; xi >= 0 exploration margin.
+ * d_mu [M], d_sigma [M] out or NULL; d_ei [M] out. 1 <= M <= 2^20. Scratch ((n rounded up to 64) + n/64)
+ * x M doubles lives in the context. Asynchronous on stream. */
+boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                       const double *d_alpha, const double *d_q, int32_t M, double best, double xi, double *d_mu,
+                       double *d_sigma, double *d_ei, void *stream);
+
 /* Kernel-time instrumentation: when enabled, every launch is bracketed by HIP events on its stream
  * and its duration is accumulated per kernel kind after the caller synchronises. */
 typedef enum {
@@ -180,7 +216,8 @@ typedef enum {
     BOAC_K_ADJ_RAY = 5,
     BOAC_K_ADJ_PIX = 6,
     BOAC_K_OTHER = 7,
-    BOAC_K_COUNT = 8
+    BOAC_K_GP = 8, /* surrogate acquisition (boac_gp_ei) */
+    BOAC_K_COUNT = 9
 } boac_kernel_kind;
 
 boac_status boac_ctx_set_profiling(boac_ctx *ctx, int32_t enable);

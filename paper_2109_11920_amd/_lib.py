@@ -28,7 +28,14 @@ class BoacSlice(ctypes.Structure):
 STATUS_NAMES = {0: "BOAC_OK", 1: "BOAC_EINVAL", 2: "BOAC_ESHAPE", 3: "BOAC_ENOMEM", 4: "BOAC_EDEVICE",
                 5: "BOAC_ETIMEOUT", 6: "BOAC_ENOTSUP"}
 
-KERNEL_KINDS = {"raster": 0, "att": 1, "fwd": 2, "back": 3, "reduce": 4, "adj_ray": 5, "adj_pix": 6, "other": 7}
+KERNEL_KINDS = {"raster": 0, "att": 1, "fwd": 2, "back": 3, "reduce": 4, "adj_ray": 5, "adj_pix": 6, "other": 7,
+                "gp": 8}
+
+
+class BoacGpInfo(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("d", c_int32), ("length", ctypes.c_double), ("amp", ctypes.c_double),
+                ("noise", ctypes.c_double), ("m0", ctypes.c_double), ("s", ctypes.c_double),
+                ("lml", ctypes.c_double)]
 
 _P = c_void_p
 _SIGNATURES = {
@@ -47,6 +54,10 @@ _SIGNATURES = {
     "boac_objective_grad_ex": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, c_int32,
                                          c_int32, _P, _P, _P, _P]),
     "boac_evaluate_batch": (c_int32, [_P, ctypes.POINTER(BoacSlice), c_int32, c_float, c_int32, c_int32, _P]),
+    "boac_gp_fit": (c_int32, [_P, _P, c_int32, c_int32, _P, c_int32, c_int32, ctypes.c_double, _P, _P,
+                              ctypes.POINTER(BoacGpInfo)]),
+    "boac_gp_ei": (c_int32, [_P, ctypes.POINTER(BoacGpInfo), _P, _P, _P, _P, c_int32, ctypes.c_double,
+                             ctypes.c_double, _P, _P, _P, _P]),
     "boac_ctx_set_profiling": (c_int32, [_P, c_int32]),
     "boac_ctx_kernel_stats": (c_int32, [_P, c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),

@@ -9,8 +9,10 @@ from typing import List, Optional, Sequence
 
 import torch
 
+import numpy as np
+
 from . import _lib
-from ._lib import BoacError, BoacGeom, BoacSlice, check
+from ._lib import BoacError, BoacGeom, BoacGpInfo, BoacSlice, check
 
 DEFAULT_TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -177,6 +179,22 @@ class Context:
                                               _stream(self.device)))
         return obj, grad, status
 
+    def gp_ei(self, model: "GpModel", q: torch.Tensor, best: float, xi: float, want_mu_sigma: bool = False):
+        """Expected improvement (and optionally posterior mean and standard deviation) of the fitted
+        surrogate at unit-box queries q [M, d] (float64 device tensor). Returns ei [M] or (ei, mu, sigma)."""
+        M = q.shape[0]
+        dm = model.on(self.device)
+        ei = torch.empty(M, device=self.device, dtype=torch.float64)
+        mu = torch.empty(M, device=self.device, dtype=torch.float64) if want_mu_sigma else None
+        sd = torch.empty(M, device=self.device, dtype=torch.float64) if want_mu_sigma else None
+        f64 = torch.float64
+        check(self.lib.boac_gp_ei(self.handle, ctypes.byref(model.info),
+                                  _ptr(dm["u"], "u", f64), _ptr(dm["linv"], "linv", f64),
+                                  _ptr(dm["alpha"], "alpha", f64), _ptr(q, "q", f64, (M, model.info.d)), M,
+                                  float(best), float(xi), _ptr(mu, "mu", f64), _ptr(sd, "sigma", f64),
+                                  _ptr(ei, "ei", f64), _stream(self.device)))
+        return (ei, mu, sd) if want_mu_sigma else ei
+
     def evaluate_batch(self, slices: Sequence["SliceBatch"], delta_r: float, n_iter: int, ckpt_every: int = 5):
         arr = (BoacSlice * len(slices))()
         for i, s in enumerate(slices):
@@ -222,6 +240,41 @@ class SliceBatch:
                           torch.empty(C, device=dev, dtype=torch.int32))
 
 
+class GpModel:
+    """A fitted surrogate (boac_gp_fit): selection info, L^-1 and K^-1 z as host arrays, and the inputs;
+    device copies are made once per device on first use."""
+
+    def __init__(self, info: BoacGpInfo, u: np.ndarray, linv: np.ndarray, alpha: np.ndarray):
+        self.info, self.u, self.linv, self.alpha = info, u, linv, alpha
+        self._dev = {}
+
+    def on(self, device: torch.device):
+        key = str(device)
+        if key not in self._dev:
+            self._dev[key] = {k: torch.as_tensor(v, device=device).contiguous()
+                              for k, v in (("u", self.u), ("linv", self.linv), ("alpha", self.alpha))}
+        return self._dev[key]
+
+
+def gp_fit(u: np.ndarray, y: np.ndarray, lengths: Sequence[float], n_select: int = 0,
+           noise: float = 1e-6) -> GpModel:
+    """Fit the surrogate on the host (native FP64, boac_gp_fit). u [n, d] unit-box inputs, y [n]."""
+    lib = _lib.load()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    lengths = np.ascontiguousarray(lengths, dtype=np.float64)
+    n, d = u.shape
+    if y.shape != (n,):
+        raise ValueError(f"y has shape {y.shape}, expected ({n},)")
+    linv = np.empty((n, n), dtype=np.float64)
+    alpha = np.empty(n, dtype=np.float64)
+    info = BoacGpInfo()
+    p = lambda a: ctypes.c_void_p(a.ctypes.data)
+    check(lib.boac_gp_fit(p(u), p(y), n, d, p(lengths), len(lengths), int(n_select), float(noise), p(linv),
+                          p(alpha), ctypes.byref(info)))
+    return GpModel(info, u, linv, alpha)
+
+
 class BoacObjective(torch.autograd.Function):
     """J(theta) for a batch of candidates theta [C, 8] with an exact hand-written adjoint.
 
@@ -249,4 +302,4 @@ def objective(boac: Context, geom: Geometry, meas: torch.Tensor, theta: torch.Te
     return BoacObjective.apply(boac, geom, meas, float(delta_r), int(n_iter), int(ckpt_every), theta)
 
 
-__all__ = ["Context", "Geometry", "SliceBatch", "BoacObjective", "BoacError", "objective"]
+__all__ = ["Context", "Geometry", "SliceBatch", "BoacObjective", "BoacError", "GpModel", "gp_fit", "objective"]

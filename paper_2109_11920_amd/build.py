@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libboac.so")
-SOURCES = ["kernels_ray.hip", "kernels_back.hip", "kernels_misc.hip", "runtime.cpp"]
+SOURCES = ["kernels_ray.hip", "kernels_back.hip", "kernels_misc.hip", "kernels_gp.hip", "gp_host.cpp", "runtime.cpp"]
 ARCH = "gfx950"
 
 

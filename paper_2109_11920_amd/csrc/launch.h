@@ -105,6 +105,22 @@ struct AdjElemArgs {
     int npix, C;
 };
 
+// Acquisition of the surrogate at M queries (kernels_gp.hip), FP64.
+struct GpEiArgs {
+    const double *u;      // [n][d] observations, unit-box coordinates
+    const double *linv;   // [n][n] inverse of the Cholesky factor (lower)
+    const double *alpha;  // [n] K^-1 z
+    const double *q;      // [M][d] queries
+    int n, d, M;
+    int npad;             // K* row stride (n rounded up to 64)
+    int nti;              // row blocks of 64 in X
+    double inv2l2, amp, m0, s, best, xi;
+    double *ks;           // scratch [M][npad]
+    double *part;         // scratch [nti][M]
+    double *mu, *sd;      // [M] or NULL
+    double *ei;           // [M]
+};
+
 // Raster-adjoint components per candidate: c_0..c_5, mu_b, mu_c, dR.
 constexpr int kGradComps = 9;
 
@@ -134,6 +150,7 @@ hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st);
 hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status, hipStream_t st);
 hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st);
 hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st);
+hipError_t launch_gp_ei(const GpEiArgs &a, hipStream_t st);
 hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
                              hipStream_t st);
 

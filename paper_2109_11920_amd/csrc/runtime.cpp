@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/boac.h"
+#include "gp_host.h"
 #include "launch.h"
 
 using namespace boac;
@@ -1177,6 +1178,106 @@ boac_status boac_objective_grad_ex(boac_ctx *ctx, const boac_geom *geom, const f
                             d_status, (hipStream_t)stream, d_grad, 9);
     return eval_grad(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, ckpt_every, d_obj, d_grad,
                      d_status, (hipStream_t)stream, 9);
+}
+
+// ------------------------------------------------------------------ surrogate (Eqs. 7-10)
+boac_status boac_gp_fit(const double *h_u, const double *h_y, int32_t n, int32_t d, const double *h_lengths,
+                        int32_t n_lengths, int32_t n_select, double noise, double *h_linv, double *h_alpha,
+                        boac_gp_info *info) {
+    if (n < 1 || n > 8192) return fail(BOAC_EINVAL, "n = %d outside [1, 8192]", n);
+    if (d < 1 || d > 64) return fail(BOAC_EINVAL, "d = %d outside [1, 64]", d);
+    if (n_lengths < 1) return fail(BOAC_EINVAL, "n_lengths = %d must be >= 1", n_lengths);
+    if (!h_u || !h_y || !h_lengths || !h_linv || !h_alpha || !info)
+        return fail(BOAC_EINVAL, "a pointer argument of boac_gp_fit is NULL");
+    if (!(noise >= 0.0) || !std::isfinite(noise)) return fail(BOAC_EINVAL, "noise must be finite and >= 0");
+    for (int i = 0; i < n_lengths; ++i)
+        if (!(h_lengths[i] > 0.0) || !std::isfinite(h_lengths[i]))
+            return fail(BOAC_EINVAL, "length %d is not a positive finite value", i);
+    for (size_t i = 0; i < (size_t)n * d; ++i)
+        if (!std::isfinite(h_u[i])) return fail(BOAC_EINVAL, "h_u[%zu] is not finite", i);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(h_y[i])) return fail(BOAC_EINVAL, "h_y[%d] is not finite", i);
+    // model selection on the n_select smallest objectives (stable: ties by index)
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    int ns = n;
+    if (n_select > 0 && n_select < n) {
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h_y[a] < h_y[b]; });
+        ns = n_select;
+    }
+    std::vector<double> us((size_t)ns * d), ys(ns), L((size_t)n * n), al(n);
+    for (int r = 0; r < ns; ++r) {
+        ys[r] = h_y[idx[r]];
+        for (int c = 0; c < d; ++c) us[(size_t)r * d + c] = h_u[(size_t)idx[r] * d + c];
+    }
+    int best = -1;
+    double best_lml = 0.0, m0, s, lml;
+    for (int g = 0; g < n_lengths; ++g) {
+        if (!gp_fit_fixed(us.data(), ys.data(), ns, d, h_lengths[g], 1.0, noise, L.data(), al.data(), &m0, &s, &lml))
+            continue;
+        if (best < 0 || lml > best_lml) {
+            best = g;
+            best_lml = lml;
+        }
+    }
+    if (best < 0) return fail(BOAC_EINVAL, "no length-scale gives a positive definite covariance; raise noise");
+    if (!gp_fit_fixed(h_u, h_y, n, d, h_lengths[best], 1.0, noise, L.data(), h_alpha, &m0, &s, &lml))
+        return fail(BOAC_EINVAL, "covariance of all %d observations is not positive definite; raise noise", n);
+    gp_tri_inverse(L.data(), h_linv, n);
+    info->n = n;
+    info->d = d;
+    info->length = h_lengths[best];
+    info->amp = 1.0;
+    info->noise = noise;
+    info->m0 = m0;
+    info->s = s;
+    info->lml = lml;
+    return BOAC_OK;
+}
+
+boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                       const double *d_alpha, const double *d_q, int32_t M, double best, double xi, double *d_mu,
+                       double *d_sigma, double *d_ei, void *stream) {
+    if (!info) return fail(BOAC_EINVAL, "info is NULL");
+    if (info->n < 1 || info->n > 8192 || info->d < 1 || info->d > 64)
+        return fail(BOAC_EINVAL, "info holds n = %d, d = %d outside the supported range", info->n, info->d);
+    if (!(info->length > 0.0) || !std::isfinite(info->length) || !(info->s > 0.0) || !std::isfinite(info->s) ||
+        !std::isfinite(info->m0) || !(info->amp > 0.0) || !std::isfinite(info->amp))
+        return fail(BOAC_EINVAL, "info holds a non-positive or non-finite model parameter");
+    if (M < 1 || M > (1 << 20)) return fail(BOAC_EINVAL, "M = %d outside [1, 2^20]", M);
+    if (!std::isfinite(best) || !(xi >= 0.0) || !std::isfinite(xi))
+        return fail(BOAC_EINVAL, "best must be finite and xi finite and >= 0");
+    BOAC_TRY(check_ptr(d_u, "d_u"));
+    BOAC_TRY(check_ptr(d_linv, "d_linv"));
+    BOAC_TRY(check_ptr(d_alpha, "d_alpha"));
+    BOAC_TRY(check_ptr(d_q, "d_q"));
+    BOAC_TRY(check_ptr(d_ei, "d_ei"));
+    BOAC_TRY(check_ptr(d_mu, "d_mu", true));
+    BOAC_TRY(check_ptr(d_sigma, "d_sigma", true));
+    CTX_CHECK();
+    GpEiArgs a{};
+    a.u = d_u;
+    a.linv = d_linv;
+    a.alpha = d_alpha;
+    a.q = d_q;
+    a.n = info->n;
+    a.d = info->d;
+    a.M = M;
+    a.npad = (info->n + 63) / 64 * 64;
+    a.nti = (info->n + 63) / 64;
+    a.inv2l2 = 1.0 / (2.0 * info->length * info->length);
+    a.amp = info->amp;
+    a.m0 = info->m0;
+    a.s = info->s;
+    a.best = best;
+    a.xi = xi;
+    a.mu = d_mu;
+    a.sd = d_sigma;
+    a.ei = d_ei;
+    BOAC_TRY(ensure_t(ctx, "gp_ks", (size_t)M * a.npad, &a.ks));
+    BOAC_TRY(ensure_t(ctx, "gp_part", (size_t)M * a.nti, &a.part));
+    const hipStream_t st = (hipStream_t)stream;
+    return timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); });
 }
 
 // Relative cost of a slice (algorithmic attenuation-tensor passes x tensor size x candidates).

@@ -124,3 +124,14 @@ def test_planted_sign_error_in_gamma_breaks_the_integral_pin():
     f = lambda t: max(0.0, best - xi - t) * stats.norm.pdf(t, mu, sigma)
     ref, _ = integrate.quad(f, mu - 12 * sigma, mu + 12 * sigma, points=[best - xi])
     assert abs(wrong(np.array([mu]), np.array([sigma]), best, xi)[0] - ref) > 1e-3
+
+
+def test_fit_gp_selection_subset():
+    rng = np.random.default_rng(5)
+    U = rng.uniform(size=(60, 3))
+    y = np.exp(2 * U[:, 0]) + U[:, 2]
+    gp = bo.fit_gp(U, y, n_select=20)
+    idx = np.argsort(y, kind="stable")[:20]
+    lmls = [bo.GP(U[idx], y[idx], l).log_marginal_likelihood() for l in bo.LENGTH_GRID]
+    assert gp.length == bo.LENGTH_GRID[int(np.argmax(lmls))]
+    assert len(gp.y) == 60
