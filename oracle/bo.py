@@ -78,15 +78,21 @@ class GP:
         return self.m0 + self.s * mu_z, self.s * np.sqrt(var_z)
 
 
-def fit_gp(U, y, grid=LENGTH_GRID, noise=NOISE) -> GP:
-    """The grid length-scale with the largest log marginal likelihood (first one on ties)."""
+def fit_gp(U, y, grid=LENGTH_GRID, noise=NOISE, n_select=None) -> GP:
+    """GP on every observation with the grid length-scale of largest log marginal likelihood (first one
+    on ties). With n_select < n the likelihood is evaluated on the n_select observations of smallest y
+    only (ties by index), a cheaper model selection for long runs."""
+    U = np.asarray(U, np.float64)
+    y = np.asarray(y, np.float64)
+    idx = np.arange(len(y))
+    if n_select is not None and 0 < n_select < len(y):
+        idx = np.argsort(y, kind="stable")[:n_select]
     best = None
     for length in grid:
-        gp = GP(U, y, length, 1.0, noise)
-        lml = gp.log_marginal_likelihood()
+        lml = GP(U[idx], y[idx], length, 1.0, noise).log_marginal_likelihood()
         if best is None or lml > best[0]:
-            best = (lml, gp)
-    return best[1]
+            best = (lml, length)
+    return GP(U, y, best[1], 1.0, noise)
 
 
 def expected_improvement(mu, sigma, best: float, xi: float):
