@@ -132,6 +132,60 @@ def uneven_line(ctx, dev):
                     "objective + gradient, checkpoint 5, one graph replay"}
 
 
+def bo_line(ctx, g, S, truth):
+    """The BOAC outer loop on the 128^2 slice: 64 initial candidates, then cycles of 64 proposals (EI by
+    chaotic search; with the envelope gradient, part of each batch is a line search along -grad J),
+    30 MLEM iterations per candidate. Plain and gradient-aware loops from the same seed."""
+    import numpy as np
+    import torch
+
+    from paper_2109_11920_amd.api import gp_fit
+    from paper_2109_11920_amd.bo import BOAC, LENGTH_GRID
+    J_true = float(ctx.objective(g, S, torch.as_tensor(truth[None].astype(np.float32), device=S.device)
+                                 .contiguous(), DELTA_R, 30)[0][0])
+    out = {"J_true_head": round(J_true, 3), "what": "64 initial + 5 cycles x 64 proposals, 30 MLEM iterations "
+                                                    "each, EI by chaotic search on the GPU"}
+    for name, grad in (("plain", None), ("envelope_grad", "envelope")):
+        bo = BOAC(ctx, g, S, n_iter=30, n_init=64, batch=64, seed=0, gradient=grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bo.run(6)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        th, J = bo.best()
+        tm = {k: round(sum(c.timings.get(k, 0.0) for c in bo.cycles), 1) for k in ("fit_ms", "acquire_ms",
+                                                                                     "evaluate_ms")}
+        out[name] = {"seconds": round(wall, 3), "evaluations": int(sum(len(c.J) for c in bo.cycles)),
+                     "best_J": round(J, 3), "best_J_minus_true": round(J - J_true, 3),
+                     "unit_box_distance_to_true": round(float(np.linalg.norm((th - truth) / (bo.hi - bo.lo))), 4),
+                     "best_J_per_cycle": [round(float(min(x.J.min() for x in bo.cycles[:k + 1])), 2)
+                                          for k in range(len(bo.cycles))], **tm,
+                     "ei_queries": int(sum(c.timings.get("ei_queries", 0) for c in bo.cycles))}
+    # the acquisition kernel alone at a larger model: n observations, M queries, FP64
+    rng = np.random.default_rng(0)
+    n, M = 512, 1 << 16
+    U = rng.uniform(size=(n, 8))
+    y = 1e5 + 300 * np.sum((U - 0.4) ** 2, axis=1)
+    model = gp_fit(U, y, LENGTH_GRID)
+    q = torch.as_tensor(rng.uniform(size=(M, 8)), device=S.device)
+    ctx.gp_ei(model, q, float(y.min()), 0.0)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    reps = 5
+    for _ in range(reps):
+        ctx.gp_ei(model, q, float(y.min()), 0.0)
+    torch.cuda.synchronize()
+    cnt, ms, _ = ctx.kernel_stats("gp")
+    ctx.set_profiling(False)
+    ms /= max(cnt, 1)
+    flops = M * n * (n + 1 + 3 * 8 + 4)   # triangular product (FMA = 2), distances, mean and norm
+    out["gp_ei_kernel"] = {"n": n, "queries": M, "ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 2),
+                           "bound": "alu", "peak_tflops": 78.6, "frac": round(flops / ms / 1e9 / 78.6, 4),
+                           "what": "k* + blocked triangular product + EI, FP64 (exp not counted)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +195,7 @@ def main():
     ap.add_argument("--cpu-cands", type=int, default=32)
     ap.add_argument("--no-uneven", action="store_true", help="skip the 48-slice uneven batch line")
     ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
+    ap.add_argument("--no-bo", action="store_true", help="skip the BOAC outer-loop line")
     ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
@@ -307,6 +362,9 @@ def main():
 
     if not args.only_main and not args.no_uneven:
         out["uneven48"] = uneven_line(ctx, dev)
+
+    if not args.only_main and not args.no_bo:
+        out["bo"] = bo_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64))
 
     if not args.no_cpu and not args.only_main:
         out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K)

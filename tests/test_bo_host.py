@@ -1,0 +1,37 @@
+"""Host logic of the BOAC outer loop (no GPU): batch selection with exclusion, line-search proposals,
+and journal records."""
+import numpy as np
+
+from paper_2109_11920_amd.bo import Cycle, greedy_select, line_search_points
+
+
+def test_greedy_select_orders_by_score_and_excludes_neighbours():
+    U = np.array([[0.5, 0.5], [0.505, 0.5], [0.1, 0.1], [0.9, 0.9], [0.101, 0.1]])
+    score = np.array([5.0, 4.0, 3.0, 1.0, 2.9])
+    assert greedy_select(U, score, 3, 0.02) == [0, 2, 3]
+    assert greedy_select(U, score, 10, 0.0) == [0, 1, 2, 4, 3]
+    # points near what is already taken are skipped
+    assert greedy_select(U, score, 2, 0.02, taken=np.array([[0.5, 0.51]])) == [2, 3]
+    # ties keep the lower index first; non-finite scores end the selection
+    assert greedy_select(U, np.array([1.0, 1.0, np.nan, 1.0, 0.5]), 5, 0.0)[:3] == [0, 1, 3]
+
+
+def test_line_search_points_follow_the_negative_gradient():
+    u0 = np.array([0.5, 0.5, 0.5])
+    g = np.array([3.0, 0.0, -4.0])
+    P = line_search_points(u0, g, steps=(0.1, 0.2))
+    np.testing.assert_allclose(P, [[0.44, 0.5, 0.58], [0.38, 0.5, 0.66]])
+    # clipped to the unit box; a zero gradient proposes nothing
+    P = line_search_points(np.array([0.99, 0.5]), np.array([-1.0, 0.0]), steps=(0.5,))
+    np.testing.assert_allclose(P, [[1.0, 0.5]])
+    assert line_search_points(u0, np.zeros(3)).shape == (0, 3)
+
+
+def test_cycle_journal_record_round_trips():
+    c = Cycle(2, np.arange(16.0).reshape(2, 8), np.array([1.5, np.inf]), None, np.array([0, 1]), ["ei", "line"],
+              0.25, 0.4, {"fit_ms": 1.0})
+    import json
+    r = Cycle.from_json(json.loads(json.dumps(c.to_json())))
+    assert r.index == 2 and r.kind == ["ei", "line"] and r.grad is None
+    np.testing.assert_array_equal(r.theta, c.theta)
+    np.testing.assert_array_equal(r.J, c.J)
