@@ -6,7 +6,8 @@ of radius 0.8-1.5 cm at 4x activity (overlaps take the maximum), rasterised with
 coverage as the attenuation map. Disk centres are uniform in the head's bounding box and accepted
 when 64 points on the disk's rim lie inside the outline. The noiseless sinogram is the oracle
 projector applied with the true attenuation map (the same projector reconstructs it), scaled to the
-slice's total counts, then each bin is a Poisson draw.
+slice's total counts, then each bin is a Poisson draw. The oversampled variant simulates on a finer
+grid than the reconstruction uses (the paper's 72-angle geometry is run that way).
 """
 from __future__ import annotations
 
@@ -53,6 +54,21 @@ def activity_phantom(g: Geometry, c, delta_r: float, disks, background: float, h
     for cx, cy, rho in disks:
         hotmap = np.maximum(hotmap, disk_coverage(g, cx, cy, rho))
     return background * fb + (hot - background) * hotmap
+
+
+def simulate_oversampled(g: Geometry, theta_true, delta_r: float, disks, background: float, hot: float,
+                         counts: float, noise_rng: np.random.Generator, factor: int = 2):
+    """Noisy sinogram of geometry g simulated on a grid `factor` times finer than the one that
+    reconstructs it, so that the model does not generate its own data (no inverse crime): phantom and
+    attenuation map at pixel/factor, rays at factor x the bins and samples; each bin of g is the sum of
+    its `factor` sub-bins (they tile it). Returns (S [N_a, N_b], noiseless mean, fine activity)."""
+    gf = Geometry(g.n * factor, g.n_angles, g.n_bins * factor, g.n_samples * factor, g.pixel / factor)
+    f = activity_phantom(gf, theta_true[:6], delta_r, disks, background, hot)
+    att = attenuation(gf, rasterize_mu(gf, theta_true, delta_r))
+    fine = project(gf, att, f)
+    ybar = fine.reshape(g.n_angles, g.n_bins, factor).sum(axis=-1)
+    ybar = ybar * (counts / ybar.sum())
+    return noise_rng.poisson(ybar), ybar, f
 
 
 def simulate(g: Geometry, theta_true, delta_r: float, activity: np.ndarray, counts: float,

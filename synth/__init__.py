@@ -14,6 +14,9 @@ family stands in for them):
 * ``batch256_n128``  the 128 slice above, 256 random candidates, 30 iterations plus the objective.
 * ``grad64_n128``    the 128 slice above, 64 random candidates (own stream), 20 iterations,
                      objective and gradient, checkpoint every 5 iterations.
+* ``paper72_n128``   the paper's angular sampling: 128x128 at 0.2 cm, 72 angles over 360 deg x 128
+                     bins, 5e5 counts, simulated on a 2x finer grid (no inverse crime), 256 random
+                     candidates, 30 iterations plus the objective.
 * ``uneven48``       48 slices with N in {96,128,192,256}, angles in {64,96,128,256}, bins = N,
                      pixel = 25.6/N cm, counts log-uniform in [1e5, 2e6], 32 candidates each,
                      40 iterations plus objective and gradient.
@@ -57,6 +60,8 @@ class SliceSpec:
     seed: int
     # independent seed stream for this slice (phantom, noise, candidates)
     stream: Tuple[int, ...] = ()
+    # data simulated on a grid this many times finer than the reconstruction grid (1: the same grid)
+    oversample: int = 1
 
 
 @dataclass(frozen=True)
@@ -86,12 +91,16 @@ def workload(name: str, seed: int = 0) -> Workload:
     if name == "grad64_n128":
         return Workload(name, (_slice(128, 128, 5e5, seed, 0.2),), 64, 20, ckpt_every=5,
                         cand_seed_offset=1)
+    if name == "paper72_n128":
+        sl = SliceSpec(n=128, n_angles=72, n_bins=128, n_samples=128, pixel=0.2, counts=5e5, seed=seed,
+                       stream=(72,), oversample=2)
+        return Workload(name, (sl,), 256, 30)
     if name == "uneven48":
         return Workload(name, tuple(uneven_layout(seed, 48)), 32, 40, ckpt_every=5)
     raise KeyError(name)
 
 
-WORKLOADS = ("smoke_n64", "plain_n128", "batch256_n128", "grad64_n128", "uneven48")
+WORKLOADS = ("smoke_n64", "plain_n128", "batch256_n128", "grad64_n128", "paper72_n128", "uneven48")
 
 
 def streams(seed: int, stream: Tuple[int, ...] = ()):
