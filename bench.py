@@ -96,6 +96,34 @@ def cpu_baseline(workload_S, n_cand, n_iter):
                       f"FP64 NumPy/SciPy single thread, {dt:.1f} s"}
 
 
+def paper72_line(ctx, dev, reps=5):
+    """The paper's angular sampling: 128^2 at 0.2 cm, 72 angles over 360 deg, data simulated on a 2x
+    finer grid; 256 candidates, 30 iterations + objective, same step as the main line."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_11920_amd.api import Geometry
+    d = np.load(os.path.join(ROOT, "tests", "golden", "slice_n128_a72.npz"))
+    w = synth.workload("paper72_n128")
+    g = Geometry(128, 72, 128, 128, 0.2)
+    S = torch.as_tensor(d["meas"].astype(np.float32), device=dev)
+    cand = torch.as_tensor(synth.workload_candidates(w)[0].astype(np.float32), device=dev)
+    ctx.objective(g, S, cand, DELTA_R, w.n_iter)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        J, _, _ = ctx.objective(g, S, cand, DELTA_R, w.n_iter)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"value": round(cand.shape[0] * w.n_iter / (ms / 1e3), 1), "unit": "cand·it/s", "ms_per_step": round(ms, 3),
+            "finite": bool(torch.isfinite(J).all()),
+            "what": "128^2, 72 angles x 128 bins, 2x-oversampled data, 256 candidates, 30 iterations + objective"}
+
+
 def uneven_line(ctx, dev):
     """The 48-slice uneven batch: N 96-256, 64-256 angles, 32 candidates each, 40 iterations, objective
     + gradient (checkpoint every 5), one captured batch over concurrent stream lanes; times one replay."""
@@ -359,6 +387,9 @@ def main():
                                 "ms_per_batch": round(env_ms, 3), "grad_over_forward": round(env_ms / fwd_ms, 3),
                                 "what": "64 candidates, 20 iterations, envelope gradient (F^K held fixed) "
                                         "with dJ/d(dR)"}
+
+    if not args.only_main:
+        out["paper72"] = paper72_line(ctx, dev)
 
     if not args.only_main and not args.no_uneven:
         out["uneven48"] = uneven_line(ctx, dev)

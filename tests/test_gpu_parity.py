@@ -180,6 +180,26 @@ def test_objective_batch_matches_oracle_samples(ctx, slice128):
         report(f"batch256 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
 
 
+def test_objective_paper72_samples(ctx):
+    # the paper's 72 angles over 360 deg at 128 x 128, data simulated on a 2x finer grid; the 256-candidate
+    # draw of that workload, 30 iterations; the true head and three sampled candidates against the oracle
+    import os
+    import synth
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "slice_n128_a72.npz"))
+    g, og = geom_pair(128, 72, 128, 128, pixel=0.2)
+    S = d["meas"].astype(np.float64)
+    th = f32(synth.workload_candidates(synth.workload("paper72_n128"))[0])
+    th[0] = f32(d["theta"])
+    J, img, st = ctx.objective(g, dev(S), dev(th), DR, 30, want_image=True)
+    J = J.cpu().numpy()
+    assert np.all(np.isfinite(J)) and np.all((st.cpu().numpy() & 3) == 0)
+    for c in (0, 91, 200):
+        Jr, Fr, _ = oracle.evaluate(og, S, th[c], DR, 30)
+        report(f"paper72 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
+        if c == 0:
+            report("paper72 F^K true head", img.cpu().numpy()[0], Fr, TOL)
+
+
 def test_count_preservation_on_gpu(ctx, slice128):
     g, og = geom_pair(128, 128, pixel=0.2)
     S = slice128["meas"].astype(np.float64)
