@@ -8,8 +8,8 @@ this file by default):
 
     python -m paper_2109_11920_amd.autotune [--out PATH] [--workloads batch256_n128,grad64_n128,...]
 
-The committed cache holds the default workloads plus every slice shape of uneven48
-(--workloads uneven48).
+The committed cache holds the default workloads, the 72-angle slice (--workloads paper72_n128) and
+every slice shape of uneven48 (--workloads uneven48).
 
 Keys follow the library: "ray:<n>x<na>x<nb>x<nt>:<C>:<image components>" -> [block, rays per thread,
 paired forward projection (one-component entries)]
