@@ -14,6 +14,7 @@ Modules:
              gradient (reconstruction held fixed), finite differences
   phantom    synthetic phantom and noisy sinogram                     (simulation study)
   bo         GP surrogate, expected improvement, chaotic search       (Eqs. 7-10, BOAC steps 4-6)
+  metrics    SSIM, CNR, PSNR of the simulation study                  (Table I)
 
 Pins: every function is checked by tests/test_oracle_*.py against closed forms, exact special cases,
 library routines and brute force. The comparison of BOAC with the paper's own Table I is
