@@ -62,6 +62,8 @@ class SliceSpec:
     stream: Tuple[int, ...] = ()
     # data simulated on a grid this many times finer than the reconstruction grid (1: the same grid)
     oversample: int = 1
+    # true head (c_0..c_5, mu_b, mu_c) of this slice; empty: the default true head
+    true_theta: Tuple[float, ...] = ()
 
 
 @dataclass(frozen=True)
@@ -101,6 +103,25 @@ def workload(name: str, seed: int = 0) -> Workload:
 
 
 WORKLOADS = ("smoke_n64", "plain_n128", "batch256_n128", "grad64_n128", "paper72_n128", "uneven48")
+
+
+# Three true heads of the BOAC-vs-NAC study (cases A, B, C), inside the candidate box.
+STUDY_HEADS = (
+    (7.5, 0.0, 1.2, 0.0, -0.3, 0.0, 0.150, 0.250),
+    (7.8, 0.3, 0.9, -0.2, -0.2, 0.1, 0.145, 0.260),
+    (7.2, -0.2, 1.4, 0.1, -0.4, -0.1, 0.155, 0.235),
+)
+
+
+def study_cases(seed: int = 0) -> List[SliceSpec]:
+    """The study's slices: the paper's geometry (128^2, 72 angles over 360 deg), data simulated on a
+    2x finer grid, 5e5 counts, one true head and phantom seed stream per case."""
+    return [SliceSpec(n=128, n_angles=72, n_bins=128, n_samples=128, pixel=0.2, counts=5e5, seed=seed,
+                      stream=(9, k), oversample=2, true_theta=tuple(h)) for k, h in enumerate(STUDY_HEADS)]
+
+
+def slice_truth(spec: SliceSpec) -> np.ndarray:
+    return np.array(spec.true_theta, dtype=np.float64) if spec.true_theta else true_candidate()
 
 
 def streams(seed: int, stream: Tuple[int, ...] = ()):

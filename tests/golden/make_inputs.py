@@ -2,6 +2,7 @@
 
     python tests/golden/make_inputs.py            # smoke_n64, plain_n128 and paper72_n128 slices
     python tests/golden/make_inputs.py --uneven   # also the 48 slices of the uneven batch
+    python tests/golden/make_inputs.py --study    # also the three slices of the BOAC-vs-NAC study
 
 Each .npz holds: meas (uint16 counts [N_a, N_b]), activity (float32 true image), geometry
 (n, n_angles, n_bins, n_samples, pixel), counts, seed, stream, and the true head theta / delta_R.
@@ -25,7 +26,7 @@ import synth  # noqa: E402
 def make_slice(spec: synth.SliceSpec):
     g = oracle.Geometry(spec.n, spec.n_angles, spec.n_bins, spec.n_samples, spec.pixel)
     rng_ph, rng_noise, _ = synth.streams(spec.seed, spec.stream)
-    theta = synth.true_candidate()
+    theta = synth.slice_truth(spec)
     disks = place_disks(theta[:6], synth.disk_proposals(rng_ph), synth.N_DISKS,
                         synth.DISK_R_LO, synth.DISK_R_HI)
     if spec.oversample > 1:
@@ -47,6 +48,7 @@ def make_slice(spec: synth.SliceSpec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--uneven", action="store_true")
+    ap.add_argument("--study", action="store_true")
     args = ap.parse_args()
     for name in ("smoke_n64", "plain_n128"):
         spec = synth.workload(name).slices[0]
@@ -57,6 +59,14 @@ def main():
     out = os.path.join(HERE, f"slice_n{spec.n}_a{spec.n_angles}.npz")
     np.savez_compressed(out, **make_slice(spec))
     print("wrote", out)
+    if args.study:
+        parts = {}
+        for k, spec in enumerate(synth.study_cases()):
+            for key, v in make_slice(spec).items():
+                parts[f"case{k}_{key}"] = v
+        out = os.path.join(HERE, "study_cases.npz")
+        np.savez_compressed(out, n_cases=np.int64(len(synth.STUDY_HEADS)), **parts)
+        print("wrote", out)
     if args.uneven:
         w = synth.workload("uneven48")
         parts = {}
