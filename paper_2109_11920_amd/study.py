@@ -5,8 +5,9 @@ For every case (a noisy 72-angle sinogram simulated on a 2x finer grid, its true
   - BOAC: the outer loop (bo.BOAC) picks the head parameters, then MLEM reconstructs with mu(theta_best);
   - NAC: MLEM with mu = 0;
   - AC with the true head, as a reference;
-and each reconstruction is scored against the true activity with SSIM, CNR and PSNR (the paper's three
-scores, parameters of Wang et al. for SSIM). The shape of Table I is reproduced, not its numbers: the
+and each reconstruction, divided by the simulation's count scale (total counts over the total projection
+of the true activity through the true attenuation), is scored against the true activity with SSIM, CNR
+and PSNR (the paper's three scores, parameters of Wang et al. for SSIM). The shape of Table I is reproduced, not its numbers: the
 paper's phantoms are not published.
 
     python -m paper_2109_11920_amd.study --inputs tests/golden/study_cases.npz [--cycles 8] [--gradient envelope]
@@ -94,10 +95,15 @@ def run_case(ctx: Context, d, k: int, n_iter: int, cycles: int, gradient, seed: 
     secs = time.perf_counter() - t0
     cand = torch.as_tensor(np.stack([th, truth]).astype(np.float32), device=dev)
     Jc, F, _ = ctx.objective(g, meas, cand, dr, n_iter, want_image=True)
-    F = F.double().cpu().numpy()
-    F_nac = ctx.mlem(g, torch.zeros((1, n, n), device=dev), meas, n_iter)[0].double().cpu().numpy()
+    # reconstructions carry the simulation's count scale; compare in the phantom's activity units:
+    # kappa = total counts / total projection of the true activity through the true attenuation
+    mu_true = ctx.rasterize_mu(g, cand[1:2].contiguous(), dr)
+    y_true = ctx.project(g, mu_true, torch.as_tensor(act[None].astype(np.float32), device=dev))
+    kappa = float(meas.double().sum() / y_true.double().sum())
+    F = F.double().cpu().numpy() / kappa
+    F_nac = ctx.mlem(g, torch.zeros((1, n, n), device=dev), meas, n_iter)[0].double().cpu().numpy() / kappa
     out = {"case": "ABC"[k] if k < 3 else str(k), "theta_true": truth.tolist(), "theta_boac": th.tolist(),
-           "J_boac": float(Jc[0]), "J_true_head": float(Jc[1]), "bo_seconds": round(secs, 3),
+           "J_boac": float(Jc[0]), "J_true_head": float(Jc[1]), "bo_seconds": round(secs, 3), "kappa": kappa,
            "evaluations": int(sum(len(c.J) for c in bo.cycles)),
            "boac": scores(F[0], act), "nac": scores(F_nac, act), "ac_true_head": scores(F[1], act)}
     return out
