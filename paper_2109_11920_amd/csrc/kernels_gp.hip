@@ -6,8 +6,8 @@
 //   gamma = (J_best - mu - xi) / sigma,  EI = sigma (gamma Phi(gamma) + phi(gamma)).
 // |X k*_m|^2 for all m is a triangular matrix product Z = X K*^T (n x M) reduced over its rows:
 //   k_gp_kstar  K* [M][npad] (zero past n)
-//   k_gp_zsq    per (64-row block of X, 64-query block): the Z block over j <= i, squared and summed
-//               over its rows -> part [n/64][M] (fixed order, no atomics)
+//   k_gp_zsq    per (64-row block of X, 64-query block): the Z block over j <= i on the FP64 matrix
+//               cores, squared and summed over its rows -> part [n/64][M] (fixed order, no atomics)
 //   k_gp_ei     one wave per query: k* . alpha, sum of the row-block partials, EI
 #include "launch.h"
 
@@ -33,17 +33,22 @@ __global__ __launch_bounds__(256) void k_gp_kstar(GpEiArgs A) {
     }
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Z block on the FP64 matrix cores: D[16 x 16] += A[16 x 4] B[4 x 16] per v_mfma_f64_16x16x4f64, with
+// lane l holding A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 v][l % 16] (v = 0..3).
+// Wave w of the 4 takes queries m0 + 16 w .. + 15 and all 64 rows (4 row tiles of 16): A = X rows,
+// B = K*^T, so D[i][m] = sum_j X[i][j] K*[m][j]. X and K* pass through LDS 16 columns at a time.
 __global__ __launch_bounds__(256) void k_gp_zsq(GpEiArgs A) {
     __shared__ double Xs[kGpJ][kGpT + 1];  // X[i0 + r][j0 + c] at [c][r]
     __shared__ double Ks[kGpJ][kGpT + 1];  // K*[m0 + r][j0 + c] at [c][r]
-    __shared__ double red[kGpT / 4][kGpT];
+    __shared__ double red[4][kGpT];
     const int i0 = blockIdx.x * kGpT, m0 = blockIdx.y * kGpT;
-    const int tm = threadIdx.x & 15, ti = threadIdx.x >> 4;  // 4 queries x 4 rows per thread
-    double acc[4][4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d acc[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
     // X is lower triangular: row block [i0, i0 + 64) needs columns j < min(i0 + 64, n)
     const int jend = min(i0 + kGpT, A.n);
     for (int j0 = 0; j0 < jend; j0 += kGpJ) {
@@ -55,33 +60,26 @@ __global__ __launch_bounds__(256) void k_gp_zsq(GpEiArgs A) {
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < kGpJ; ++c) {
-            double a[4], b[4];
+        for (int kk = 0; kk < kGpJ; kk += 4) {
+            const double b = Ks[kk + lk][16 * w + lr];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                a[x] = Xs[c][ti * 4 + x];
-                b[x] = Ks[c][tm * 4 + x];
-            }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[kk + lk][16 * t + lr], b, acc[t], 0, 0, 0);
         }
         __syncthreads();
     }
+    // this lane: query m0 + 16 w + lr, rows 16 t + lk + 4 v; sum of squares over its 16 rows
+    double s = 0.0;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-        double s = 0.0;
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) s = fma(acc[x][y], acc[x][y], s);
-        red[ti][tm * 4 + y] = s;
-    }
+        for (int v = 0; v < 4; ++v) s = fma(acc[t][v], acc[t][v], s);
+    red[lk][16 * w + lr] = s;
     __syncthreads();
     if (threadIdx.x < kGpT) {
-        double s = 0.0;
-        for (int r = 0; r < kGpT / 4; ++r) s += red[r][threadIdx.x];
+        const double q = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
         const int m = m0 + threadIdx.x;
-        if (m < A.M) A.part[(size_t)blockIdx.x * A.M + m] = s;
+        if (m < A.M) A.part[(size_t)blockIdx.x * A.M + m] = q;
     }
 }
 
