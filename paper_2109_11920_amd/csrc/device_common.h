@@ -17,6 +17,11 @@ constexpr int kWave = 64;
 
 struct DevGeom {
     int n, na, nb, nt;
+    // angles the attenuation tensor holds: na, or na / 2 with opposed-ray pairing (na even): ray
+    // (a, b) and ray (a + na/2, nb-1-b) run along one line in opposite directions, sample k of the
+    // first at sample nt-1-k of the second, and with the half-self rule their path lengths add up to
+    // the ray total T, so the second ray's attenuation is exp(-T) / att of the first
+    int nah;
     float dx;       // pixel size (cm)
     float cN;       // (n-1)/2
     float cB;       // (nb-1)/2

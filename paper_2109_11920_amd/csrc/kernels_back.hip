@@ -565,7 +565,11 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
 // folded in while staging as in the slot variant. A group is loaded unless all of it lies outside the
 // union of the tile pixels' supports (tested at its centre with half widths grown by 1.5 samples); a
 // skipped group keeps finite values, gathered only with weight 0.
-template <int CG, bool WEIGHTED>
+// PAIRED (opposed-ray pairing, g.nah = na/2): the slab of angle a < na/2 also stands for angle
+// a + na/2, whose sample (nb-1-b, nt-1-k) sits at sample (b, k) of angle a with attenuation
+// exp(-T_ab) / att and the same bilinear weights; each staged slot holds both contributions,
+// att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles.
+template <int CG, bool WEIGHTED, bool PAIRED>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
     constexpr int PL = kSlidPitch;
@@ -609,12 +613,16 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src + (size_t)c0 * A.att_cs, (unsigned)ncg * cand_src);
     const __amdgpu_buffer_rsrc_t rz =
         buffer_rsrc(WEIGHTED ? A.z + (size_t)c0 * A.sino_cs : src, WEIGHTED ? (unsigned)ncg * cand_z : 0u);
-    const int4 *rects = T.rects + (size_t)tile * g.na;
-    unsigned qs[CG], qz[CG];
+    const unsigned cand_e = 4u * (unsigned)A.e_cs;
+    const __amdgpu_buffer_rsrc_t re =
+        buffer_rsrc(PAIRED ? A.E + (size_t)c0 * A.e_cs : src, PAIRED ? (unsigned)ncg * cand_e : 0u);
+    const int4 *rects = T.rects + (size_t)tile * g.nah;
+    unsigned qs[CG], qz[CG], qe[CG];
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
         qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
         qz[q] = (unsigned)min(q, ncg - 1) * cand_z;
+        qe[q] = (unsigned)min(q, ncg - 1) * cand_e;
     }
 
     Comp acc[CG];
@@ -626,11 +634,13 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     }
 
     float4 pre[CG];
-    float zv[CG];
+    float zv[CG], ev[CG], zo[CG];  // ray weight; with PAIRED exp(-T) and the opposed ray's weight
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
         pre[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         zv[q] = 1.f;
+        ev[q] = 0.f;
+        zo[q] = 1.f;
     }
     auto prefetch = [&](int a, int4 r) {
         const float2 cs = g.trig[a];
@@ -647,12 +657,23 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
 #pragma unroll
             for (int q = 0; q < CG; ++q) zv[q] = buffer_ld(rz, 4u * (unsigned)bb, zbase + qz[q]);
         }
+        if constexpr (PAIRED) {
+            // exp(-T) of ray (a, bin); the opposed ray (a + na/2, nb-1-bin) takes its weight
+            const unsigned ebase = 4u * (unsigned)(a * g.nb + r.x);
+#pragma unroll
+            for (int q = 0; q < CG; ++q) ev[q] = buffer_ld(re, 4u * (unsigned)bb, ebase + qe[q]);
+            if constexpr (WEIGHTED) {
+                const unsigned obase = 4u * (unsigned)((a + g.nah) * g.nb + (g.nb - 1 - r.x));
+#pragma unroll
+                for (int q = 0; q < CG; ++q) zo[q] = buffer_ld(rz, obase - 4u * (unsigned)bb, qz[q]);
+            }
+        }
     };
 
     int4 cur = rects[0];
     prefetch(0, cur);
 
-    for (int a = 0; a < g.na; ++a) {
+    for (int a = 0; a < g.nah; ++a) {
         __syncthreads();  // previous gather done with the LDS
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -661,6 +682,10 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             for (int q = 0; q < CG; ++q) {
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
                 v[q] = WEIGHTED ? x * zv[q] : x;
+                if constexpr (PAIRED) {
+                    const float xo = x > 1e-30f ? ev[q] * __builtin_amdgcn_rcpf(x) : 0.f;
+                    v[q] = WEIGHTED ? fmaf(xo, zo[q], v[q]) : v[q] + xo;
+                }
             }
             float *d = lds + ((4 * kb + t) * PL + bb) * V;
             if constexpr (CG == 8) {
@@ -676,7 +701,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
         }
         __syncthreads();
         const int4 r = cur;
-        if (a + 1 < g.na) {
+        if (a + 1 < g.nah) {
             cur = rects[a + 1];
             prefetch(a + 1, cur);
         }
@@ -715,7 +740,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                 }
             }
         }
-        if ((a & 7) == 7 || a == g.na - 1) {
+        if ((a & 7) == 7 || a == g.nah - 1) {
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
                 comp_add(acc[q], blk[q]);
@@ -751,10 +776,19 @@ template <int CG>
 static hipError_t back_col4(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
     const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
-    if (mode == BACK_SENS || mode == BACK_FIELD)
-        hipLaunchKernelGGL((k_back_col4<CG, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
-    else
-        hipLaunchKernelGGL((k_back_col4<CG, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    const bool weighted = !(mode == BACK_SENS || mode == BACK_FIELD);
+    if (a.E) {
+        // opposed-ray pairing covers the attenuation-weighted modes only
+        if (mode == BACK_FIELD || mode == BACK_ADJ || g.nah * 2 != g.na) return hipErrorInvalidValue;
+        if (weighted)
+            hipLaunchKernelGGL((k_back_col4<CG, true, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+        else
+            hipLaunchKernelGGL((k_back_col4<CG, false, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    } else if (weighted) {
+        hipLaunchKernelGGL((k_back_col4<CG, true, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    } else {
+        hipLaunchKernelGGL((k_back_col4<CG, false, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    }
     return hipGetLastError();
 }
 
@@ -786,6 +820,8 @@ static hipError_t back_tile(const DevGeom &g, const BackCfg &bc, const BackArgs 
 }
 
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
+    // opposed-ray pairing exists in the column-group gather only
+    if ((a.E || g.nah != g.na) && bc.slid != 2) return hipErrorInvalidValue;
     if (bc.slid == 2) {
         if (bc.tw != 16 || bc.th != 16 || bc.hb != 1) return hipErrorInvalidValue;
         switch (bc.cg) {

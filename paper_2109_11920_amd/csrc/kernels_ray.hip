@@ -35,11 +35,11 @@ constexpr int kBandChunk = 16;  // samples per load batch in the row-band paths
 template <bool SINGLE>
 __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
                                              const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
-                                             size_t att_cs) {
+                                             size_t att_cs, float *__restrict__ E, size_t e_cs) {
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
-    const int nrays = g.na * g.nb;
+    const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     const float *img = mu + cand * img_cs;
@@ -82,6 +82,8 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
                     }
                     *reinterpret_cast<float4 *>(col + att_row(g, 4 * kg)) = make_float4(e[0], e[1], e[2], e[3]);
                 }
+                // opposed-ray pairing: exp(-T) of the whole ray, T = dx sum_k m_k
+                if (E) E[cand * e_cs + ray] = expf(-g.dx * comp_value(T));
             } else {
                 // pass 1 of 2: store m_k of the samples in this band, a 4-sample group (one 16-byte
                 // load and store) at a time from the 4-aligned group holding the first. The ray is this
@@ -155,21 +157,61 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
 }
 
 // ------------------------------------------------------------------ forward projection
-template <int MODE, bool SINGLE>
+// The epilogue of one ray: y, or the MLEM ratio, or the NLL term added to nll (zero_proj set where
+// S > 0 meets y <= 0).
+template <int MODE>
+__device__ __forceinline__ void fwd_emit(const FwdArgs &A, size_t cand, int ray, float y, Comp &nll, bool &zero_proj) {
+    const size_t si = cand * A.sino_cs + ray;
+    if constexpr (MODE == FWD_PROJ) {
+        A.y_out[si] = y;
+    } else if constexpr (MODE == FWD_RATIO) {
+        const float S = A.meas[ray];
+        A.r_out[si] = (y > 0.f) ? S / y : 0.f;
+        if (A.y_out) A.y_out[si] = y;
+    } else {  // FWD_NLL
+        const float S = A.meas[ray];
+        if (A.y_out) A.y_out[si] = y;
+        float term;
+        if (S > 0.f) {
+            if (y > 0.f) {
+                term = y - S * logf(y);
+            } else if (y <= 0.f) {
+                term = __builtin_inff();
+                zero_proj = true;
+            } else {
+                term = y;  // NaN propagates (flagged as non-finite at the end)
+            }
+        } else {
+            term = y;
+        }
+        comp_add(nll, term);
+    }
+}
+
+// Attenuation of the opposed ray's sample from the held one: exp(-T) / att (0 where att has
+// underflowed or is a padding row).
+__device__ __forceinline__ float opposed_att(float e_ray, float at) {
+    return at > 1e-30f ? e_ray * __builtin_amdgcn_rcpf(at) : 0.f;
+}
+
+// PAIRED (opposed-ray pairing, single stage only): each thread's ray (a, b), a < na/2, also gives the
+// projection of ray (a + na/2, nb-1-b) from the same samples and bilinear values.
+template <int MODE, bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     __shared__ float red[32];  // two floats per wave, up to 16 waves
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
-    const int nrays = g.na * g.nb;
+    const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     const float *att = A.att + cand * A.att_cs;
     const float *img = A.img + cand * A.img_cs;
 
-    Comp acc[kMaxRpt];
+    Comp acc[kMaxRpt], acc2[kMaxRpt];
 #pragma unroll
-    for (int j = 0; j < kMaxRpt; ++j) acc[j] = Comp{0.f, 0.f};
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
@@ -188,7 +230,6 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
             const float2 cs = g.trig[a];
             float Ub, Vb;
             ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
-            const float *col = att + att_base(g, a, b);
             Comp c = acc[j];
             if constexpr (SINGLE) {
                 // att is streamed 16 samples ahead of use: the loads of chunk k0 + 16 are in flight
@@ -200,6 +241,8 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                 const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                Comp c2 = acc2[j];
                 float4 cur[KG], nxt[KG];
 #pragma unroll
                 for (int q = 0; q < KG; ++q) cur[q] = (4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, 4 * q)) : z4;
@@ -210,20 +253,25 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                         const int k = k0 + KC + 4 * q;
                         nxt[q] = (k < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, k)) : z4;
                     }
-                    float part = 0.f;
+                    float part = 0.f, part2 = 0.f;
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         if (k0 + q < g.nt) {
                             float U, V;
                             sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
-                            part = fmaf(f4at(cur[q >> 2], q & 3), bilinear_whole(lds, U, V, nf, pitch), part);
+                            const float at = f4at(cur[q >> 2], q & 3);
+                            const float w = bilinear_whole(lds, U, V, nf, pitch);
+                            part = fmaf(at, w, part);
+                            if constexpr (PAIRED) part2 = fmaf(opposed_att(e_ray, at), w, part2);
                         }
                         tau += 1.f;
                     }
                     kahan_add(c, part);
+                    if constexpr (PAIRED) kahan_add(c2, part2);
 #pragma unroll
                     for (int q = 0; q < KG; ++q) cur[q] = nxt[q];
                 }
+                acc2[j] = c2;
             } else {
                 // the ray's samples in this band, 16 at a time from the 4-aligned group holding the
                 // first: the chunk's att loads (4 samples per 16-byte load) are issued together, then
@@ -268,31 +316,10 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
         if (j >= rpt) break;
         const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
         if (ray >= nrays) continue;
-        const size_t si = cand * A.sino_cs + ray;
-        const float y = g.dx * comp_value(acc[j]);
-        if constexpr (MODE == FWD_PROJ) {
-            A.y_out[si] = y;
-        } else if constexpr (MODE == FWD_RATIO) {
-            const float S = A.meas[ray];
-            A.r_out[si] = (y > 0.f) ? S / y : 0.f;
-            if (A.y_out) A.y_out[si] = y;
-        } else {  // FWD_NLL
-            const float S = A.meas[ray];
-            if (A.y_out) A.y_out[si] = y;
-            float term;
-            if (S > 0.f) {
-                if (y > 0.f) {
-                    term = y - S * logf(y);
-                } else if (y <= 0.f) {
-                    term = __builtin_inff();
-                    zero_proj = true;
-                } else {
-                    term = y;  // NaN propagates (flagged as non-finite at the end)
-                }
-            } else {
-                term = y;
-            }
-            comp_add(nll, term);
+        fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(acc[j]), nll, zero_proj);
+        if constexpr (PAIRED) {
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(acc2[j]), nll, zero_proj);
         }
     }
     if constexpr (MODE == FWD_NLL) {
@@ -306,8 +333,8 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
 // float2): each sample's position, clamp, tap index and bilinear fractions are computed once and
 // serve both candidates (one pair lerp, two FMAs), about half the vector work per candidate-sample of
 // k_fwd. Single-stage images only (the pair stage is twice the size). An odd batch's last pair
-// repeats its candidate and writes it once.
-template <int MODE>
+// repeats its candidate and writes it once. PAIRED: opposed-ray pairing as in k_fwd.
+template <int MODE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
     extern __shared__ float lds[];
     __shared__ float red[32];  // two floats per wave, up to 16 waves
@@ -317,7 +344,7 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
     const int c0 = 2 * pr;
     const bool two = (c0 + 1 < C);
     const int c1 = two ? c0 + 1 : c0;
-    const int nrays = g.na * g.nb;
+    const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     stage_band_pair(A.img + c0 * A.img_cs, A.img + c1 * A.img_cs, g.n, bands.b[0], lds);
@@ -326,9 +353,9 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
     const __amdgpu_buffer_rsrc_t r0 = buffer_rsrc(A.att + c0 * A.att_cs, (unsigned)(4 * A.att_cs));
     const __amdgpu_buffer_rsrc_t r1 = buffer_rsrc(A.att + c1 * A.att_cs, (unsigned)(4 * A.att_cs));
 
-    Comp acc0[kMaxRpt], acc1[kMaxRpt];
+    Comp acc0[kMaxRpt], acc1[kMaxRpt], opp0[kMaxRpt], opp1[kMaxRpt];
 #pragma unroll
-    for (int j = 0; j < kMaxRpt; ++j) acc0[j] = acc1[j] = Comp{0.f, 0.f};
+    for (int j = 0; j < kMaxRpt; ++j) acc0[j] = acc1[j] = opp0[j] = opp1[j] = Comp{0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < kMaxRpt; ++j) {
         if (j >= rpt) break;
@@ -339,6 +366,8 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
         float Ub, Vb;
         ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
         const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+        const float e0 = PAIRED ? A.E[c0 * A.e_cs + ray] : 0.f;
+        const float e1 = PAIRED ? A.E[c1 * A.e_cs + ray] : 0.f;
         constexpr int KC = 16, KG = KC / 4;
         const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 u0[KG], u1[KG], n0[KG], n1[KG];
@@ -347,7 +376,7 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
             u0[q] = (4 * q < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, 4 * q)) : z4;
             u1[q] = (4 * q < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, 4 * q)) : z4;
         }
-        Comp s0 = acc0[j], s1 = acc1[j];
+        Comp s0 = acc0[j], s1 = acc1[j], t0 = opp0[j], t1 = opp1[j];
         float tau = -g.cT;
         for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
@@ -356,7 +385,7 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
                 n0[q] = (k < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, k)) : z4;
                 n1[q] = (k < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, k)) : z4;
             }
-            float p0 = 0.f, p1 = 0.f;
+            float p0 = 0.f, p1 = 0.f, o0 = 0.f, o1 = 0.f;
 #pragma unroll
             for (int q = 0; q < KC; ++q) {
                 if (k0 + q < g.nt) {
@@ -367,13 +396,22 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
                     const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
                     const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
                                              __builtin_amdgcn_fractf(Vc));
-                    p0 = fmaf(f4at(u0[q >> 2], q & 3), w.x, p0);
-                    p1 = fmaf(f4at(u1[q >> 2], q & 3), w.y, p1);
+                    const float a0 = f4at(u0[q >> 2], q & 3), a1 = f4at(u1[q >> 2], q & 3);
+                    p0 = fmaf(a0, w.x, p0);
+                    p1 = fmaf(a1, w.y, p1);
+                    if constexpr (PAIRED) {
+                        o0 = fmaf(opposed_att(e0, a0), w.x, o0);
+                        o1 = fmaf(opposed_att(e1, a1), w.y, o1);
+                    }
                 }
                 tau += 1.f;
             }
             kahan_add(s0, p0);
             kahan_add(s1, p1);
+            if constexpr (PAIRED) {
+                kahan_add(t0, o0);
+                kahan_add(t1, o1);
+            }
 #pragma unroll
             for (int q = 0; q < KG; ++q) {
                 u0[q] = n0[q];
@@ -382,6 +420,8 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
         }
         acc0[j] = s0;
         acc1[j] = s1;
+        opp0[j] = t0;
+        opp1[j] = t1;
     }
 
     // epilogues, candidate by candidate
@@ -396,31 +436,11 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
             if (j >= rpt) break;
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays || !live) continue;
-            const size_t si = cand * A.sino_cs + ray;
-            const float y = g.dx * comp_value(h ? acc1[j] : acc0[j]);
-            if constexpr (MODE == FWD_PROJ) {
-                A.y_out[si] = y;
-            } else if constexpr (MODE == FWD_RATIO) {
-                const float S = A.meas[ray];
-                A.r_out[si] = (y > 0.f) ? S / y : 0.f;
-                if (A.y_out) A.y_out[si] = y;
-            } else {  // FWD_NLL
-                const float S = A.meas[ray];
-                if (A.y_out) A.y_out[si] = y;
-                float term;
-                if (S > 0.f) {
-                    if (y > 0.f) {
-                        term = y - S * logf(y);
-                    } else if (y <= 0.f) {
-                        term = __builtin_inff();
-                        zero_proj = true;
-                    } else {
-                        term = y;  // NaN propagates (flagged as non-finite at the end)
-                    }
-                } else {
-                    term = y;
-                }
-                comp_add(nll, term);
+            fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(h ? acc1[j] : acc0[j]), nll, zero_proj);
+            if constexpr (PAIRED) {
+                const int a = ray / g.nb, b = ray - a * g.nb;
+                fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(h ? opp1[j] : opp0[j]),
+                               nll, zero_proj);
             }
         }
         if constexpr (MODE == FWD_NLL) {
@@ -757,36 +777,43 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
 static dim3 ray_grid(const RayCfg &rc, int C) { return dim3((unsigned)(rc.chunks * C)); }
 
 hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
-                      size_t img_cs, size_t att_cs, int C, hipStream_t st) {
+                      size_t img_cs, size_t att_cs, float *E, size_t e_cs, int C, hipStream_t st) {
     if (rc.single)
         hipLaunchKernelGGL(k_att<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
-                           mu, att, img_cs, att_cs);
-    else
+                           mu, att, img_cs, att_cs, E, e_cs);
+    else if (!E)
         hipLaunchKernelGGL(k_att<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
-                           C, mu, att, img_cs, att_cs);
+                           C, mu, att, img_cs, att_cs, E, e_cs);
+    else
+        return hipErrorInvalidValue;  // opposed-ray pairing needs the single-stage image
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool PAIRED>
 static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                      hipStream_t st) {
     if (rc.pair && rc.single && a.img_comps == 1 && C >= 2)
-        hipLaunchKernelGGL((k_fwd_pair<MODE>), dim3((unsigned)(rc.chunks * ((C + 1) / 2))), dim3(rc.block),
+        hipLaunchKernelGGL((k_fwd_pair<MODE, PAIRED>), dim3((unsigned)(rc.chunks * ((C + 1) / 2))), dim3(rc.block),
                            2 * rc.lds, st, g, bands, rc.rpt, rc.chunks, C, a);
     else if (rc.single)
-        hipLaunchKernelGGL((k_fwd<MODE, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                           rc.chunks, C, a);
-    else
-        hipLaunchKernelGGL((k_fwd<MODE, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
-                           rc.chunks, C, a);
+        hipLaunchKernelGGL((k_fwd<MODE, true, PAIRED>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
+                           rc.rpt, rc.chunks, C, a);
+    else if constexpr (!PAIRED)
+        hipLaunchKernelGGL((k_fwd<MODE, false, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
+                           rc.rpt, rc.chunks, C, a);
 }
 
 hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                       hipStream_t st) {
+    const bool paired = a.E != nullptr;
+    if (paired && (!rc.single || g.nah * 2 != g.na)) return hipErrorInvalidValue;
     switch (mode) {
-        case FWD_PROJ: fwd_mode<FWD_PROJ>(g, rc, bands, a, C, st); break;
-        case FWD_RATIO: fwd_mode<FWD_RATIO>(g, rc, bands, a, C, st); break;
-        case FWD_NLL: fwd_mode<FWD_NLL>(g, rc, bands, a, C, st); break;
+        case FWD_PROJ: paired ? fwd_mode<FWD_PROJ, true>(g, rc, bands, a, C, st)
+                              : fwd_mode<FWD_PROJ, false>(g, rc, bands, a, C, st); break;
+        case FWD_RATIO: paired ? fwd_mode<FWD_RATIO, true>(g, rc, bands, a, C, st)
+                               : fwd_mode<FWD_RATIO, false>(g, rc, bands, a, C, st); break;
+        case FWD_NLL: paired ? fwd_mode<FWD_NLL, true>(g, rc, bands, a, C, st)
+                             : fwd_mode<FWD_NLL, false>(g, rc, bands, a, C, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -794,6 +821,7 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
 
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
                             hipStream_t st) {
+    if (g.nah != g.na) return hipErrorInvalidValue;  // the gradient sweeps hold every angle
     if (rc.single)
         hipLaunchKernelGGL(k_adj_sweep<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
                            C, a);
@@ -805,6 +833,7 @@ hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &ban
 
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st) {
+    if (g.nah != g.na) return hipErrorInvalidValue;  // the gradient sweeps hold every angle
     if (rc.single)
         hipLaunchKernelGGL(k_tail<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
                            a);

@@ -30,6 +30,7 @@ enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2 };
 
 struct FwdArgs {
     const float *att;     // [C] attenuation tensors (4 x 8-block slabs, att_row / att_col)
+    const float *E;       // opposed-ray pairing: [C][nah][nb] exp(-T) per ray, else null
     const float *img;     // [C][n][n] x img_comps interleaved (component 0 is sampled)
     const float *meas;    // [na][nb]
     float *y_out;         // [C][na][nb] or null
@@ -37,6 +38,7 @@ struct FwdArgs {
     float2 *partial;      // NLL: [C][chunks]
     uint32_t *status;     // NLL: [C] or null
     size_t att_cs, img_cs, sino_cs;
+    size_t e_cs;          // E stride per candidate
     int img_comps;        // 1 or 2
 };
 
@@ -83,6 +85,7 @@ constexpr int kSlidPitch = 34;  // its LDS row pitch, in slots
 
 struct BackArgs {
     const float *att;     // [C] attenuation tensors (4 x 8-block slabs)
+    const float *E;       // opposed-ray pairing: [C][nah][nb] exp(-T) per ray, else null
     const float *z;       // PLAIN/MLEM/ADJ: per-ray weights [C][na][nb]; FIELD: [C] per-sample field, att layout
     const float *F;       // MLEM: current image
     const float *s;       // MLEM: sensitivity
@@ -90,6 +93,7 @@ struct BackArgs {
     float *out;           // [C][n][n]
     float *q_out;         // MLEM: update factor b/s (nullable)
     size_t att_cs, sino_cs, img_cs;
+    size_t e_cs;          // E stride per candidate
     int C;
 };
 
@@ -130,8 +134,9 @@ hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta
 // grad: [C][kGradComps] partial gradients
 hipError_t launch_raster_adj(const DevGeom &g, const float *cand, int C, float delta_r, const float *mubar,
                              size_t img_cs, float *grad, hipStream_t st);
+// E: with opposed-ray pairing (g.nah < g.na) exp(-T) per ray [C][nah][nb] (stride e_cs), else null
 hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
-                      size_t img_cs, size_t att_cs, int C, hipStream_t st);
+                      size_t img_cs, size_t att_cs, float *E, size_t e_cs, int C, hipStream_t st);
 hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                       hipStream_t st);
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,

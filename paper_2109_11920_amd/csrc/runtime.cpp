@@ -217,8 +217,9 @@ static boac_status host_trig(int na, std::vector<float2> &h) {
 // Footprint rectangles of every (pixel tile, angle) of the backprojection: bins and samples whose
 // window can reach a pixel of the tile, with one sample of margin on every side (the kernel's window
 // centres, computed in FP32, stay inside). Computed in double from the same FP32 angle table.
-static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
-    std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb, bc->slid};
+// nah: angles held (the first nah of the n_angles, the table's stride per tile).
+static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc, int nah) {
+    std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb, bc->slid, nah};
     auto it = ctx->rects.find(key);
     if (it != ctx->rects.end()) {
         bc->rects = it->second;
@@ -232,13 +233,13 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
     const int ntiles = bc->tiles_x * bc->tiles_y;
     const int wb_cap = std::min(bc->wbmax, 64);
     const int wk_cap = bc->wkmax;
-    std::vector<int4> h((size_t)ntiles * g.n_angles);
+    std::vector<int4> h((size_t)ntiles * nah);
     for (int t = 0; t < ntiles; ++t) {
         const int ty = t / bc->tiles_x, tx = t % bc->tiles_x;
         const int l0 = tx * bc->tw, i0 = ty * bc->th;
         const double xl[2] = {l0 - cN, std::min(l0 + bc->tw - 1, g.n - 1) - cN};
         const double yi[2] = {i0 - cN, std::min(i0 + bc->th - 1, g.n - 1) - cN};
-        for (int a = 0; a < g.n_angles; ++a) {
+        for (int a = 0; a < nah; ++a) {
             const double c = trig[a].x, s = trig[a].y;
             double Smin = 1e300, Smax = -1e300, Tmin = 1e300, Tmax = -1e300;
             for (double x : xl)
@@ -277,14 +278,14 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
                 int ub, vb;
                 std::memcpy(&ub, &uf, 4);
                 std::memcpy(&vb, &vf, 4);
-                h[(size_t)t * g.n_angles + a] = make_int4(b0, k0, ub, vb);
+                h[(size_t)t * nah + a] = make_int4(b0, k0, ub, vb);
                 continue;
             }
             const int slots = (bc->hb > 1) ? 8 : (bc->tw == 16 && bc->th == 16) ? 4 : (bc->tw == 32 && bc->th == 16) ? 8 : 11;
             if (wb > wb_cap || wk > wk_cap || wb * wk > 256 * slots)
                 return fail(BOAC_EDEVICE, "internal: footprint %dx%d exceeds the staged bound %dx%d", wb, wk, wb_cap,
                             wk_cap);
-            h[(size_t)t * g.n_angles + a] = make_int4(b_lo, k_lo, wb, wk);
+            h[(size_t)t * nah + a] = make_int4(b_lo, k_lo, wb, wk);
         }
     }
     int4 *d = nullptr;
@@ -298,6 +299,7 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc) {
 static boac_status dev_geom(boac_ctx *ctx, const boac_geom &g, DevGeom *dg) {
     dg->n = g.n;
     dg->na = g.n_angles;
+    dg->nah = g.n_angles;
     dg->nb = g.n_bins;
     dg->nt = g.n_samples;
     dg->dx = g.pixel_cm;
@@ -342,9 +344,10 @@ static std::string shape_key(const char *kind, const boac_geom &g, int C, int ex
     return buf;
 }
 
-static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands) {
+// nah: angles whose rays the kernels walk (n_angles, or half of them with opposed-ray pairing).
+static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands, int nah) {
     make_bands(g.n, comps, rc, bands);
-    const int nrays = g.n_angles * g.n_bins;
+    const int nrays = nah * g.n_bins;
     // default: the largest workgroups (the image stage is shared by more waves, and a stage that
     // fills the LDS still gives 16 waves per CU) and the most rays per thread that still give every
     // CU a workgroup
@@ -472,11 +475,12 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
     }
 }
 
-static boac_status make_plan(boac_ctx *ctx, const boac_geom &g, int C, Plan *p) {
-    ray_plan(ctx, g, C, 1, &p->ray1, &p->bands1);
-    ray_plan(ctx, g, C, 2, &p->ray2, &p->bands2);
+static boac_status make_plan(boac_ctx *ctx, const boac_geom &g, int C, Plan *p, int nah = -1) {
+    if (nah < 0) nah = g.n_angles;
+    ray_plan(ctx, g, C, 1, &p->ray1, &p->bands1, nah);
+    ray_plan(ctx, g, C, 2, &p->ray2, &p->bands2, nah);
     back_plan(ctx, g, C, &p->back);
-    return rect_table(ctx, g, &p->back);
+    return rect_table(ctx, g, &p->back, nah);
 }
 
 // ------------------------------------------------------------------ instrumentation
@@ -528,17 +532,45 @@ static boac_status drain_timings(boac_ctx *ctx) {
 struct Sizes {
     size_t I, Y, V;  // elements per candidate: image, sinogram, attenuation tensor (algorithmic)
     size_t VS;       // attenuation tensor stride per candidate (4 x 8-block slabs, padded)
+    size_t E;        // opposed-ray pairing: exp(-T) per held ray (0 without pairing)
 };
-static Sizes sizes_of(const boac_geom &g) {
-    return Sizes{(size_t)g.n * g.n, (size_t)g.n_angles * g.n_bins, (size_t)g.n_angles * g.n_bins * g.n_samples,
-                 (size_t)g.n_angles * att_slab(g)};
+// nah: angles the attenuation tensor holds (n_angles, or n_angles / 2 with opposed-ray pairing)
+static Sizes sizes_of(const boac_geom &g, int nah = -1) {
+    if (nah < 0) nah = g.n_angles;
+    return Sizes{(size_t)g.n * g.n, (size_t)g.n_angles * g.n_bins, (size_t)nah * g.n_bins * g.n_samples,
+                 (size_t)nah * att_slab(g), nah < g.n_angles ? (size_t)nah * g.n_bins : 0};
+}
+
+// Opposed-ray pairing (the attenuation tensor for half the angles plus exp(-T) per ray, both rays of a
+// line from one pass) applies to an even angle count with single-stage ray kernels and the
+// column-group gather; BOAC_OPPOSED_RAYS=0 turns it off.
+static bool pairing_enabled() {
+    const char *e = std::getenv("BOAC_OPPOSED_RAYS");
+    return !(e && e[0] == '0');
+}
+
+// Launch geometry, plan and sizes of one slice for the attenuation-weighted paths (projection,
+// backprojection, MLEM, objective); with allow_pairing, opposed-ray pairing where it applies.
+static boac_status plan_slice(boac_ctx *ctx, const boac_geom &g, int C, bool allow_pairing, DevGeom *dg, Plan *p,
+                              Sizes *z) {
+    BOAC_TRY(dev_geom(ctx, g, dg));
+    *z = sizes_of(g);
+    BOAC_TRY(make_plan(ctx, g, C, p));
+    if (allow_pairing && pairing_enabled() && g.n_angles % 2 == 0 && p->ray1.single && p->back.slid == 2) {
+        const int nah = g.n_angles / 2;
+        dg->nah = nah;
+        *z = sizes_of(g, nah);
+        BOAC_TRY(make_plan(ctx, g, C, p, nah));
+        if (!(p->ray1.single && p->back.slid == 2)) return fail(BOAC_EDEVICE, "internal: paired plan changed family");
+    }
+    return BOAC_OK;
 }
 
 // Bytes models (algorithmic HBM traffic per launch) used by the instrumentation.
-static double bytes_att(const Sizes &z, int C) { return 4.0 * C * (double)(z.I + z.V); }
-static double bytes_fwd(const Sizes &z, int C) { return 4.0 * C * (double)(z.V + z.I + 2 * z.Y); }
+static double bytes_att(const Sizes &z, int C) { return 4.0 * C * (double)(z.I + z.V + z.E); }
+static double bytes_fwd(const Sizes &z, int C) { return 4.0 * C * (double)(z.V + z.E + z.I + 2 * z.Y); }
 static double bytes_back(const Sizes &z, int C, int mode) {
-    double per = (double)z.V + z.I;  // att read + image written
+    double per = (double)z.V + z.E + z.I;  // att (and exp(-T)) read + image written
     if (mode == BACK_PLAIN || mode == BACK_MLEM || mode == BACK_ADJ) per += z.Y;
     if (mode == BACK_MLEM) per += 2.0 * z.I;
     if (mode == BACK_ADJ) per += z.I;
@@ -546,10 +578,11 @@ static double bytes_back(const Sizes &z, int C, int mode) {
     return 4.0 * C * per;
 }
 
+// E: exp(-T) per held ray with opposed-ray pairing (z.E > 0), else null
 static boac_status run_att(boac_ctx *ctx, const DevGeom &dg, const Plan &p, const Sizes &z, const float *mu,
-                           float *att, int C, hipStream_t st) {
+                           float *att, int C, hipStream_t st, float *E = nullptr) {
     return timed(ctx, BOAC_K_ATT, bytes_att(z, C), st,
-                 [&] { return launch_att(dg, p.ray1, p.bands1, mu, att, z.I, z.VS, C, st); });
+                 [&] { return launch_att(dg, p.ray1, p.bands1, mu, att, z.I, z.VS, E, z.E, C, st); });
 }
 
 static boac_status run_fwd(boac_ctx *ctx, int mode, const DevGeom &dg, const Plan &p, const Sizes &z,
@@ -564,9 +597,12 @@ static boac_status run_back(boac_ctx *ctx, int mode, const DevGeom &dg, const Pl
                  [&] { return launch_back(mode, dg, p.back, a, st); });
 }
 
-static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, const float *meas) {
+static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, const float *meas,
+                        const float *E = nullptr) {
     FwdArgs a{};
     a.att = att;
+    a.E = E;
+    a.e_cs = z.E;
     a.img = img;
     a.meas = meas;
     a.att_cs = z.VS;
@@ -575,9 +611,12 @@ static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, cons
     a.img_comps = 1;
     return a;
 }
-static BackArgs back_args(const Sizes &z, const float *att, const float *zz, float *out, int C) {
+static BackArgs back_args(const Sizes &z, const float *att, const float *zz, float *out, int C,
+                          const float *E = nullptr) {
     BackArgs a{};
     a.att = att;
+    a.E = E;
+    a.e_cs = z.E;
     a.z = zz;
     a.out = out;
     a.att_cs = z.VS;
@@ -601,12 +640,13 @@ static int cand_chunk(const Sizes &z, int C, int tensors) {
 static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
                                 float delta_r, int K, float *obj, float *img_out, uint32_t *status, hipStream_t st,
                                 float *env_grad = nullptr, int ncomp = 8) {
-    const Sizes z = sizes_of(g);
+    const int Cc = cand_chunk(sizes_of(g), C, env_grad ? 2 : 1);
     DevGeom dg;
-    BOAC_TRY(dev_geom(ctx, g, &dg));
-    const int Cc = cand_chunk(z, C, env_grad ? 2 : 1);
     Plan p;
-    BOAC_TRY(make_plan(ctx, g, Cc, &p));
+    Sizes z;
+    BOAC_TRY(plan_slice(ctx, g, Cc, env_grad == nullptr, &dg, &p, &z));
+    float *E = nullptr;
+    if (z.E) BOAC_TRY(ensure_t(ctx, "attE", (size_t)Cc * z.E, &E));
     float *mu, *att, *s, *F0, *F1, *r;
     float2 *partial, *lg;
     uint32_t *flag, *st_int;
@@ -642,24 +682,24 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
         const float *cd = cand + (size_t)c0 * 8;
         BOAC_TRY(timed(ctx, BOAC_K_RASTER, 4.0 * n * (8 + z.I), st,
                        [&] { return launch_raster(dg, cd, n, delta_r, mu, z.I, stat + c0, st); }));
-        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st, E));
         {
-            BackArgs b = back_args(z, att, nullptr, s, n);
+            BackArgs b = back_args(z, att, nullptr, s, n, E);
             BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, b, st));
         }
         HIP_TRY(launch_fill(F0, (size_t)n * z.I, 1.f, st));
         float *Fc = F0, *Fn = F1;
         for (int it = 0; it < K; ++it) {
-            FwdArgs a = fwd_args(z, att, Fc, meas);
+            FwdArgs a = fwd_args(z, att, Fc, meas, E);
             a.r_out = r;
             BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
-            BackArgs b = back_args(z, att, r, Fn, n);
+            BackArgs b = back_args(z, att, r, Fn, n, E);
             b.F = Fc;
             b.s = s;
             BOAC_TRY(run_back(ctx, BACK_MLEM, dg, p, z, b, st));
             std::swap(Fc, Fn);
         }
-        FwdArgs a = fwd_args(z, att, Fc, meas);
+        FwdArgs a = fwd_args(z, att, Fc, meas, E);
         a.partial = partial;
         a.status = stat + c0;
         a.y_out = yK;
@@ -1017,13 +1057,15 @@ boac_status boac_rasterize_mu(boac_ctx *ctx, const boac_geom *geom, const boac_c
 }
 
 // att for a chunk of candidates from caller mu maps
-static boac_status build_att(boac_ctx *ctx, const boac_geom &g, const DevGeom &dg, const Plan &p, const float *mu,
-                             int n, float **att_out, hipStream_t st) {
-    const Sizes z = sizes_of(g);
-    float *att;
+// The attenuation tensors of n candidates (and exp(-T) per held ray with opposed-ray pairing).
+static boac_status build_att(boac_ctx *ctx, const Sizes &z, const DevGeom &dg, const Plan &p, const float *mu,
+                             int n, float **att_out, float **E_out, hipStream_t st) {
+    float *att, *E = nullptr;
     BOAC_TRY(ensure_t(ctx, "att", (size_t)n * z.VS, &att));
-    BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+    if (z.E) BOAC_TRY(ensure_t(ctx, "attE", (size_t)n * z.E, &E));
+    BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st, E));
     *att_out = att;
+    *E_out = E;
     return BOAC_OK;
 }
 
@@ -1036,17 +1078,16 @@ boac_status boac_project(boac_ctx *ctx, const boac_geom *geom, const float *d_mu
     BOAC_TRY(check_ptr(d_sino, "d_sino"));
     CTX_CHECK();
     hipStream_t st = (hipStream_t)stream;
-    const Sizes z = sizes_of(*geom);
+    const int Cc = cand_chunk(sizes_of(*geom), C, 1);
     DevGeom dg;
-    BOAC_TRY(dev_geom(ctx, *geom, &dg));
-    const int Cc = cand_chunk(z, C, 1);
     Plan p;
-    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
+    Sizes z;
+    BOAC_TRY(plan_slice(ctx, *geom, Cc, true, &dg, &p, &z));
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int n = std::min(Cc, C - c0);
-        float *att;
-        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
-        FwdArgs a = fwd_args(z, att, d_img + (size_t)c0 * z.I, nullptr);
+        float *att, *E;
+        BOAC_TRY(build_att(ctx, z, dg, p, d_mu + (size_t)c0 * z.I, n, &att, &E, st));
+        FwdArgs a = fwd_args(z, att, d_img + (size_t)c0 * z.I, nullptr, E);
         a.y_out = d_sino + (size_t)c0 * z.Y;
         BOAC_TRY(run_fwd(ctx, FWD_PROJ, dg, p, z, a, n, st));
     }
@@ -1062,17 +1103,16 @@ boac_status boac_backproject(boac_ctx *ctx, const boac_geom *geom, const float *
     BOAC_TRY(check_ptr(d_img, "d_img"));
     CTX_CHECK();
     hipStream_t st = (hipStream_t)stream;
-    const Sizes z = sizes_of(*geom);
+    const int Cc = cand_chunk(sizes_of(*geom), C, 1);
     DevGeom dg;
-    BOAC_TRY(dev_geom(ctx, *geom, &dg));
-    const int Cc = cand_chunk(z, C, 1);
     Plan p;
-    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
+    Sizes z;
+    BOAC_TRY(plan_slice(ctx, *geom, Cc, true, &dg, &p, &z));
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int n = std::min(Cc, C - c0);
-        float *att;
-        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
-        BackArgs b = back_args(z, att, d_sino + (size_t)c0 * z.Y, d_img + (size_t)c0 * z.I, n);
+        float *att, *E;
+        BOAC_TRY(build_att(ctx, z, dg, p, d_mu + (size_t)c0 * z.I, n, &att, &E, st));
+        BackArgs b = back_args(z, att, d_sino + (size_t)c0 * z.Y, d_img + (size_t)c0 * z.I, n, E);
         BOAC_TRY(run_back(ctx, BACK_PLAIN, dg, p, z, b, st));
     }
     return BOAC_OK;
@@ -1088,29 +1128,28 @@ boac_status boac_mlem(boac_ctx *ctx, const boac_geom *geom, const float *d_mu, c
     if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
     CTX_CHECK();
     hipStream_t st = (hipStream_t)stream;
-    const Sizes z = sizes_of(*geom);
+    const int Cc = cand_chunk(sizes_of(*geom), C, 1);
     DevGeom dg;
-    BOAC_TRY(dev_geom(ctx, *geom, &dg));
-    const int Cc = cand_chunk(z, C, 1);
     Plan p;
-    BOAC_TRY(make_plan(ctx, *geom, Cc, &p));
+    Sizes z;
+    BOAC_TRY(plan_slice(ctx, *geom, Cc, true, &dg, &p, &z));
     float *s, *Fs, *r;
     BOAC_TRY(ensure_t(ctx, "s", (size_t)Cc * z.I, &s));
     BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &Fs));
     BOAC_TRY(ensure_t(ctx, "r", (size_t)Cc * z.Y, &r));
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int n = std::min(Cc, C - c0);
-        float *att;
-        BOAC_TRY(build_att(ctx, *geom, dg, p, d_mu + (size_t)c0 * z.I, n, &att, st));
-        BackArgs sb = back_args(z, att, nullptr, s, n);
+        float *att, *E;
+        BOAC_TRY(build_att(ctx, z, dg, p, d_mu + (size_t)c0 * z.I, n, &att, &E, st));
+        BackArgs sb = back_args(z, att, nullptr, s, n, E);
         BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, sb, st));
         float *Fio = d_img_inout + (size_t)c0 * z.I;
         float *Fc = Fio, *Fn = Fs;
         for (int it = 0; it < n_iter; ++it) {
-            FwdArgs a = fwd_args(z, att, Fc, d_meas);
+            FwdArgs a = fwd_args(z, att, Fc, d_meas, E);
             a.r_out = r;
             BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
-            BackArgs b = back_args(z, att, r, Fn, n);
+            BackArgs b = back_args(z, att, r, Fn, n, E);
             b.F = Fc;
             b.s = s;
             BOAC_TRY(run_back(ctx, BACK_MLEM, dg, p, z, b, st));
