@@ -568,7 +568,8 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
 // PAIRED (opposed-ray pairing, g.nah = na/2): the slab of angle a < na/2 also stands for angle
 // a + na/2, whose sample (nb-1-b, nt-1-k) sits at sample (b, k) of angle a with attenuation
 // exp(-T_ab) / att and the same bilinear weights; each staged slot holds both contributions,
-// att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles.
+// att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles. In the
+// field mode (mu_bar = W^T m_bar) the slot holds m_bar + dx Tbar_ab, the per-ray value in A.E.
 template <int CG, bool WEIGHTED, bool PAIRED>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
@@ -683,8 +684,12 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
                 v[q] = WEIGHTED ? x * zv[q] : x;
                 if constexpr (PAIRED) {
-                    const float xo = x > 1e-30f ? ev[q] * __builtin_amdgcn_rcpf(x) : 0.f;
-                    v[q] = WEIGHTED ? fmaf(xo, zo[q], v[q]) : v[q] + xo;
+                    if (mode == BACK_FIELD) {
+                        v[q] = x + ev[q];  // m_bar plus the ray's dx Tbar
+                    } else {
+                        const float xo = x > 1e-30f ? ev[q] * __builtin_amdgcn_rcpf(x) : 0.f;
+                        v[q] = WEIGHTED ? fmaf(xo, zo[q], v[q]) : v[q] + xo;
+                    }
                 }
             }
             float *d = lds + ((4 * kb + t) * PL + bb) * V;
@@ -778,8 +783,7 @@ static hipError_t back_col4(const DevGeom &g, const BackCfg &bc, const BackArgs 
     const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
     const bool weighted = !(mode == BACK_SENS || mode == BACK_FIELD);
     if (a.E) {
-        // opposed-ray pairing covers the attenuation-weighted modes only
-        if (mode == BACK_FIELD || mode == BACK_ADJ || g.nah * 2 != g.na) return hipErrorInvalidValue;
+        if (g.nah * 2 != g.na) return hipErrorInvalidValue;
         if (weighted)
             hipLaunchKernelGGL((k_back_col4<CG, true, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
         else

@@ -458,12 +458,17 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
 //   ybar^n_i = -rbar_i r^n_i / y^n_i   (0 where y^n_i <= 0)               (adjoint of r = S / y)
 // The ybar^{n+1} term is the y^{n+1} = A F^{n+1} adjoint left pending by the previous step (or the
 // objective's adjoint for the first step), so each step sweeps the rays once.
-template <bool SINGLE>
+// PAIRED (opposed-ray pairing, single stage): the held ray i also carries the opposed ray i', whose
+// attenuation at the shared sample is att' = exp(-T) / att; its r_bar and ybar are formed the same
+// way, and its attenuation adjoint c' = dx [ r^n_i' W bbar + ybar^{n+1}_i' W F^{n+1} ] reaches the
+// held tensors through att' = E / att: att_bar += -att' c' / att, E_bar += c' / att.
+template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
+    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
-    const int nrays = g.na * g.nb;
+    const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     const float *att = A.att + cand * A.att_cs;
@@ -471,9 +476,9 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
     const float *img = A.pair + cand * A.img_cs;
     const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
 
-    Comp acc[kMaxRpt];
+    Comp acc[kMaxRpt], acc2[kMaxRpt];
 #pragma unroll
-    for (int j = 0; j < kMaxRpt; ++j) acc[j] = Comp{0.f, 0.f};
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
@@ -511,6 +516,11 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                     at[q] = (4 * q < g.nt) ? buffer_ld4(ra, roff, o) : z4;
                     bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                 }
+                const size_t si2 = cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b));
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                const float rr2 = PAIRED ? g.dx * A.r[si2] : 0.f;
+                const float yp2 = PAIRED ? g.dx * A.ybar_in[si2] : 0.f;
+                Comp c2 = acc2[j], eb{0.f, 0.f};
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
@@ -520,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                         an[q] = (k < g.nt) ? buffer_ld4(ra, roff, o) : z4;
                         bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                     }
-                    float part = 0.f;
+                    float part = 0.f, part2 = 0.f, epart = 0.f;
                     float ov[4];
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
@@ -534,19 +544,39 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                             const int idx = (int)fmaf(floorf(Vc), (float)pitch, floorf(Uc));
                             const float2 w = lerp2x2(lds2 + idx + (pitch + 1), pitch, __builtin_amdgcn_fractf(Uc),
                                                      __builtin_amdgcn_fractf(Vc));
-                            part = fmaf(f4at(at[q >> 2], q & 3), w.x, part);
-                            ov[q & 3] = f4at(bt[q >> 2], q & 3) + fmaf(rr, w.x, yp * w.y);
+                            const float a0 = f4at(at[q >> 2], q & 3);
+                            part = fmaf(a0, w.x, part);
+                            const float cv = fmaf(rr, w.x, yp * w.y);
+                            if constexpr (PAIRED) {
+                                const float ri = a0 > 1e-30f ? __builtin_amdgcn_rcpf(a0) : 0.f;
+                                const float ao = e_ray * ri;
+                                const float cv2 = fmaf(rr2, w.x, yp2 * w.y);
+                                part2 = fmaf(ao, w.x, part2);
+                                epart = fmaf(cv2, ri, epart);
+                                ov[q & 3] = f4at(bt[q >> 2], q & 3) + fmaf(-ao * ri, cv2, cv);
+                            } else {
+                                ov[q & 3] = f4at(bt[q >> 2], q & 3) + cv;
+                            }
                         }
                         tau += 1.f;
                         if ((q & 3) == 3 && k - 3 < g.nt)
                             buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     kahan_add(c, part);
+                    if constexpr (PAIRED) {
+                        kahan_add(c2, part2);
+                        kahan_add(eb, epart);
+                    }
 #pragma unroll
                     for (int q = 0; q < KG; ++q) {
                         at[q] = an[q];
                         bt[q] = bn[q];
                     }
+                }
+                if constexpr (PAIRED) {
+                    acc2[j] = c2;
+                    float *eo = A.Ebar + cand * A.e_cs + ray;
+                    *eo = (A.accumulate ? *eo : 0.f) + comp_value(eb);
                 }
             } else {
                 // the ray's samples in this band, 16 at a time (loads of att, and of att_bar when
@@ -604,6 +634,13 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
         const float rbar = g.dx * comp_value(acc[j]);
         const float yn = A.y[si];
         A.ybar_out[si] = (yn > 0.f) ? -(rbar * A.r[si]) / yn : 0.f;
+        if constexpr (PAIRED) {
+            const int a = ray / g.nb, b = ray - a * g.nb;
+            const size_t si2 = cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b));
+            const float rbar2 = g.dx * comp_value(acc2[j]);
+            const float yn2 = A.y[si2];
+            A.ybar_out[si2] = (yn2 > 0.f) ? -(rbar2 * A.r[si2]) / yn2 : 0.f;
+        }
     }
 }
 
@@ -612,12 +649,17 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
 // (the sensitivity adjoint and the last pending projection adjoint); then
 // L_bar = -att * att_bar and m_bar_k = dx (L_bar_k / 2 + sum_{k'<k} L_bar_k') (the scan's transpose),
 // written in place of att_bar.
-template <bool SINGLE>
+// PAIRED (opposed-ray pairing, single stage): the opposed ray's part c' = dx (W G1 + rho_i' W G2)
+// reaches att_bar and E_bar as in the sweep; at the ray's end Tbar = -E E_bar (E = exp(-T)), and
+// since T = dx sum_k m_k every sample's m_bar gains dx Tbar, written per ray in place of E_bar (the
+// field gather adds it).
+template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
+    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
-    const int nrays = g.na * g.nb;
+    const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     const float *att = A.att + cand * A.att_cs;
@@ -656,6 +698,10 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                     bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                 }
                 Comp P{0.f, 0.f};
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                const float rho2 =
+                    PAIRED ? A.rho[cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b))] : 0.f;
+                Comp eb{0.f, 0.f};
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
@@ -666,6 +712,7 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                         bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
                     }
                     float ov[4];
+                    float epart = 0.f;
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
                         const int k = k0 + q;
@@ -678,8 +725,18 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                             const int l0 = __float2int_rd(Uc), i0 = __float2int_rd(Vc);
                             const float2 w = lerp2x2(lds2 + (i0 + 1) * pitch + (l0 + 1), pitch,
                                                      __builtin_amdgcn_fractf(Uc), __builtin_amdgcn_fractf(Vc));
-                            const float abar = f4at(bt[q >> 2], q & 3) + g.dx * fmaf(rho, w.y, w.x);
-                            const float Lbar = -f4at(at[q >> 2], q & 3) * abar;
+                            const float a0 = f4at(at[q >> 2], q & 3);
+                            float abar;
+                            if constexpr (PAIRED) {
+                                const float ri = a0 > 1e-30f ? __builtin_amdgcn_rcpf(a0) : 0.f;
+                                const float ao = e_ray * ri;
+                                const float cv2 = g.dx * fmaf(rho2, w.y, w.x);
+                                epart = fmaf(cv2, ri, epart);
+                                abar = f4at(bt[q >> 2], q & 3) + fmaf(-ao * ri, cv2, g.dx * fmaf(rho, w.y, w.x));
+                            } else {
+                                abar = f4at(bt[q >> 2], q & 3) + g.dx * fmaf(rho, w.y, w.x);
+                            }
+                            const float Lbar = -a0 * abar;
                             ov[q & 3] = g.dx * (fmaf(0.5f, Lbar, P.s) + P.e);
                             comp_add(P, Lbar);
                         }
@@ -687,11 +744,17 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                         if ((q & 3) == 3 && k - 3 < g.nt)
                             buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
+                    if constexpr (PAIRED) kahan_add(eb, epart);
 #pragma unroll
                     for (int q = 0; q < KG; ++q) {
                         at[q] = an[q];
                         bt[q] = bn[q];
                     }
+                }
+                if constexpr (PAIRED) {
+                    float *eo = A.Ebar + cand * A.e_cs + ray;
+                    const float etot = (A.accumulate ? *eo : 0.f) + comp_value(eb);
+                    *eo = g.dx * (-e_ray * etot);
                 }
             } else {
                 // pass 1 of 2 (band by band): att_bar (+)= dx (W G1 + rho W G2), 16 samples at a time
@@ -821,25 +884,35 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
 
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
                             hipStream_t st) {
-    if (g.nah != g.na) return hipErrorInvalidValue;  // the gradient sweeps hold every angle
-    if (rc.single)
-        hipLaunchKernelGGL(k_adj_sweep<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
-                           C, a);
-    else
-        hipLaunchKernelGGL(k_adj_sweep<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+    const bool paired = a.E != nullptr;
+    if (paired != (g.nah != g.na) || (paired && (!rc.single || g.nah * 2 != g.na || !a.Ebar)))
+        return hipErrorInvalidValue;
+    if (paired)
+        hipLaunchKernelGGL((k_adj_sweep<true, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
                            rc.chunks, C, a);
+    else if (rc.single)
+        hipLaunchKernelGGL((k_adj_sweep<true, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+    else
+        hipLaunchKernelGGL((k_adj_sweep<false, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
+                           rc.rpt, rc.chunks, C, a);
     return hipGetLastError();
 }
 
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st) {
-    if (g.nah != g.na) return hipErrorInvalidValue;  // the gradient sweeps hold every angle
-    if (rc.single)
-        hipLaunchKernelGGL(k_tail<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
-                           a);
+    const bool paired = a.E != nullptr;
+    if (paired != (g.nah != g.na) || (paired && (!rc.single || g.nah * 2 != g.na || !a.Ebar)))
+        return hipErrorInvalidValue;
+    if (paired)
+        hipLaunchKernelGGL((k_tail<true, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+    else if (rc.single)
+        hipLaunchKernelGGL((k_tail<true, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
     else
-        hipLaunchKernelGGL(k_tail<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
-                           C, a);
+        hipLaunchKernelGGL((k_tail<false, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
     return hipGetLastError();
 }
 

@@ -52,6 +52,11 @@ struct SweepArgs {
     float *ybar_out;      // ybar^n
     size_t att_cs, img_cs, sino_cs;  // img_cs in floats (2 n^2 per candidate)
     int accumulate;
+    // opposed-ray pairing (else null): exp(-T) per held ray and its adjoint Ebar (same layout),
+    // written (accumulate = 0) or accumulated
+    const float *E;
+    float *Ebar;
+    size_t e_cs;
 };
 
 struct TailArgs {
@@ -61,6 +66,11 @@ struct TailArgs {
     const float *rho;     // ybar^0 [C][na][nb]
     size_t att_cs, img_cs, sino_cs;
     int accumulate;       // 0: att_bar starts at zero (no MLEM iterations)
+    // opposed-ray pairing (else null): exp(-T) per held ray; Ebar in: its accumulated adjoint,
+    // out: dx Tbar, the per-ray term every sample of the held ray adds to m_bar
+    const float *E;
+    float *Ebar;
+    size_t e_cs;
 };
 
 enum BackMode { BACK_PLAIN = 0, BACK_SENS = 1, BACK_MLEM = 2, BACK_FIELD = 3, BACK_ADJ = 4 };

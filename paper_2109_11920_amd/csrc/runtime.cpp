@@ -551,12 +551,15 @@ static bool pairing_enabled() {
 
 // Launch geometry, plan and sizes of one slice for the attenuation-weighted paths (projection,
 // backprojection, MLEM, objective); with allow_pairing, opposed-ray pairing where it applies.
+// pair_stage: the caller also runs the two-image ray kernels (the gradient's sweeps and tail), which
+// then need a single stage too.
 static boac_status plan_slice(boac_ctx *ctx, const boac_geom &g, int C, bool allow_pairing, DevGeom *dg, Plan *p,
-                              Sizes *z) {
+                              Sizes *z, bool pair_stage = false) {
     BOAC_TRY(dev_geom(ctx, g, dg));
     *z = sizes_of(g);
     BOAC_TRY(make_plan(ctx, g, C, p));
-    if (allow_pairing && pairing_enabled() && g.n_angles % 2 == 0 && p->ray1.single && p->back.slid == 2) {
+    if (allow_pairing && pairing_enabled() && g.n_angles % 2 == 0 && p->ray1.single && p->back.slid == 2 &&
+        (!pair_stage || p->ray2.single)) {
         const int nah = g.n_angles / 2;
         dg->nah = nah;
         *z = sizes_of(g, nah);
@@ -644,9 +647,10 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     DevGeom dg;
     Plan p;
     Sizes z;
-    BOAC_TRY(plan_slice(ctx, g, Cc, env_grad == nullptr, &dg, &p, &z));
-    float *E = nullptr;
+    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z, env_grad != nullptr));
+    float *E = nullptr, *Ebar = nullptr;
     if (z.E) BOAC_TRY(ensure_t(ctx, "attE", (size_t)Cc * z.E, &E));
+    if (z.E && env_grad) BOAC_TRY(ensure_t(ctx, "attEbar", (size_t)Cc * z.E, &Ebar));
     float *mu, *att, *s, *F0, *F1, *r;
     float2 *partial, *lg;
     uint32_t *flag, *st_int;
@@ -724,9 +728,12 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
             ta.img_cs = 2 * z.I;
             ta.sino_cs = z.Y;
             ta.accumulate = 0;
-            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (2.0 * z.V + 2 * z.I + z.Y), st,
+            ta.E = E;
+            ta.Ebar = Ebar;
+            ta.e_cs = z.E;
+            BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (2.0 * z.V + 2 * z.E + 2 * z.I + z.Y), st,
                            [&] { return launch_tail(dg, p.ray2, p.bands2, ta, n, st); }));
-            BackArgs b = back_args(z, att, attbar, mubar, n);
+            BackArgs b = back_args(z, att, attbar, mubar, n, Ebar);
             BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
             BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * z.I, st,
                            [&] { return launch_raster_adj(dg, cd, n, delta_r, mubar, z.I, gtmp, st); }));
@@ -743,15 +750,19 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
 static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
                              float delta_r, int K, int ck, float *obj, float *grad, uint32_t *status, hipStream_t st,
                              int ncomp = 8) {
-    const Sizes z = sizes_of(g);
-    DevGeom dg;
-    BOAC_TRY(dev_geom(ctx, g, &dg));
     if (ck < 1) ck = 1;
     if (ck > std::max(K, 1)) ck = std::max(K, 1);
     const int nck = (K + ck - 1) / ck;  // stored records 0, ck, 2ck, ... < K
-    const int Cc = cand_chunk(z, C, 2);
+    const int Cc = cand_chunk(sizes_of(g), C, 2);
+    DevGeom dg;
     Plan p;
-    BOAC_TRY(make_plan(ctx, g, Cc, &p));
+    Sizes z;
+    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z, true));
+    float *E = nullptr, *Ebar = nullptr;
+    if (z.E) {
+        BOAC_TRY(ensure_t(ctx, "attE", (size_t)Cc * z.E, &E));
+        BOAC_TRY(ensure_t(ctx, "attEbar", (size_t)Cc * z.E, &Ebar));
+    }
     const size_t I = z.I, Y = z.Y;
     float *mu, *att, *attbar, *s, *sbar, *fbar, *fdir, *mubar, *gtmp, *yK, *ybar, *ybar2, *Ftmp, *Fwork;
     float2 *pair, *partial, *lg;
@@ -799,18 +810,18 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
 
         BOAC_TRY(timed(ctx, BOAC_K_RASTER, 4.0 * n * (8 + I), st,
                        [&] { return launch_raster(dg, cd, n, delta_r, mu, I, stat + c0, st); }));
-        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st));
+        BOAC_TRY(run_att(ctx, dg, p, z, mu, att, n, st, E));
         {
-            BackArgs b = back_args(z, att, nullptr, s, n);
+            BackArgs b = back_args(z, att, nullptr, s, n, E);
             BOAC_TRY(run_back(ctx, BACK_SENS, dg, p, z, b, st));
         }
         // one MLEM iteration from record (F, y, r, Q) slots: fills y, r, Q and writes F^{n+1} to Fnext
         auto iterate = [&](const float *F, float *y, float *r, float *Q, float *Fnext) -> boac_status {
-            FwdArgs a = fwd_args(z, att, F, meas);
+            FwdArgs a = fwd_args(z, att, F, meas, E);
             a.r_out = r;
             a.y_out = y;
             BOAC_TRY(run_fwd(ctx, FWD_RATIO, dg, p, z, a, n, st));
-            BackArgs b = back_args(z, att, r, Fnext, n);
+            BackArgs b = back_args(z, att, r, Fnext, n, E);
             b.F = F;
             b.s = s;
             b.q_out = Q;
@@ -839,7 +850,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
         }
         // ---- objective at F^K (y^K kept for the reverse sweep)
         {
-            FwdArgs a = fwd_args(z, att, Fcur, meas);
+            FwdArgs a = fwd_args(z, att, Fcur, meas, E);
             a.partial = partial;
             a.status = stat + c0;
             a.y_out = yK;
@@ -856,7 +867,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
         BOAC_TRY(timed(ctx, BOAC_K_OTHER, 12.0 * nY, st,
                        [&] { return launch_ybar_final(meas, yK, ypend, n, (int)Y, Y, st); }));
         if (K > 0) {
-            BackArgs b = back_args(z, att, ypend, fbar, n);
+            BackArgs b = back_args(z, att, ypend, fbar, n, E);
             BOAC_TRY(run_back(ctx, BACK_PLAIN, dg, p, z, b, st));
         }
         bool first = true;
@@ -905,12 +916,15 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
                 sa.img_cs = 2 * I;
                 sa.sino_cs = Y;
                 sa.accumulate = first ? 0 : 1;
+                sa.E = E;
+                sa.Ebar = Ebar;
+                sa.e_cs = z.E;
                 BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * ((first ? 2.0 : 3.0) * z.V + 2 * I + 4 * Y), st,
                                [&] { return launch_adj_sweep(dg, p.ray2, p.bands2, sa, n, st); }));
                 first = false;
                 std::swap(ypend, ynext);
                 if (it > 0) {
-                    BackArgs b = back_args(z, att, ypend, fbar, n);
+                    BackArgs b = back_args(z, att, ypend, fbar, n, E);
                     b.aux = fdir;
                     BOAC_TRY(run_back(ctx, BACK_ADJ, dg, p, z, b, st));
                 }
@@ -929,9 +943,12 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
             ta.img_cs = 2 * I;
             ta.sino_cs = Y;
             ta.accumulate = first ? 0 : 1;
+            ta.E = E;
+            ta.Ebar = Ebar;
+            ta.e_cs = z.E;
             BOAC_TRY(timed(ctx, BOAC_K_ADJ_RAY, 4.0 * n * (3.0 * z.V + 2 * I + Y), st,
                            [&] { return launch_tail(dg, p.ray2, p.bands2, ta, n, st); }));
-            BackArgs b = back_args(z, att, attbar, mubar, n);
+            BackArgs b = back_args(z, att, attbar, mubar, n, Ebar);
             BOAC_TRY(run_back(ctx, BACK_FIELD, dg, p, z, b, st));
             BOAC_TRY(timed(ctx, BOAC_K_ADJ_PIX, 4.0 * n * I, st,
                            [&] { return launch_raster_adj(dg, cd, n, delta_r, mubar, I, gtmp, st); }));

@@ -229,6 +229,32 @@ def test_opposed_ray_pairing_matches_the_full_tensor(ctx, shape, monkeypatch):
     report(f"pairing {shape} J vs oracle", runs["1"][0][1:2], np.array([Jr]), TOL)
 
 
+@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 4), ((64, 64, 64, 64), 3), ((32, 16, 32, 32), 0)])
+def test_opposed_ray_pairing_in_the_gradients(ctx, shape, K, monkeypatch):
+    # the reverse sweeps and the tail carry the opposed ray's adjoint through att' = exp(-T) / att
+    # (att_bar and a per-ray E_bar); the unrolled and envelope gradients equal the full tensor's to
+    # FP32 rounding and the oracle's to the gate
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=33)
+    th = cands(34, 3)
+    th[2] = f32(th[2] + np.array([0.3, 0.2, -0.2, 0.1, 0.1, -0.1, 0.01, -0.02]))
+    runs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BOAC_OPPOSED_RAYS", flag)
+        out = []
+        for mode in ("unrolled", "envelope"):
+            J, G, st = ctx.objective_grad_ex(g, dev(S), dev(th), DR, K, 2, mode=mode)
+            out += [J.cpu().numpy(), G.cpu().numpy()]
+        runs[flag] = out
+    for name, a, b in zip(("J", "dJ", "J env", "dJ env"), runs["1"], runs["0"]):
+        report(f"pairing grad {shape} K={K} {name}", a, b, 2e-5)
+    for c in range(3):
+        _, Gr = oracle.objective_and_grad(og, S, th[c], DR, K, with_delta_r=True)
+        report(f"pairing grad {shape} K={K} cand {c} dJ vs oracle", runs["1"][1][c], Gr, TOL_GRAD)
+        _, Ge = oracle.objective_and_envelope_grad(og, S, th[c], DR, K, with_delta_r=True)
+        report(f"pairing grad {shape} K={K} cand {c} envelope dJ vs oracle", runs["1"][3][c], Ge, TOL_GRAD)
+
+
 def test_count_preservation_on_gpu(ctx, slice128):
     g, og = geom_pair(128, 128, pixel=0.2)
     S = slice128["meas"].astype(np.float64)
