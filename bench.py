@@ -69,7 +69,10 @@ def kernel_name(kind, C):
     except (OSError, ValueError):
         e = None
     if e and len(e) >= 5 and e[4] == 2:
-        return f"k_back_col4<{e[2]}, true> (MLEM gather)"
+        # 128 angles: the attenuation tensor holds half of them (opposed-ray pairing)
+        if os.environ.get("BOAC_OPPOSED_RAYS", "1") != "0":
+            return f"k_back_col4<{e[2]}, true, true> (MLEM gather, opposed-ray pairing)"
+        return f"k_back_col4<{e[2]}, true, false> (MLEM gather)"
     if e and len(e) >= 5 and e[4]:
         return f"k_back_slid<{e[2]}, true> (MLEM gather)"
     if e:
@@ -189,13 +192,23 @@ def bo_line(ctx, g, S, truth):
                      "best_J_per_cycle": [round(float(min(x.J.min() for x in bo.cycles[:k + 1])), 2)
                                           for k in range(len(bo.cycles))], **tm,
                      "ei_queries": int(sum(c.timings.get("ei_queries", 0) for c in bo.cycles))}
-    # the acquisition kernel alone at a larger model: n observations, M queries, FP64
+    out["gp_ei_kernel"] = gp_kernel_line(ctx, S.device)
+    return out
+
+
+def gp_kernel_line(ctx, dev):
+    """The acquisition kernels alone at a larger model: 512 observations, 65536 queries, FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2109_11920_amd.api import gp_fit
+    from paper_2109_11920_amd.bo import LENGTH_GRID
     rng = np.random.default_rng(0)
     n, M = 512, 1 << 16
     U = rng.uniform(size=(n, 8))
     y = 1e5 + 300 * np.sum((U - 0.4) ** 2, axis=1)
     model = gp_fit(U, y, LENGTH_GRID)
-    q = torch.as_tensor(rng.uniform(size=(M, 8)), device=S.device)
+    q = torch.as_tensor(rng.uniform(size=(M, 8)), device=dev)
     ctx.gp_ei(model, q, float(y.min()), 0.0)
     torch.cuda.synchronize()
     ctx.reset_stats()
@@ -208,9 +221,61 @@ def bo_line(ctx, g, S, truth):
     ctx.set_profiling(False)
     ms /= max(cnt, 1)
     flops = M * n * (n + 1 + 3 * 8 + 4)   # triangular product (FMA = 2), distances, mean and norm
-    out["gp_ei_kernel"] = {"n": n, "queries": M, "ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 2),
-                           "bound": "alu", "peak_tflops": 78.6, "frac": round(flops / ms / 1e9 / 78.6, 4),
-                           "what": "k* + blocked triangular product + EI, FP64 (exp not counted)"}
+    return {"n": n, "queries": M, "ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 2),
+            "bound": "alu", "peak_tflops": 78.6, "frac": round(flops / ms / 1e9 / 78.6, 4),
+            "what": "k* + blocked triangular product (FP64 matrix cores) + EI, FP64 (exp not counted)"}
+
+
+def grad_lines(ctx, g, S, dev, steps):
+    """Objective + gradient on the 64-candidate draw (20 iterations, checkpoint every 5): the unrolled
+    gradient against the forward evaluation, and the envelope gradient with dJ/d(dR)."""
+    import numpy as np
+    import torch
+
+    import synth
+    stream = torch.cuda.current_stream(dev)
+    # ---- objective + gradient: 64 candidates, 20 iterations, checkpoint every 5
+    wg = synth.workload("grad64_n128")
+    cg = torch.as_tensor(synth.workload_candidates(wg)[0].astype(np.float32), device=dev)
+    Kg = wg.n_iter
+    ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
+    ctx.objective(g, S, cg, DELTA_R, Kg)
+    torch.cuda.synchronize()
+    reps = max(2, steps // 2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        _, G, st = ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
+    e1.record(stream)
+    for _ in range(reps):
+        ctx.objective(g, S, cg, DELTA_R, Kg)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(G).all())
+    grad_ms = e0.elapsed_time(e1) / reps
+    fwd_ms = e1.elapsed_time(e2) / reps
+    out = {}
+    out["grad"] = {"value": round(cg.shape[0] / (grad_ms / 1e3), 1), "unit": "obj+grad evals/s",
+                   "ms_per_batch": round(grad_ms, 3), "forward_ms_per_batch": round(fwd_ms, 3),
+                   "grad_over_forward": round(grad_ms / fwd_ms, 3),
+                   "what": "64 candidates, 20 iterations, checkpoint every 5"}
+
+    # ---- envelope gradient (reconstruction held fixed) with dJ/d(dR), same 64 candidates
+    ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        _, Ge, _ = ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Ge).all())
+    env_ms = e0.elapsed_time(e1) / reps
+    out["grad_envelope"] = {"value": round(cg.shape[0] / (env_ms / 1e3), 1), "unit": "obj+grad evals/s",
+                            "ms_per_batch": round(env_ms, 3), "grad_over_forward": round(env_ms / fwd_ms, 3),
+                            "what": "64 candidates, 20 iterations, envelope gradient (F^K held fixed) "
+                                    "with dJ/d(dR)"}
     return out
 
 
@@ -224,6 +289,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the 48-slice uneven batch line")
     ap.add_argument("--only-main", action="store_true", help="timed batch only (for profiler runs)")
     ap.add_argument("--no-bo", action="store_true", help="skip the BOAC outer-loop line")
+    ap.add_argument("--only-grad", action="store_true", help="the gradient lines only (for profiler runs)")
+    ap.add_argument("--only-gp", action="store_true", help="the acquisition-kernel line only (for profiler runs)")
     ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
@@ -252,8 +319,15 @@ def main():
     C, K = cand.shape[0], w.n_iter
     ctx = Context(0)
     stream = torch.cuda.current_stream(dev)
-    if args.only_uneven:
-        print(json.dumps({"uneven48": uneven_line(ctx, dev)}), flush=True)
+    if args.only_uneven or args.only_gp or args.only_grad:
+        out = {}
+        if args.only_uneven:
+            out["uneven48"] = uneven_line(ctx, dev)
+        if args.only_grad:
+            out.update(grad_lines(ctx, g, S, dev, args.steps))
+        if args.only_gp:
+            out["gp_ei_kernel"] = gp_kernel_line(ctx, dev)
+        print(json.dumps(out), flush=True)
         ctx.close()
         return
     if args.copy_calib:
@@ -346,47 +420,7 @@ def main():
                         "what": f"{n_plain} candidates, one call each (C=1), {K} iterations + objective"}
         out["batched_over_plain"] = round(value / plain_rate, 2)
 
-        # ---- objective + gradient: 64 candidates, 20 iterations, checkpoint every 5
-        wg = synth.workload("grad64_n128")
-        cg = torch.as_tensor(synth.workload_candidates(wg)[0].astype(np.float32), device=dev)
-        Kg = wg.n_iter
-        ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
-        ctx.objective(g, S, cg, DELTA_R, Kg)
-        torch.cuda.synchronize()
-        reps = max(2, args.steps // 2)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            _, G, st = ctx.objective_grad(g, S, cg, DELTA_R, Kg, wg.ckpt_every)
-        e1.record(stream)
-        for _ in range(reps):
-            ctx.objective(g, S, cg, DELTA_R, Kg)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        assert bool(torch.isfinite(G).all())
-        grad_ms = e0.elapsed_time(e1) / reps
-        fwd_ms = e1.elapsed_time(e2) / reps
-        out["grad"] = {"value": round(cg.shape[0] / (grad_ms / 1e3), 1), "unit": "obj+grad evals/s",
-                       "ms_per_batch": round(grad_ms, 3), "forward_ms_per_batch": round(fwd_ms, 3),
-                       "grad_over_forward": round(grad_ms / fwd_ms, 3),
-                       "what": "64 candidates, 20 iterations, checkpoint every 5"}
-
-        # ---- envelope gradient (reconstruction held fixed) with dJ/d(dR), same 64 candidates
-        ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(reps):
-            _, Ge, _ = ctx.objective_grad_ex(g, S, cg, DELTA_R, Kg, wg.ckpt_every, mode="envelope")
-        e1.record(stream)
-        torch.cuda.synchronize()
-        assert bool(torch.isfinite(Ge).all())
-        env_ms = e0.elapsed_time(e1) / reps
-        out["grad_envelope"] = {"value": round(cg.shape[0] / (env_ms / 1e3), 1), "unit": "obj+grad evals/s",
-                                "ms_per_batch": round(env_ms, 3), "grad_over_forward": round(env_ms / fwd_ms, 3),
-                                "what": "64 candidates, 20 iterations, envelope gradient (F^K held fixed) "
-                                        "with dJ/d(dR)"}
+        out.update(grad_lines(ctx, g, S, dev, args.steps))
 
     if not args.only_main:
         out["paper72"] = paper72_line(ctx, dev)
