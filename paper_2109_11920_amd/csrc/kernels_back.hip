@@ -634,11 +634,13 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
         blk[q] = 0.f;
     }
 
+    // PAIRED: the initial staging values are 1 (a reciprocal is taken of them; never gathered with a
+    // nonzero weight, as in the unpaired case where they are 0)
     float4 pre[CG];
     float zv[CG], ev[CG], zo[CG];  // ray weight; with PAIRED exp(-T) and the opposed ray's weight
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
-        pre[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        pre[q] = PAIRED ? make_float4(1.f, 1.f, 1.f, 1.f) : make_float4(0.f, 0.f, 0.f, 0.f);
         zv[q] = 1.f;
         ev[q] = 0.f;
         zo[q] = 1.f;
@@ -676,20 +678,27 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
 
     for (int a = 0; a < g.nah; ++a) {
         __syncthreads();  // previous gather done with the LDS
+        // PAIRED: the opposed ray's factor exp(-T) z' of this thread's bin, once per angle
+        float ez[CG];
+#pragma unroll
+        for (int q = 0; q < CG; ++q) ez[q] = WEIGHTED ? ev[q] * zo[q] : ev[q];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             float v[CG];
 #pragma unroll
             for (int q = 0; q < CG; ++q) {
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
-                v[q] = WEIGHTED ? x * zv[q] : x;
                 if constexpr (PAIRED) {
                     if (mode == BACK_FIELD) {
                         v[q] = x + ev[q];  // m_bar plus the ray's dx Tbar
                     } else {
-                        const float xo = x > 1e-30f ? ev[q] * __builtin_amdgcn_rcpf(x) : 0.f;
-                        v[q] = WEIGHTED ? fmaf(xo, zo[q], v[q]) : v[q] + xo;
+                        // att z + (exp(-T) / att) z'; an underflowed att is clamped (its opposed value is 0
+                        // then, as exp(-T) has underflowed too)
+                        const float ri = __builtin_amdgcn_rcpf(fmaxf(x, 1e-30f));
+                        v[q] = fmaf(ri, ez[q], WEIGHTED ? x * zv[q] : x);
                     }
+                } else {
+                    v[q] = WEIGHTED ? x * zv[q] : x;
                 }
             }
             float *d = lds + ((4 * kb + t) * PL + bb) * V;

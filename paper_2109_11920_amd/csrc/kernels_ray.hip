@@ -188,11 +188,10 @@ __device__ __forceinline__ void fwd_emit(const FwdArgs &A, size_t cand, int ray,
     }
 }
 
-// Attenuation of the opposed ray's sample from the held one: exp(-T) / att (0 where att has
-// underflowed or is a padding row).
-__device__ __forceinline__ float opposed_att(float e_ray, float at) {
-    return at > 1e-30f ? e_ray * __builtin_amdgcn_rcpf(at) : 0.f;
-}
+// 1 / att for the opposed ray's attenuation exp(-T) / att; an underflowed att is clamped (exp(-T)
+// has underflowed too, so the opposed value is 0).
+__device__ __forceinline__ float inv_att(float at) { return __builtin_amdgcn_rcpf(fmaxf(at, 1e-30f)); }
+__device__ __forceinline__ float opposed_att(float e_ray, float at) { return e_ray * inv_att(at); }
 
 // PAIRED (opposed-ray pairing, single stage only): each thread's ray (a, b), a < na/2, also gives the
 // projection of ray (a + na/2, nb-1-b) from the same samples and bilinear values.
@@ -548,7 +547,7 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                             part = fmaf(a0, w.x, part);
                             const float cv = fmaf(rr, w.x, yp * w.y);
                             if constexpr (PAIRED) {
-                                const float ri = a0 > 1e-30f ? __builtin_amdgcn_rcpf(a0) : 0.f;
+                                const float ri = inv_att(a0);
                                 const float ao = e_ray * ri;
                                 const float cv2 = fmaf(rr2, w.x, yp2 * w.y);
                                 part2 = fmaf(ao, w.x, part2);
@@ -728,7 +727,7 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                             const float a0 = f4at(at[q >> 2], q & 3);
                             float abar;
                             if constexpr (PAIRED) {
-                                const float ri = a0 > 1e-30f ? __builtin_amdgcn_rcpf(a0) : 0.f;
+                                const float ri = inv_att(a0);
                                 const float ao = e_ray * ri;
                                 const float cv2 = g.dx * fmaf(rho2, w.y, w.x);
                                 epart = fmaf(cv2, ri, epart);
