@@ -152,6 +152,7 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
                     buffer_st4(rs, roff + 4u * att_row(g, 4 * kg), 0u, make_float4(e[0], e[1], e[2], e[3]));
                 }
             }
+            if (E) E[cand * e_cs + ray] = expf(-g.dx * comp_value(T));  // opposed-ray pairing
         }
     }
 }
@@ -197,7 +198,6 @@ __device__ __forceinline__ float opposed_att(float e_ray, float at) { return e_r
 // projection of ray (a + na/2, nb-1-b) from the same samples and bilinear values.
 template <int MODE, bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
-    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     __shared__ float red[32];  // two floats per wave, up to 16 waves
     int cand, chunk;
@@ -281,6 +281,8 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                Comp c2 = acc2[j];
                 for (int kc = kstart; kc <= k1; kc += kBandChunk) {
                     float4 av[kBandChunk / 4];
 #pragma unroll
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                         const int k = kc + 4 * q;
                         av[q] = (k <= k1) ? buffer_ld4(rs, roff + 4u * att_row(g, k), 0u) : z4;
                     }
-                    float part = 0.f;
+                    float part = 0.f, part2 = 0.f;
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
                         const int k = kc + q;
@@ -296,12 +298,18 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                             float U, V;
                             sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
                             const Tap t = make_tap<false>(U, V, nf, pitch, band);
-                            if (t.mine)
-                                part = fmaf(f4at(av[q >> 2], q & 3), lerp2(lds + t.off, pitch, t.fu, t.fv), part);
+                            if (t.mine) {
+                                const float at = f4at(av[q >> 2], q & 3);
+                                const float w = lerp2(lds + t.off, pitch, t.fu, t.fv);
+                                part = fmaf(at, w, part);
+                                if constexpr (PAIRED) part2 = fmaf(opposed_att(e_ray, at), w, part2);
+                            }
                         }
                     }
                     kahan_add(c, part);
+                    if constexpr (PAIRED) kahan_add(c2, part2);
                 }
+                acc2[j] = c2;
             }
             acc[j] = c;
         }
@@ -463,7 +471,6 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
 // held tensors through att' = E / att: att_bar += -att' c' / att, E_bar += c' / att.
 template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
-    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
@@ -475,9 +482,9 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
     const float *img = A.pair + cand * A.img_cs;
     const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
 
-    Comp acc[kMaxRpt], acc2[kMaxRpt];
+    Comp acc[kMaxRpt], acc2[kMaxRpt], ebj[kMaxRpt];  // PAIRED: r_bar of the opposed ray, its E_bar part
 #pragma unroll
-    for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = Comp{0.f, 0.f};
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = ebj[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                 const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
                 const float rr2 = PAIRED ? g.dx * A.r[si2] : 0.f;
                 const float yp2 = PAIRED ? g.dx * A.ybar_in[si2] : 0.f;
-                Comp c2 = acc2[j], eb{0.f, 0.f};
+                Comp c2 = acc2[j], eb = ebj[j];
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
@@ -574,8 +581,7 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                 }
                 if constexpr (PAIRED) {
                     acc2[j] = c2;
-                    float *eo = A.Ebar + cand * A.e_cs + ray;
-                    *eo = (A.accumulate ? *eo : 0.f) + comp_value(eb);
+                    ebj[j] = eb;
                 }
             } else {
                 // the ray's samples in this band, 16 at a time (loads of att, and of att_bar when
@@ -590,6 +596,11 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                 const unsigned roff = 4u * (unsigned)col0;
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                const size_t si2 = cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b));
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                const float rr2 = PAIRED ? g.dx * A.r[si2] : 0.f;
+                const float yp2 = PAIRED ? g.dx * A.ybar_in[si2] : 0.f;
+                Comp c2 = acc2[j], eb = ebj[j];
                 for (int kc = kstart; kc <= k1; kc += kBandChunk) {
                     float4 av[kBandChunk / 4], bv[kBandChunk / 4];
 #pragma unroll
@@ -599,7 +610,7 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                         av[q] = (k <= k1) ? buffer_ld4(ra, o, 0u) : z4;
                         bv[q] = (k <= k1) ? buffer_ld4(rb, o, 0u) : z4;
                     }
-                    float part = 0.f;
+                    float part = 0.f, part2 = 0.f, epart = 0.f;
                     float ov[4];
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
@@ -611,15 +622,33 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                             const Tap t = make_tap<false>(U, V, nf, pitch, band);
                             if (t.mine) {
                                 const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                                part = fmaf(f4at(av[q >> 2], q & 3), w.x, part);
-                                ov[q & 3] = (A.accumulate ? ov[q & 3] : 0.f) + fmaf(rr, w.x, yp * w.y);
+                                const float a0 = f4at(av[q >> 2], q & 3);
+                                part = fmaf(a0, w.x, part);
+                                const float cv = fmaf(rr, w.x, yp * w.y);
+                                const float base = A.accumulate ? ov[q & 3] : 0.f;
+                                if constexpr (PAIRED) {
+                                    const float ri = inv_att(a0);
+                                    const float ao = e_ray * ri;
+                                    const float cv2 = fmaf(rr2, w.x, yp2 * w.y);
+                                    part2 = fmaf(ao, w.x, part2);
+                                    epart = fmaf(cv2, ri, epart);
+                                    ov[q & 3] = base + fmaf(-ao * ri, cv2, cv);
+                                } else {
+                                    ov[q & 3] = base + cv;
+                                }
                             }
                         }
                         if ((q & 3) == 3 && k - 3 <= k1)
                             buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     kahan_add(c, part);
+                    if constexpr (PAIRED) {
+                        kahan_add(c2, part2);
+                        kahan_add(eb, epart);
+                    }
                 }
+                acc2[j] = c2;
+                ebj[j] = eb;
             }
             acc[j] = c;
         }
@@ -639,6 +668,8 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
             const float rbar2 = g.dx * comp_value(acc2[j]);
             const float yn2 = A.y[si2];
             A.ybar_out[si2] = (yn2 > 0.f) ? -(rbar2 * A.r[si2]) / yn2 : 0.f;
+            float *eo = A.Ebar + cand * A.e_cs + ray;
+            *eo = (A.accumulate ? *eo : 0.f) + comp_value(ebj[j]);
         }
     }
 }
@@ -654,7 +685,6 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
 // field gather adds it).
 template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
-    static_assert(SINGLE || !PAIRED, "opposed-ray pairing needs the single-stage image");
     extern __shared__ float lds[];
     int cand, chunk;
     ray_block(chunks, C, cand, chunk);
@@ -665,6 +695,9 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
     float *ab = A.attbar + cand * A.att_cs;
     const float *img = A.pair + cand * A.img_cs;
     const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
+    Comp ebj[kMaxRpt];  // PAIRED, row bands: the opposed ray's E_bar part, summed over the bands
+#pragma unroll
+    for (int j = 0; j < kMaxRpt; ++j) ebj[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
@@ -761,18 +794,26 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                 // another band are written back as loaded, as in the sweep)
                 int k0, k1;
                 band_k_range(g, band, Vb, cs.x, k0, k1);
+                const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(att, (unsigned)(4 * A.att_cs));
                 const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(ab, (unsigned)(4 * A.att_cs));
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
+                const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
+                const float rho2 =
+                    PAIRED ? A.rho[cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b))] : 0.f;
+                Comp eb = ebj[j];
                 for (int kc = kstart; kc <= k1; kc += kBandChunk) {
-                    float4 bv[kBandChunk / 4];
+                    float4 av[kBandChunk / 4], bv[kBandChunk / 4];
 #pragma unroll
                     for (int q = 0; q < kBandChunk / 4; ++q) {
                         const int k = kc + 4 * q;
-                        bv[q] = (k <= k1) ? buffer_ld4(rb, roff + 4u * att_row(g, k), 0u) : z4;
+                        const unsigned o = roff + 4u * att_row(g, k);
+                        bv[q] = (k <= k1) ? buffer_ld4(rb, o, 0u) : z4;
+                        av[q] = (PAIRED && k <= k1) ? buffer_ld4(ra, o, 0u) : z4;
                     }
                     float ov[4];
+                    float epart = 0.f;
 #pragma unroll
                     for (int q = 0; q < kBandChunk; ++q) {
                         const int k = kc + q;
@@ -783,13 +824,25 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                             const Tap t = make_tap<false>(U, V, nf, pitch, band);
                             if (t.mine) {
                                 const float2 w = lerp2x2(lds2 + t.off, pitch, t.fu, t.fv);
-                                ov[q & 3] = (A.accumulate ? ov[q & 3] : 0.f) + g.dx * fmaf(rho, w.y, w.x);
+                                const float base = A.accumulate ? ov[q & 3] : 0.f;
+                                const float cv = g.dx * fmaf(rho, w.y, w.x);
+                                if constexpr (PAIRED) {
+                                    const float ri = inv_att(f4at(av[q >> 2], q & 3));
+                                    const float ao = e_ray * ri;
+                                    const float cv2 = g.dx * fmaf(rho2, w.y, w.x);
+                                    epart = fmaf(cv2, ri, epart);
+                                    ov[q & 3] = base + fmaf(-ao * ri, cv2, cv);
+                                } else {
+                                    ov[q & 3] = base + cv;
+                                }
                             }
                         }
                         if ((q & 3) == 3 && k - 3 <= k1)
                             buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
+                    if constexpr (PAIRED) kahan_add(eb, epart);
                 }
+                ebj[j] = eb;
             }
         }
     }
@@ -831,6 +884,11 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                         buffer_st4(rb, roff + 4u * att_row(g, k - 3), 0u, make_float4(ov[0], ov[1], ov[2], ov[3]));
                 }
             }
+            if constexpr (PAIRED) {
+                float *eo = A.Ebar + cand * A.e_cs + ray;
+                const float etot = (A.accumulate ? *eo : 0.f) + comp_value(ebj[j]);
+                *eo = g.dx * (-A.E[cand * A.e_cs + ray] * etot);
+            }
         }
     }
 }
@@ -843,11 +901,9 @@ hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, co
     if (rc.single)
         hipLaunchKernelGGL(k_att<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
                            mu, att, img_cs, att_cs, E, e_cs);
-    else if (!E)
+    else
         hipLaunchKernelGGL(k_att<false>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks,
                            C, mu, att, img_cs, att_cs, E, e_cs);
-    else
-        return hipErrorInvalidValue;  // opposed-ray pairing needs the single-stage image
     return hipGetLastError();
 }
 
@@ -860,15 +916,15 @@ static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, con
     else if (rc.single)
         hipLaunchKernelGGL((k_fwd<MODE, true, PAIRED>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
                            rc.rpt, rc.chunks, C, a);
-    else if constexpr (!PAIRED)
-        hipLaunchKernelGGL((k_fwd<MODE, false, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
+    else
+        hipLaunchKernelGGL((k_fwd<MODE, false, PAIRED>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands,
                            rc.rpt, rc.chunks, C, a);
 }
 
 hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                       hipStream_t st) {
     const bool paired = a.E != nullptr;
-    if (paired && (!rc.single || g.nah * 2 != g.na)) return hipErrorInvalidValue;
+    if (paired && g.nah * 2 != g.na) return hipErrorInvalidValue;
     switch (mode) {
         case FWD_PROJ: paired ? fwd_mode<FWD_PROJ, true>(g, rc, bands, a, C, st)
                               : fwd_mode<FWD_PROJ, false>(g, rc, bands, a, C, st); break;
@@ -884,10 +940,12 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
                             hipStream_t st) {
     const bool paired = a.E != nullptr;
-    if (paired != (g.nah != g.na) || (paired && (!rc.single || g.nah * 2 != g.na || !a.Ebar)))
-        return hipErrorInvalidValue;
-    if (paired)
+    if (paired != (g.nah != g.na) || (paired && (g.nah * 2 != g.na || !a.Ebar))) return hipErrorInvalidValue;
+    if (paired && rc.single)
         hipLaunchKernelGGL((k_adj_sweep<true, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+    else if (paired)
+        hipLaunchKernelGGL((k_adj_sweep<false, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
                            rc.chunks, C, a);
     else if (rc.single)
         hipLaunchKernelGGL((k_adj_sweep<true, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
@@ -901,10 +959,12 @@ hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &ban
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st) {
     const bool paired = a.E != nullptr;
-    if (paired != (g.nah != g.na) || (paired && (!rc.single || g.nah * 2 != g.na || !a.Ebar)))
-        return hipErrorInvalidValue;
-    if (paired)
+    if (paired != (g.nah != g.na) || (paired && (g.nah * 2 != g.na || !a.Ebar))) return hipErrorInvalidValue;
+    if (paired && rc.single)
         hipLaunchKernelGGL((k_tail<true, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
+                           rc.chunks, C, a);
+    else if (paired)
+        hipLaunchKernelGGL((k_tail<false, true>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,
                            rc.chunks, C, a);
     else if (rc.single)
         hipLaunchKernelGGL((k_tail<true, false>), ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt,

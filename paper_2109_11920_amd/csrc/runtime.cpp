@@ -542,8 +542,8 @@ static Sizes sizes_of(const boac_geom &g, int nah = -1) {
 }
 
 // Opposed-ray pairing (the attenuation tensor for half the angles plus exp(-T) per ray, both rays of a
-// line from one pass) applies to an even angle count with single-stage ray kernels and the
-// column-group gather; BOAC_OPPOSED_RAYS=0 turns it off.
+// line from one pass) applies to an even angle count with the column-group gather;
+// BOAC_OPPOSED_RAYS=0 turns it off.
 static bool pairing_enabled() {
     const char *e = std::getenv("BOAC_OPPOSED_RAYS");
     return !(e && e[0] == '0');
@@ -551,20 +551,17 @@ static bool pairing_enabled() {
 
 // Launch geometry, plan and sizes of one slice for the attenuation-weighted paths (projection,
 // backprojection, MLEM, objective); with allow_pairing, opposed-ray pairing where it applies.
-// pair_stage: the caller also runs the two-image ray kernels (the gradient's sweeps and tail), which
-// then need a single stage too.
 static boac_status plan_slice(boac_ctx *ctx, const boac_geom &g, int C, bool allow_pairing, DevGeom *dg, Plan *p,
-                              Sizes *z, bool pair_stage = false) {
+                              Sizes *z) {
     BOAC_TRY(dev_geom(ctx, g, dg));
     *z = sizes_of(g);
     BOAC_TRY(make_plan(ctx, g, C, p));
-    if (allow_pairing && pairing_enabled() && g.n_angles % 2 == 0 && p->ray1.single && p->back.slid == 2 &&
-        (!pair_stage || p->ray2.single)) {
+    if (allow_pairing && pairing_enabled() && g.n_angles % 2 == 0 && p->back.slid == 2) {
         const int nah = g.n_angles / 2;
         dg->nah = nah;
         *z = sizes_of(g, nah);
         BOAC_TRY(make_plan(ctx, g, C, p, nah));
-        if (!(p->ray1.single && p->back.slid == 2)) return fail(BOAC_EDEVICE, "internal: paired plan changed family");
+        if (p->back.slid != 2) return fail(BOAC_EDEVICE, "internal: paired plan changed family");
     }
     return BOAC_OK;
 }
@@ -647,7 +644,7 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     DevGeom dg;
     Plan p;
     Sizes z;
-    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z, env_grad != nullptr));
+    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z));
     float *E = nullptr, *Ebar = nullptr;
     if (z.E) BOAC_TRY(ensure_t(ctx, "attE", (size_t)Cc * z.E, &E));
     if (z.E && env_grad) BOAC_TRY(ensure_t(ctx, "attEbar", (size_t)Cc * z.E, &Ebar));
@@ -757,7 +754,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     DevGeom dg;
     Plan p;
     Sizes z;
-    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z, true));
+    BOAC_TRY(plan_slice(ctx, g, Cc, true, &dg, &p, &z));
     float *E = nullptr, *Ebar = nullptr;
     if (z.E) {
         BOAC_TRY(ensure_t(ctx, "attE", (size_t)Cc * z.E, &E));

@@ -200,7 +200,7 @@ def test_objective_paper72_samples(ctx):
             report("paper72 F^K true head", img.cpu().numpy()[0], Fr, TOL)
 
 
-@pytest.mark.parametrize("shape", [(40, 24, 40, 40), (64, 64, 64, 64), (36, 25, 36, 36)])
+@pytest.mark.parametrize("shape", [(40, 24, 40, 40), (64, 64, 64, 64), (36, 25, 36, 36), (200, 16, 200, 200)])
 def test_opposed_ray_pairing_matches_the_full_tensor(ctx, shape, monkeypatch):
     # even angle counts with the column-group gather hold half the angles plus exp(-T) per ray; the
     # result equals the full tensor's to FP32 rounding (odd counts always hold every angle)
@@ -229,11 +229,13 @@ def test_opposed_ray_pairing_matches_the_full_tensor(ctx, shape, monkeypatch):
     report(f"pairing {shape} J vs oracle", runs["1"][0][1:2], np.array([Jr]), TOL)
 
 
-@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 4), ((64, 64, 64, 64), 3), ((32, 16, 32, 32), 0)])
+@pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 4), ((64, 64, 64, 64), 3), ((32, 16, 32, 32), 0),
+                                     ((192, 12, 192, 192), 2), ((256, 8, 256, 256), 1)])
 def test_opposed_ray_pairing_in_the_gradients(ctx, shape, K, monkeypatch):
+    # 192 and 256 pixels: the two-image ray kernels (and at 256 the one-image ones) run in row bands
     # the reverse sweeps and the tail carry the opposed ray's adjoint through att' = exp(-T) / att
     # (att_bar and a per-ray E_bar); the unrolled and envelope gradients equal the full tensor's to
-    # FP32 rounding and the oracle's to the gate
+    # FP32 rounding and the oracle's to the gate.
     g, og = geom_pair(*shape)
     S, _ = make_slice(og, seed=33)
     th = cands(34, 3)
