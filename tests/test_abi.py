@@ -90,3 +90,23 @@ def test_stats_need_a_context(lib):
     assert lib.boac_ctx_set_profiling(None, 1) == 1
     assert lib.boac_ctx_reset_stats(None) == 1
     lib.boac_ctx_destroy(None)  # no-op
+
+
+def test_gp_entry_points_validate_before_the_device(lib):
+    from paper_2109_11920_amd._lib import BoacGpInfo
+    info = BoacGpInfo(4, 8, 0.5, 1.0, 1e-6, 10.0, 2.0, -3.0)
+    args = lambda M, best=1.0, xi=0.0: (None, ctypes.byref(info), ALIGNED, ALIGNED, ALIGNED, ALIGNED, M, best, xi,
+                                        None, None, ALIGNED, None)
+    assert lib.boac_gp_ei(*args(0)) == 1 and b"M" in lib.boac_last_error()
+    assert lib.boac_gp_ei(*args((1 << 20) + 1)) == 1
+    assert lib.boac_gp_ei(*args(16, xi=-1.0)) == 1
+    assert lib.boac_gp_ei(*args(16, best=float("inf"))) == 1
+    bad = BoacGpInfo(4, 8, 0.0, 1.0, 1e-6, 10.0, 2.0, -3.0)
+    assert lib.boac_gp_ei(None, ctypes.byref(bad), ALIGNED, ALIGNED, ALIGNED, ALIGNED, 16, 1.0, 0.0, None, None,
+                          ALIGNED, None) == 1
+    assert lib.boac_gp_ei(None, None, ALIGNED, ALIGNED, ALIGNED, ALIGNED, 16, 1.0, 0.0, None, None, ALIGNED,
+                          None) == 1
+    # valid arguments, no context: refused before any device call
+    assert lib.boac_gp_ei(*args(16)) == 1 and b"context" in lib.boac_last_error()
+    assert lib.boac_gp_fit(None, None, 0, 8, None, 1, 0, 1e-6, None, None, None) == 1
+
