@@ -675,6 +675,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
 
     int4 cur = rects[0];
     prefetch(0, cur);
+    const bool field = (mode == BACK_FIELD);
 
     for (int a = 0; a < g.nah; ++a) {
         __syncthreads();  // previous gather done with the LDS
@@ -689,13 +690,14 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             for (int q = 0; q < CG; ++q) {
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
                 if constexpr (PAIRED) {
-                    if (mode == BACK_FIELD) {
-                        v[q] = x + ev[q];  // m_bar plus the ray's dx Tbar
+                    // att z + (exp(-T) / att) z'; an underflowed att is clamped (its opposed value is 0
+                    // then, as exp(-T) has underflowed too). The field mode (unweighted) stages m_bar plus
+                    // the ray's dx Tbar instead, picked by a select rather than a branch per value.
+                    const float ri = __builtin_amdgcn_rcpf(fmaxf(x, 1e-30f));
+                    if constexpr (WEIGHTED) {
+                        v[q] = fmaf(ri, ez[q], x * zv[q]);
                     } else {
-                        // att z + (exp(-T) / att) z'; an underflowed att is clamped (its opposed value is 0
-                        // then, as exp(-T) has underflowed too)
-                        const float ri = __builtin_amdgcn_rcpf(fmaxf(x, 1e-30f));
-                        v[q] = fmaf(ri, ez[q], WEIGHTED ? x * zv[q] : x);
+                        v[q] = field ? x + ev[q] : fmaf(ri, ez[q], x);
                     }
                 } else {
                     v[q] = WEIGHTED ? x * zv[q] : x;
