@@ -158,17 +158,19 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
 }
 
 // ------------------------------------------------------------------ forward projection
-// The epilogue of one ray: y, or the MLEM ratio, or the NLL term added to nll (zero_proj set where
-// S > 0 meets y <= 0).
+// The epilogue of one ray: y, or the MLEM ratio, or (returned) the NLL term; zero_proj is set where
+// S > 0 meets y <= 0.
 template <int MODE>
-__device__ __forceinline__ void fwd_emit(const FwdArgs &A, size_t cand, int ray, float y, Comp &nll, bool &zero_proj) {
+__device__ __forceinline__ float fwd_emit(const FwdArgs &A, size_t cand, int ray, float y, bool &zero_proj) {
     const size_t si = cand * A.sino_cs + ray;
     if constexpr (MODE == FWD_PROJ) {
         A.y_out[si] = y;
+        return 0.f;
     } else if constexpr (MODE == FWD_RATIO) {
         const float S = A.meas[ray];
         A.r_out[si] = (y > 0.f) ? S / y : 0.f;
         if (A.y_out) A.y_out[si] = y;
+        return 0.f;
     } else {  // FWD_NLL
         const float S = A.meas[ray];
         if (A.y_out) A.y_out[si] = y;
@@ -185,7 +187,7 @@ __device__ __forceinline__ void fwd_emit(const FwdArgs &A, size_t cand, int ray,
         } else {
             term = y;
         }
-        comp_add(nll, term);
+        return term;
     }
 }
 
@@ -208,9 +210,11 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
     const float *att = A.att + cand * A.att_cs;
     const float *img = A.img + cand * A.img_cs;
 
-    Comp acc[kMaxRpt], acc2[kMaxRpt];
+    Comp acc[kMaxRpt], acc2[PAIRED ? kMaxRpt : 1];
 #pragma unroll
-    for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = Comp{0.f, 0.f};
+    for (int j = 0; j < kMaxRpt; ++j) acc[j] = Comp{0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < (PAIRED ? kMaxRpt : 1); ++j) acc2[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
         const Band band = bands.b[bi];
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                 const unsigned roff = 4u * (unsigned)att_base(g, a, b);
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
-                Comp c2 = acc2[j];
+                Comp c2 = PAIRED ? acc2[j] : Comp{0.f, 0.f};
                 float4 cur[KG], nxt[KG];
 #pragma unroll
                 for (int q = 0; q < KG; ++q) cur[q] = (4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, 4 * q)) : z4;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
 #pragma unroll
                     for (int q = 0; q < KG; ++q) cur[q] = nxt[q];
                 }
-                acc2[j] = c2;
+                if constexpr (PAIRED) acc2[j] = c2;
             } else {
                 // the ray's samples in this band, 16 at a time from the 4-aligned group holding the
                 // first: the chunk's att loads (4 samples per 16-byte load) are issued together, then
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                 const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 const int kstart = (k0 <= k1) ? (k0 & ~3) : k1 + 1;
                 const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
-                Comp c2 = acc2[j];
+                Comp c2 = PAIRED ? acc2[j] : Comp{0.f, 0.f};
                 for (int kc = kstart; kc <= k1; kc += kBandChunk) {
                     float4 av[kBandChunk / 4];
 #pragma unroll
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
                     kahan_add(c, part);
                     if constexpr (PAIRED) kahan_add(c2, part2);
                 }
-                acc2[j] = c2;
+                if constexpr (PAIRED) acc2[j] = c2;
             }
             acc[j] = c;
         }
@@ -323,10 +327,13 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
         if (j >= rpt) break;
         const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
         if (ray >= nrays) continue;
-        fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(acc[j]), nll, zero_proj);
+        const float t0 = fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(acc[j]), zero_proj);
+        if constexpr (MODE == FWD_NLL) comp_add(nll, t0);
         if constexpr (PAIRED) {
             const int a = ray / g.nb, b = ray - a * g.nb;
-            fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(acc2[j]), nll, zero_proj);
+            const float t1 =
+                fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(acc2[j]), zero_proj);
+            if constexpr (MODE == FWD_NLL) comp_add(nll, t1);
         }
     }
     if constexpr (MODE == FWD_NLL) {
@@ -443,11 +450,13 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
             if (j >= rpt) break;
             const int ray = (chunk * rpt + j) * blockDim.x + threadIdx.x;
             if (ray >= nrays || !live) continue;
-            fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(h ? acc1[j] : acc0[j]), nll, zero_proj);
+            const float t0 = fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(h ? acc1[j] : acc0[j]), zero_proj);
+            if constexpr (MODE == FWD_NLL) comp_add(nll, t0);
             if constexpr (PAIRED) {
                 const int a = ray / g.nb, b = ray - a * g.nb;
-                fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(h ? opp1[j] : opp0[j]),
-                               nll, zero_proj);
+                const float t1 = fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b),
+                                                g.dx * comp_value(h ? opp1[j] : opp0[j]), zero_proj);
+                if constexpr (MODE == FWD_NLL) comp_add(nll, t1);
             }
         }
         if constexpr (MODE == FWD_NLL) {
@@ -647,8 +656,10 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
                         kahan_add(eb, epart);
                     }
                 }
-                acc2[j] = c2;
-                ebj[j] = eb;
+                if constexpr (PAIRED) {
+                    acc2[j] = c2;
+                    ebj[j] = eb;
+                }
             }
             acc[j] = c;
         }
@@ -842,7 +853,7 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
                     }
                     if constexpr (PAIRED) kahan_add(eb, epart);
                 }
-                ebj[j] = eb;
+                if constexpr (PAIRED) ebj[j] = eb;
             }
         }
     }
