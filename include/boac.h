@@ -39,8 +39,8 @@
  *     reverse order, and under the half-self rule their attenuations multiply to exp(-T), T the ray's
  *     total. Where the backprojection runs on its column-group kernel, the library then stores the
  *     attenuation of the first n_angles/2 angles plus exp(-T) per ray and derives the rest ("opposed-
- *     ray pairing"). Results equal those of holding every angle up to FP32 rounding. An attenuation
- *     below 1e-30 (path lengths beyond ~69 optical depths) is treated as 0. Setting the environment
+ *     ray pairing"). Results equal those of holding every angle up to FP32 rounding for optical path
+ *     lengths below ~87 (attenuations above the smallest normal float). Setting the environment
  *     variable BOAC_OPPOSED_RAYS=0 holds every angle.
  */
 #ifndef BOAC_H

@@ -14,6 +14,9 @@
 namespace boac {
 
 constexpr int kWave = 64;
+// Smallest normal float: an attenuation is clamped to it before its reciprocal is taken (opposed-ray
+// pairing), exact for every path length below ~87 optical depths.
+constexpr float kMinNormal = 1.17549435e-38f;
 
 struct DevGeom {
     int n, na, nb, nt;

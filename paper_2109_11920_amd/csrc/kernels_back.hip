@@ -690,10 +690,10 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             for (int q = 0; q < CG; ++q) {
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
                 if constexpr (PAIRED) {
-                    // att z + (exp(-T) / att) z'; an underflowed att is clamped (its opposed value is 0
-                    // then, as exp(-T) has underflowed too). The field mode (unweighted) stages m_bar plus
+                    // att z + (exp(-T) / att) z'; an att below the smallest normal float is clamped
+                    // (exact for path lengths below ~87 optical depths). The field mode (unweighted) stages m_bar plus
                     // the ray's dx Tbar instead, picked by a select rather than a branch per value.
-                    const float ri = __builtin_amdgcn_rcpf(fmaxf(x, 1e-30f));
+                    const float ri = __builtin_amdgcn_rcpf(fmaxf(x, kMinNormal));
                     if constexpr (WEIGHTED) {
                         v[q] = fmaf(ri, ez[q], x * zv[q]);
                     } else {
