@@ -257,6 +257,29 @@ def test_opposed_ray_pairing_in_the_gradients(ctx, shape, K, monkeypatch):
         report(f"pairing grad {shape} K={K} cand {c} envelope dJ vs oracle", runs["1"][3][c], Ge, TOL_GRAD)
 
 
+def test_opposed_ray_pairing_under_heavy_attenuation(ctx, monkeypatch):
+    # mu up to 2/cm over a 25.6 cm field: ray totals T near 40, opposed attenuations exp(-T) / att far
+    # below 1e-10; paired and full tensors still agree, and both match the oracle
+    g, og = geom_pair(48, 32)
+    S, _ = make_slice(og, seed=35)
+    th = cands(36, 3)
+    th[1, 6:] = (1.5, 2.0)
+    th[2, 6:] = (0.8, 1.2)
+    th = f32(th)
+    runs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BOAC_OPPOSED_RAYS", flag)
+        J, G, st = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 3, 2, mode="unrolled")
+        runs[flag] = (J.cpu().numpy(), G.cpu().numpy(), st.cpu().numpy())
+    assert np.all(np.isfinite(runs["1"][0])) and np.all(np.isfinite(runs["1"][1]))
+    report("heavy attenuation J paired vs full", runs["1"][0], runs["0"][0], 1e-6)
+    report("heavy attenuation dJ paired vs full", runs["1"][1], runs["0"][1], 1e-5)
+    for c in (1, 2):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 3, with_delta_r=True)
+        report(f"heavy attenuation cand {c} J", runs["1"][0][c:c + 1], np.array([Jr]), TOL)
+        report(f"heavy attenuation cand {c} dJ", runs["1"][1][c], Gr, TOL_GRAD)
+
+
 def test_count_preservation_on_gpu(ctx, slice128):
     g, og = geom_pair(128, 128, pixel=0.2)
     S = slice128["meas"].astype(np.float64)
