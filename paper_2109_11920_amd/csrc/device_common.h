@@ -18,6 +18,14 @@ constexpr int kWave = 64;
 // pairing), exact for every path length below ~87 optical depths.
 constexpr float kMinNormal = 1.17549435e-38f;
 
+// Reciprocal of max(x, kMinNormal). The max is taken on the bit patterns as signed integers, which order
+// non-negative floats as the floats do and put every negative float below kMinNormal (same result as
+// fmaxf for every non-NaN x); one integer max instead of a float max plus the NaN-quieting
+// canonicalisation the compiler adds to a float max of loaded values.
+__device__ __forceinline__ float rcp_clamped(float x) {
+    return __builtin_amdgcn_rcpf(__int_as_float(max(__float_as_int(x), __float_as_int(kMinNormal))));
+}
+
 struct DevGeom {
     int n, na, nb, nt;
     // angles the attenuation tensor holds: na, or na / 2 with opposed-ray pairing (na even): ray

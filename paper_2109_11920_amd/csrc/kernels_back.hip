@@ -693,7 +693,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                     // att z + (exp(-T) / att) z'; an att below the smallest normal float is clamped
                     // (exact for path lengths below ~87 optical depths). The field mode (unweighted) stages m_bar plus
                     // the ray's dx Tbar instead, picked by a select rather than a branch per value.
-                    const float ri = __builtin_amdgcn_rcpf(fmaxf(x, kMinNormal));
+                    const float ri = rcp_clamped(x);
                     if constexpr (WEIGHTED) {
                         v[q] = fmaf(ri, ez[q], x * zv[q]);
                     } else {

@@ -193,7 +193,7 @@ __device__ __forceinline__ float fwd_emit(const FwdArgs &A, size_t cand, int ray
 
 // 1 / att for the opposed ray's attenuation exp(-T) / att; att is clamped to the smallest normal
 // float (exact for path lengths below ~87 optical depths).
-__device__ __forceinline__ float inv_att(float at) { return __builtin_amdgcn_rcpf(fmaxf(at, kMinNormal)); }
+__device__ __forceinline__ float inv_att(float at) { return rcp_clamped(at); }
 __device__ __forceinline__ float opposed_att(float e_ray, float at) { return e_ray * inv_att(at); }
 
 // PAIRED (opposed-ray pairing, single stage only): each thread's ray (a, b), a < na/2, also gives the
