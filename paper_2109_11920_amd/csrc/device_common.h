@@ -22,6 +22,19 @@ constexpr float kMinNormal = 1.17549435e-38f;
 // non-negative floats as the floats do and put every negative float below kMinNormal (same result as
 // fmaxf for every non-NaN x); one integer max instead of a float max plus the NaN-quieting
 // canonicalisation the compiler adds to a float max of loaded values.
+// Element i of a table that no kernel writes while it reads it, loaded through the constant address
+// space: with a uniform i these are scalar loads, whatever else the kernel stores.
+typedef const __attribute__((address_space(4))) int *const_int_ptr;
+typedef const __attribute__((address_space(4))) float *const_float_ptr;
+__device__ __forceinline__ int4 const_ld(const int4 *t, int i) {
+    const const_int_ptr p = (const_int_ptr)(t + i);
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ float2 const_ld(const float2 *t, int i) {
+    const const_float_ptr p = (const_float_ptr)(t + i);
+    return make_float2(p[0], p[1]);
+}
+
 __device__ __forceinline__ float rcp_clamped(float x) {
     return __builtin_amdgcn_rcpf(__int_as_float(max(__float_as_int(x), __float_as_int(kMinNormal))));
 }

@@ -570,6 +570,28 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
 // exp(-T_ab) / att and the same bilinear weights; each staged slot holds both contributions,
 // att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles. In the
 // field mode (mu_bar = W^T m_bar) the slot holds m_bar + dx Tbar_ab, the per-ray value in A.E.
+// CG consecutive floats from LDS into registers, as wide reads where CG allows (p aligned to CG floats
+// for CG <= 4, to 4 floats for CG = 8)
+template <int CG>
+__device__ __forceinline__ void load_cands(const float *p, float (&v)[CG]) {
+    if constexpr (CG % 4 == 0) {
+#pragma unroll
+        for (int h = 0; h < CG / 4; ++h) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[h];
+            v[4 * h] = t.x;
+            v[4 * h + 1] = t.y;
+            v[4 * h + 2] = t.z;
+            v[4 * h + 3] = t.w;
+        }
+    } else if constexpr (CG == 2) {
+        const float2 t = reinterpret_cast<const float2 *>(p)[0];
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
 template <int CG, bool WEIGHTED, bool PAIRED>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
@@ -577,7 +599,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     constexpr int V = SlidLayout<CG>::V;
     constexpr int PLANES = SlidLayout<CG>::PLANES;
     constexpr int PLANE = SlidLayout<CG>::PLANE;
-    extern __shared__ float lds[];  // [PLANES][P rows][PL slots][V]
+    extern __shared__ float lds[];  // [PLANES][P rows][PL slots][V], then the ray weights wz, we
     const int ntiles = T.tiles_x * T.tiles_y;
     const int ngroups = (A.C + CG - 1) / CG;
     const int total = ntiles * ngroups;
@@ -617,14 +639,13 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     const unsigned cand_e = 4u * (unsigned)A.e_cs;
     const __amdgpu_buffer_rsrc_t re =
         buffer_rsrc(PAIRED ? A.E + (size_t)c0 * A.e_cs : src, PAIRED ? (unsigned)ncg * cand_e : 0u);
+    // per-angle block origins and trigonometry, read through the constant address space: the tables
+    // are not written while the kernel runs, so their uniform loads stay scalar whatever the kernel
+    // stores to LDS
     const int4 *rects = T.rects + (size_t)tile * g.nah;
-    unsigned qs[CG], qz[CG], qe[CG];
+    unsigned qs[CG];
 #pragma unroll
-    for (int q = 0; q < CG; ++q) {
-        qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
-        qz[q] = (unsigned)min(q, ncg - 1) * cand_z;
-        qe[q] = (unsigned)min(q, ncg - 1) * cand_e;
-    }
+    for (int q = 0; q < CG; ++q) qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
 
     Comp acc[CG];
     float blk[CG];
@@ -637,16 +658,41 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     // PAIRED: the initial staging values are 1 (a reciprocal is taken of them; never gathered with a
     // nonzero weight, as in the unpaired case where they are 0)
     float4 pre[CG];
-    float zv[CG], ev[CG], zo[CG];  // ray weight; with PAIRED exp(-T) and the opposed ray's weight
 #pragma unroll
-    for (int q = 0; q < CG; ++q) {
+    for (int q = 0; q < CG; ++q)
         pre[q] = PAIRED ? make_float4(1.f, 1.f, 1.f, 1.f) : make_float4(0.f, 0.f, 0.f, 0.f);
-        zv[q] = 1.f;
-        ev[q] = 0.f;
-        zo[q] = 1.f;
-    }
+
+    // Ray weights of the staged angle, [bin][candidate], shared through LDS: wz = z of the ray, we = its
+    // opposed ray's factor exp(-T) z' (PAIRED; exp(-T) alone when unweighted). Thread t < 32 CG loads
+    // those of bin t % 32 and candidate t / 32 for the next angle while the current one is gathered,
+    // and writes them after the gather (the staging, their only reader, is then done); every thread of
+    // a bin reads them back. One load per (bin, candidate) instead of one per staging thread, and no
+    // registers held across the gather.
+    float *wz = lds + PLANES * PLANE;
+    float *we = wz + P * CG;
+    const bool wl = (WEIGHTED || PAIRED) && tid < P * CG;
+    const int wj = tid & (P - 1), wq = min(tid >> 5, CG - 1);
+    const unsigned wcz = (unsigned)min(wq, ncg - 1) * cand_z, wce = (unsigned)min(wq, ncg - 1) * cand_e;
+    float lz = 1.f, le = 0.f, lo = 1.f;
+    auto wload = [&](int a, int4 r) {
+        if (!wl) return;
+        if constexpr (WEIGHTED) lz = buffer_ld(rz, 4u * (unsigned)wj + wcz, 4u * (unsigned)(a * g.nb + r.x));
+        if constexpr (PAIRED) {
+            // exp(-T) of ray (a, bin); the opposed ray (a + na/2, nb-1-bin) takes its weight
+            le = buffer_ld(re, 4u * (unsigned)wj + wce, 4u * (unsigned)(a * g.nb + r.x));
+            if constexpr (WEIGHTED)
+                // bin nb-1-(r.x+wj) of angle a + na/2: the per-lane offset stays non-negative since the
+                // block's last bin r.x + 31 is inside the sinogram
+                lo = buffer_ld(rz, wcz + 4u * (unsigned)((a + g.nah) * g.nb + (g.nb - 1 - r.x) - wj), 0u);
+        }
+    };
+    auto wstore = [&]() {
+        if (!wl) return;
+        if constexpr (WEIGHTED) lds[PLANES * PLANE + wj * CG + wq] = lz;
+        if constexpr (PAIRED) lds[PLANES * PLANE + P * CG + wj * CG + wq] = WEIGHTED ? le * lo : le;
+    };
     auto prefetch = [&](int a, int4 r) {
-        const float2 cs = g.trig[a];
+        const float2 cs = const_ld(g.trig, a);
         const float U = fmaf(fkc, -cs.y, fmaf(fbb, cs.x * g.bscale, __int_as_float(r.z)));
         const float V = fmaf(fkc, cs.x, fmaf(fbb, cs.y * g.bscale, __int_as_float(r.w)));
         // a group sample is within 1.5 samples of the group centre; one sample step moves (U, V) by (-s, c)
@@ -655,34 +701,20 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
 #pragma unroll
             for (int q = 0; q < CG; ++q) pre[q] = buffer_ld4(rs, off, (unsigned)a * a_stride + qs[q]);
         }
-        if constexpr (WEIGHTED) {
-            const unsigned zbase = 4u * (unsigned)(a * g.nb + r.x);
-#pragma unroll
-            for (int q = 0; q < CG; ++q) zv[q] = buffer_ld(rz, 4u * (unsigned)bb, zbase + qz[q]);
-        }
-        if constexpr (PAIRED) {
-            // exp(-T) of ray (a, bin); the opposed ray (a + na/2, nb-1-bin) takes its weight
-            const unsigned ebase = 4u * (unsigned)(a * g.nb + r.x);
-#pragma unroll
-            for (int q = 0; q < CG; ++q) ev[q] = buffer_ld(re, 4u * (unsigned)bb, ebase + qe[q]);
-            if constexpr (WEIGHTED) {
-                const unsigned obase = 4u * (unsigned)((a + g.nah) * g.nb + (g.nb - 1 - r.x));
-#pragma unroll
-                for (int q = 0; q < CG; ++q) zo[q] = buffer_ld(rz, obase - 4u * (unsigned)bb, qz[q]);
-            }
-        }
     };
 
-    int4 cur = rects[0];
+    int4 cur = const_ld(rects, 0);
+    wload(0, cur);
     prefetch(0, cur);
     const bool field = (mode == BACK_FIELD);
 
     for (int a = 0; a < g.nah; ++a) {
+        if (a == 0) wstore();  // later angles' weights are stored after the previous gather
         __syncthreads();  // previous gather done with the LDS
-        // PAIRED: the opposed ray's factor exp(-T) z' of this thread's bin, once per angle
-        float ez[CG];
-#pragma unroll
-        for (int q = 0; q < CG; ++q) ez[q] = WEIGHTED ? ev[q] * zo[q] : ev[q];
+        // this thread's bin: z and (PAIRED) the opposed ray's factor exp(-T) z'
+        float zv[CG], ez[CG];
+        if constexpr (WEIGHTED) load_cands<CG>(wz + bb * CG, zv);
+        if constexpr (PAIRED) load_cands<CG>(we + bb * CG, ez);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             float v[CG];
@@ -697,7 +729,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                     if constexpr (WEIGHTED) {
                         v[q] = fmaf(ri, ez[q], x * zv[q]);
                     } else {
-                        v[q] = field ? x + ev[q] : fmaf(ri, ez[q], x);
+                        v[q] = field ? x + ez[q] : fmaf(ri, ez[q], x);
                     }
                 } else {
                     v[q] = WEIGHTED ? x * zv[q] : x;
@@ -718,12 +750,13 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
         __syncthreads();
         const int4 r = cur;
         if (a + 1 < g.nah) {
-            cur = rects[a + 1];
+            cur = const_ld(rects, a + 1);
+            wload(a + 1, cur);
             prefetch(a + 1, cur);
         }
 
         // ---- gather (as in the slot variant)
-        const float2 cs = g.trig[a];
+        const float2 cs = const_ld(g.trig, a);
         const float c = cs.x, s = cs.y;
         const float ub = c * g.bscale, vb = s * g.bscale;
         const float fb1 = (float)(r.x + 1), fk1 = (float)(r.y + 1);
@@ -756,6 +789,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                 }
             }
         }
+        if (a + 1 < g.nah) wstore();  // the weights of angle a + 1, for its staging
         if ((a & 7) == 7 || a == g.nah - 1) {
 #pragma unroll
             for (int q = 0; q < CG; ++q) {

@@ -387,7 +387,8 @@ static void back_fill(const boac_geom &g, BackCfg *bc) {
     bc->wkmax = (int)std::ceil(diag) + 8;
     bc->tiles_x = (g.n + bc->tw - 1) / bc->tw;
     bc->tiles_y = (g.n + bc->th - 1) / bc->th;
-    bc->lds = bc->slid ? (size_t)bc->cg * kSlidBlock * kSlidPitch * sizeof(float)
+    // slid blocks: the staged block, then two [bin][candidate] ray-weight tables
+    bc->lds = bc->slid ? (size_t)bc->cg * (kSlidBlock * kSlidPitch + 2 * kSlidBlock) * sizeof(float)
                        : (size_t)bc->cg * (bc->wbmax * bc->wkmax + bc->wbmax) * sizeof(float);
 }
 
