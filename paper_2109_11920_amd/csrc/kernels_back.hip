@@ -787,6 +787,9 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                         for (int q = 0; q < V; ++q) blk[h * V + q] = fmaf(w, gv.v[q], blk[h * V + q]);
                     }
                 }
+                // keep the next window row's LDS reads after this row's FMAs: 12 registers of taps in
+                // flight instead of 36 (71 VGPRs, one more wave per SIMD)
+                if (db < 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
         if (a + 1 < g.nah) wstore();  // the weights of angle a + 1, for its staging
