@@ -722,10 +722,12 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             for (int q = 0; q < CG; ++q) {
                 const float x = t == 0 ? pre[q].x : t == 1 ? pre[q].y : t == 2 ? pre[q].z : pre[q].w;
                 if constexpr (PAIRED) {
-                    // att z + (exp(-T) / att) z'; an att below the smallest normal float is clamped
-                    // (exact for path lengths below ~87 optical depths). The field mode (unweighted) stages m_bar plus
-                    // the ray's dx Tbar instead, picked by a select rather than a branch per value.
-                    const float ri = rcp_clamped(x);
+                    // att z + (exp(-T) / att) z'. The attenuation build stores att no smaller than the
+                    // smallest normal float (exact for path lengths below ~87 optical depths) and every
+                    // staged group lies inside the sinogram, so the reciprocal needs no clamp here. The
+                    // field mode (unweighted) stages m_bar plus the ray's dx Tbar instead, picked by a
+                    // select rather than a branch per value (its reciprocal is discarded).
+                    const float ri = __builtin_amdgcn_rcpf(x);
                     if constexpr (WEIGHTED) {
                         v[q] = fmaf(ri, ez[q], x * zv[q]);
                     } else {

@@ -2,7 +2,8 @@
 // in LDS (whole image, or row bands for large n).
 //
 //   k_att     attenuation scan, Eq. (1) inner integral: m = W mu, L_k = dx (m_k/2 + sum_{k'>k} m_k'),
-//             att = exp(-L), scanned from the detector end with a compensated running sum.
+//             att = exp(-L), scanned from the detector end with a compensated running sum, stored
+//             no smaller than the smallest normal float (the paired kernels take its reciprocal).
 //   k_fwd     attenuated projection, Eq. (2): y = dx sum_k att (W f), compensated; epilogues give the
 //             MLEM ratio S/y or the Poisson NLL terms of Eq. (5).
 //   k_fwd_pair  the same for two candidates per workgroup, sharing each sample's geometry.
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
                             const Tap t = make_tap<true>(U, V, nf, pitch, band);
                             const float m = lerp2(lds + t.off, pitch, t.fu, t.fv);
                             const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                            e[q] = expf(-L);
+                            e[q] = fmaxf(expf(-L), kMinNormal);
                             comp_add(T, m);
                         }
                     }
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
                         if (k < g.nt) {
                             const float m = f4at(mv[j], q);
                             const float L = g.dx * (fmaf(0.5f, m, T.s) + T.e);
-                            e[q] = expf(-L);
+                            e[q] = fmaxf(expf(-L), kMinNormal);
                             comp_add(T, m);
                         }
                     }
