@@ -30,6 +30,10 @@ __device__ __forceinline__ int4 const_ld(const int4 *t, int i) {
     const const_int_ptr p = (const_int_ptr)(t + i);
     return make_int4(p[0], p[1], p[2], p[3]);
 }
+__device__ __forceinline__ float4 const_ld(const float4 *t, int i) {
+    const const_float_ptr p = (const_float_ptr)(t + i);
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
 __device__ __forceinline__ float2 const_ld(const float2 *t, int i) {
     const const_float_ptr p = (const_float_ptr)(t + i);
     return make_float2(p[0], p[1]);

@@ -620,7 +620,6 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     const bool pv = (l < g.n) && (i < g.n);
     const float xc = (float)l - g.cN, yc = (float)i - g.cN;
     const float cB5 = g.cB + 0.5f, cT5 = g.cT + 0.5f;
-    const float inv_bscale = 1.f / g.bscale;
 
     // open support box of the tile's pixels (half widths around its centre)
     const int l1 = min(l0 + 15, g.n - 1), i1 = min(i0 + 15, g.n - 1);
@@ -643,6 +642,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     // are not written while the kernel runs, so their uniform loads stay scalar whatever the kernel
     // stores to LDS
     const int4 *rects = T.rects + (size_t)tile * g.nah;
+    const float4 *rectf = T.rectf + (size_t)tile * g.nah * 2;  // float forms of the block origins
     unsigned qs[CG];
 #pragma unroll
     for (int q = 0; q < CG; ++q) qs[q] = (unsigned)min(q, ncg - 1) * cand_src;
@@ -692,11 +692,11 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
         if constexpr (PAIRED) lds[PLANES * PLANE + P * CG + wj * CG + wq] = WEIGHTED ? le * lo : le;
     };
     auto prefetch = [&](int a, int4 r) {
-        const float2 cs = const_ld(g.trig, a);
-        const float U = fmaf(fkc, -cs.y, fmaf(fbb, cs.x * g.bscale, __int_as_float(r.z)));
-        const float V = fmaf(fkc, cs.x, fmaf(fbb, cs.y * g.bscale, __int_as_float(r.w)));
+        const float4 t = const_ld(T.angt, 2 * a);  // c, s, c bscale, s bscale
+        const float U = fmaf(fkc, -t.y, fmaf(fbb, t.z, __int_as_float(r.z)));
+        const float V = fmaf(fkc, t.x, fmaf(fbb, t.w, __int_as_float(r.w)));
         // a group sample is within 1.5 samples of the group centre; one sample step moves (U, V) by (-s, c)
-        if (fabsf(U) < fmaf(1.5f, fabsf(cs.y), hu) && fabsf(V) < fmaf(1.5f, fabsf(cs.x), hv)) {
+        if (fabsf(U) < fmaf(1.5f, fabsf(t.y), hu) && fabsf(V) < fmaf(1.5f, fabsf(t.x), hv)) {
             const unsigned off = 4u * (att_row(g, r.y + 4 * kb) + att_col(r.x + bb));
 #pragma unroll
             for (int q = 0; q < CG; ++q) pre[q] = buffer_ld4(rs, off, (unsigned)a * a_stride + qs[q]);
@@ -709,6 +709,9 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     const bool field = (mode == BACK_FIELD);
 
     for (int a = 0; a < g.nah; ++a) {
+        // the gather's per-angle constants, loaded here so the staging hides their latency
+        const float4 t0 = const_ld(T.angt, 2 * a), t1 = const_ld(T.angt, 2 * a + 1);
+        const float4 f0 = const_ld(rectf, 2 * a), f1 = const_ld(rectf, 2 * a + 1);
         if (a == 0) wstore();  // later angles' weights are stored after the previous gather
         __syncthreads();  // previous gather done with the LDS
         // this thread's bin: z and (PAIRED) the opposed ray's factor exp(-T) z'
@@ -750,27 +753,26 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             }
         }
         __syncthreads();
-        const int4 r = cur;
         if (a + 1 < g.nah) {
             cur = const_ld(rects, a + 1);
             wload(a + 1, cur);
             prefetch(a + 1, cur);
         }
 
-        // ---- gather (as in the slot variant)
-        const float2 cs = const_ld(g.trig, a);
-        const float c = cs.x, s = cs.y;
-        const float ub = c * g.bscale, vb = s * g.bscale;
-        const float fb1 = (float)(r.x + 1), fk1 = (float)(r.y + 1);
+        // ---- gather (as in the slot variant); t0 = (c, s, c bscale, s bscale), t1 = (c / bscale,
+        // s / bscale, ..), f0 = (b0 + 1, k0 + 1, b0 + P - 2, k0 + P - 2), f1.x = (k0 + 1) PL + b0 + 1
+        const float c = t0.x, s = t0.y;
+        const float ub = t0.z, vb = t0.w;
         if (pv) {
-            const float Sj5 = fmaf(xc, c * inv_bscale, fmaf(yc, s * inv_bscale, cB5));
+            const float Sj5 = fmaf(xc, t1.x, fmaf(yc, t1.y, cB5));
             const float Tj5 = fmaf(yc, c, fmaf(xc, -s, cT5));
-            const float bcf = __builtin_amdgcn_fmed3f(floorf(Sj5), fb1, fb1 + (float)(P - 3));
-            const float kcf = __builtin_amdgcn_fmed3f(floorf(Tj5), fk1, fk1 + (float)(P - 3));
+            const float bcf = __builtin_amdgcn_fmed3f(floorf(Sj5), f0.x, f0.z);
+            const float kcf = __builtin_amdgcn_fmed3f(floorf(Tj5), f0.y, f0.w);
             const float sig = (bcf - g.cB) * g.bscale, tau = kcf - g.cT;
             const float du0 = fmaf(sig, c, fmaf(tau, -s, -xc));
             const float dv0 = fmaf(sig, s, fmaf(tau, c, -yc));
-            const int corner = (int)(kcf - fk1) * PL + (int)(bcf - fb1);  // window tap (-1, -1)
+            // window tap (-1, -1): (kcf - k0 - 1) PL + bcf - b0 - 1, exact in FP32
+            const int corner = (int)(fmaf(kcf, (float)PL, bcf) - f1.x);
             const float *base = lds + corner * V;
 #pragma unroll
             for (int db = -1; db <= 1; ++db) {

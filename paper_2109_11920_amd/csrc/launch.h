@@ -84,6 +84,10 @@ struct BackCfg {
     int tiles_x, tiles_y; // tiles per image
     size_t lds;
     const int4 *rects;    // [tiles][n_angles] footprint rectangles (b_lo, k_lo, wb, wk)
+    const float4 *rectf;  // slid blocks: [tiles][n_angles][2] block origin as floats, (b0 + 1, k0 + 1,
+                          // b0 + P - 2, k0 + P - 2) and ((k0 + 1) kSlidPitch + b0 + 1, 0, 0, 0)
+    const float4 *angt;   // slid blocks: [n_angles][2] (c, s, c bscale, s bscale), (c / bscale, s / bscale,
+                          // 0, 0), each the FP32 product the kernels would form
     int xcd_remap;        // keep a candidate group's tiles on one XCD
     int slid;             // 16 x 16 tiles, one-bin half window: fixed 32 x 32 staging block slid inside
                           // the sinogram; rects then hold (b0, k0, u0 bits, v0 bits). 1: staging by

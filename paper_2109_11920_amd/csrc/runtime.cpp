@@ -220,9 +220,16 @@ static boac_status host_trig(int na, std::vector<float2> &h) {
 // nah: angles held (the first nah of the n_angles, the table's stride per tile).
 static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc, int nah) {
     std::vector<int> key{g.n, g.n_angles, g.n_bins, g.n_samples, bc->tw, bc->th, bc->hb, bc->slid, nah};
+    const size_t nent = (size_t)bc->tiles_x * bc->tiles_y * nah;
+    // one allocation: the int4 rectangles, then (slid blocks) their float forms and the angle table
+    auto point = [&](int4 *d) {
+        bc->rects = d;
+        bc->rectf = bc->slid ? reinterpret_cast<const float4 *>(d + nent) : nullptr;
+        bc->angt = bc->slid ? bc->rectf + 2 * nent : nullptr;
+    };
     auto it = ctx->rects.find(key);
     if (it != ctx->rects.end()) {
-        bc->rects = it->second;
+        point(it->second);
         return BOAC_OK;
     }
     if (ctx->capturing) return fail(BOAC_EDEVICE, "rectangle table upload during graph capture");
@@ -288,11 +295,34 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc, in
             h[(size_t)t * nah + a] = make_int4(b_lo, k_lo, wb, wk);
         }
     }
+    if (bc->slid) {
+        // float forms of the block origins and per-angle trigonometry for the slid-block gathers, each
+        // value the FP32 operation the kernel would otherwise repeat per angle (same rounding)
+        const float bscale = (float)g.n / (float)g.n_bins;
+        const float inv_bscale = 1.f / bscale;
+        for (size_t e = 0; e < nent; ++e) {
+            const float fb1 = (float)(h[e].x + 1), fk1 = (float)(h[e].y + 1);
+            const float f[8] = {fb1, fk1, fb1 + (float)(kSlidBlock - 3), fk1 + (float)(kSlidBlock - 3),
+                                fk1 * (float)kSlidPitch + fb1, 0.f, 0.f, 0.f};
+            int4 w[2];
+            std::memcpy(w, f, sizeof(f));
+            h.push_back(w[0]);
+            h.push_back(w[1]);
+        }
+        for (int a = 0; a < nah; ++a) {
+            const float c = trig[a].x, s = trig[a].y;
+            const float f[8] = {c, s, c * bscale, s * bscale, c * inv_bscale, s * inv_bscale, 0.f, 0.f};
+            int4 w[2];
+            std::memcpy(w, f, sizeof(f));
+            h.push_back(w[0]);
+            h.push_back(w[1]);
+        }
+    }
     int4 *d = nullptr;
     HIP_TRY(hipMalloc(&d, sizeof(int4) * h.size()));
     HIP_TRY(hipMemcpy(d, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice));
     ctx->rects[key] = d;
-    bc->rects = d;
+    point(d);
     return BOAC_OK;
 }
 
