@@ -556,20 +556,6 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
 }
 
 // ---------------------------------------------------------------------------------------------------
-// Column-group variant of the slid-block gather (n_samples a multiple of 4). The host aligns the
-// block's first sample row to a multiple of 4, so the 4 samples k..k+3 (k = first row + 4 j) of a bin
-// are one aligned 16-byte load in the attenuation layout (sample fastest inside a 4 x 8 block): thread
-// t stages bin t % 32 of rows 4 (t / 32) .. + 3 with one 16-byte load per candidate, a quarter of the
-// vector-memory instructions of the slot variant (which is bound by its vector-memory pipeline), and
-// 8 lanes on consecutive bins read one whole 128-byte line. All 4 samples share the bin's ray weight,
-// folded in while staging as in the slot variant. A group is loaded unless all of it lies outside the
-// union of the tile pixels' supports (tested at its centre with half widths grown by 1.5 samples); a
-// skipped group keeps finite values, gathered only with weight 0.
-// PAIRED (opposed-ray pairing, g.nah = na/2): the slab of angle a < na/2 also stands for angle
-// a + na/2, whose sample (nb-1-b, nt-1-k) sits at sample (b, k) of angle a with attenuation
-// exp(-T_ab) / att and the same bilinear weights; each staged slot holds both contributions,
-// att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles. In the
-// field mode (mu_bar = W^T m_bar) the slot holds m_bar + dx Tbar_ab, the per-ray value in A.E.
 // CG consecutive floats from LDS into registers, as wide reads where CG allows (p aligned to CG floats
 // for CG <= 4, to 4 floats for CG = 8)
 template <int CG>
@@ -592,6 +578,23 @@ __device__ __forceinline__ void load_cands(const float *p, float (&v)[CG]) {
     }
 }
 
+// Column-group variant of the slid-block gather (n_samples a multiple of 4). The host aligns the
+// block's first sample row to a multiple of 4, so the 4 samples k..k+3 (k = first row + 4 j) of a bin
+// are one aligned 16-byte load in the attenuation layout (sample fastest inside a 4 x 8 block): thread
+// t stages bin t % 32 of rows 4 (t / 32) .. + 3 with one 16-byte load per candidate, a quarter of the
+// vector-memory instructions of the slot variant (which is bound by its vector-memory pipeline), and
+// 8 lanes on consecutive bins read one whole 128-byte line. All 4 samples share the bin's ray weight,
+// folded in while staging as in the slot variant. A group is loaded unless all of it lies outside the
+// union of the tile pixels' supports (tested at its centre with half widths grown by 1.5 samples); a
+// skipped group keeps finite values, gathered only with weight 0.
+// PAIRED (opposed-ray pairing, g.nah = na/2): the slab of angle a < na/2 also stands for angle
+// a + na/2, whose sample (nb-1-b, nt-1-k) sits at sample (b, k) of angle a with attenuation
+// exp(-T_ab) / att and the same bilinear weights; each staged slot holds both contributions,
+// att z_ab + (exp(-T_ab) / att) z_(a+na/2, nb-1-b), so one gather serves the two angles. In the
+// field mode (mu_bar = W^T m_bar) the slot holds m_bar + dx Tbar_ab, the per-ray value in A.E.
+// The ray weights reach the staging threads through a small LDS table (one load per bin and
+// candidate, one angle ahead), and the per-angle trigonometry and block origins through scalar loads
+// of host tables (BackCfg::angt, BackCfg::rectf).
 template <int CG, bool WEIGHTED, bool PAIRED>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
