@@ -130,7 +130,8 @@ boac_status boac_objective(boac_ctx *ctx, const boac_geom *geom, const float *d_
                            int32_t C, float delta_r_cm, int32_t n_iter, float *d_obj, float *d_img_out,
                            uint32_t *d_status, void *stream);
 
-/* Objective and its exact gradient dJ/d(c_0..c_5, mu_b, mu_c) through the unrolled MLEM iterations
+/* Eq. (6) with the inner problem solved by the fixed number of MLEM iterations of BOAC step 3: the
+ * objective and its exact gradient dJ/d(c_0..c_5, mu_b, mu_c) through the unrolled MLEM iterations
  * (reverse mode; the MLEM state is checkpointed every ckpt_every iterations and recomputed between
  * checkpoints; 1 <= ckpt_every, values above n_iter mean "only F^0").
  * d_obj [C], d_grad [C][8] out (order c_0..c_5, mu_b, mu_c); d_status [C] or NULL. */
@@ -233,6 +234,12 @@ boac_status boac_ctx_set_profiling(boac_ctx *ctx, int32_t enable);
 boac_status boac_ctx_kernel_stats(boac_ctx *ctx, int32_t kind, int64_t *count, double *total_ms,
                                   double *total_bytes);
 boac_status boac_ctx_reset_stats(boac_ctx *ctx);
+
+/* Graph cache of boac_evaluate_batch: the number of graphs held, the captures and replays so far, and
+ * the scratch generation (bumped whenever a scratch buffer is reallocated; a graph captured under an
+ * older generation is destroyed, never replayed). Any out pointer may be NULL. */
+boac_status boac_ctx_graph_stats(boac_ctx *ctx, int64_t *graphs, int64_t *captures, int64_t *replays,
+                                 int64_t *scratch_generation);
 
 #ifdef __cplusplus
 }

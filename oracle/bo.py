@@ -15,9 +15,16 @@ improvement (Eqs. 9-10) is largest. Readings of the printed formulas:
     kernel amplitude is 1 in standardised units; a fixed nugget `noise` is added to the diagonal;
     the length-scale is the one of a fixed geometric grid with the largest log marginal likelihood.
   - The paper's acquisition optimiser is a chaotic optimisation algorithm whose details it does not
-    give; the reading is a two-stage chaotic search driven by the logistic map z <- 4 z (1 - z):
-    a global stage that maps the chaotic sequence onto the whole box, then a local stage that maps it
-    onto a box around the incumbent whose half-width shrinks geometrically.
+    give, and it proposes one candidate per cycle. The reading (the one the library's outer loop runs):
+    P chains z in (0, 1)^d follow the logistic map z <- 4 z (1 - z), one step per evaluation round.
+    Global stage: n_global rounds, each evaluating every chain's point u = z. Centres: greedily, in
+    decreasing acquisition value, the evaluated points at least `exclusion` apart (unit-box distance),
+    max(centres, q) of them. Local stage: n_local rounds; the first per = P // (number of centres)
+    chains are split evenly over the centres (chain i * per + p serves centre i) and evaluate
+    u = clip(centre + r (2 z - 1), 0, 1) with r = radius0 shrink^t; a centre moves to its best point of
+    the round when that beats the centre's value. Every round keeps its per_step best points (ties by
+    lower index) as the pool; the q proposals are taken from the pool greedily in decreasing value,
+    each at least `exclusion` from the points already taken and from `taken`.
 """
 from __future__ import annotations
 
@@ -117,28 +124,69 @@ def logistic_map(z0, steps: int) -> np.ndarray:
     return np.stack(out)
 
 
-def chaotic_search(fun, z0: np.ndarray, n_global: int, n_local: int, shrink: float = 0.9,
-                   radius0: float = 0.25):
-    """Maximise fun over [0, 1]^d. z0 [P, d] chaotic seeds in (0, 1) (P parallel chains).
+def _greedy(points, values, q, exclusion, taken):
+    """Indices of up to q points in decreasing value (ties by lower index), each at least `exclusion`
+    from every point in `taken` and from every point picked before it."""
+    order = sorted(range(len(values)), key=lambda i: (-values[i], i))
+    ref = [np.asarray(t, np.float64) for t in taken]
+    picked = []
+    for i in order:
+        if len(picked) == q:
+            break
+        u = points[i]
+        if all(float(np.sum((u - t) ** 2)) >= exclusion * exclusion for t in ref):
+            picked.append(i)
+            ref.append(u)
+    return picked
 
-    Global stage: n_global steps, every chain's point u = z. Local stage: n_local steps around the
-    incumbent u*, u = clip(u* + r (2 z - 1), 0, 1) with r = radius0 shrink^t. Returns (u*, f*)."""
-    z = np.asarray(z0, np.float64).copy()
-    best_u, best_f = None, -np.inf
 
-    def consider(U):
-        nonlocal best_u, best_f
-        f = fun(U)
-        i = int(np.argmax(f))
-        if f[i] > best_f:
-            best_u, best_f = U[i].copy(), float(f[i])
+def _best_of_round(U, values, per_step):
+    """The per_step best points of one round (ties by lower index), in their original order."""
+    if len(values) <= per_step:
+        return U, values
+    keep = sorted(sorted(range(len(values)), key=lambda i: (-values[i], i))[:per_step])
+    return U[keep], values[keep]
 
+
+def chaotic_search(fun, z0: np.ndarray, q: int, taken, n_global: int, n_local: int, centres: int,
+                   radius0: float, shrink: float, exclusion: float, per_step: int):
+    """Maximise the acquisition `fun` (rows of a [m, d] array -> [m] values) over [0, 1]^d by the
+    two-stage chaotic search of the module header, from chains z0 [P, d] in (0, 1).
+
+    Returns (proposals [<= q, d], largest value evaluated, number of evaluations)."""
+    z = np.array(z0, dtype=np.float64)
+    P, d = z.shape
+    pool_u, pool_v = [], []
+    evaluations = 0
     for _ in range(n_global):
-        consider(z)
+        v = np.asarray(fun(z.copy()), np.float64)
+        evaluations += P
+        ku, kv = _best_of_round(z.copy(), v, per_step)
+        pool_u += list(ku)
+        pool_v += list(kv)
         z = 4.0 * z * (1.0 - z)
+    n_c = min(max(centres, q), P)
+    cidx = _greedy(pool_u, pool_v, n_c, exclusion, [])
+    cen = [pool_u[i].copy() for i in cidx]
+    cval = [pool_v[i] for i in cidx]
+    per = max(1, P // max(1, len(cen)))
     r = radius0
     for _ in range(n_local):
-        consider(np.clip(best_u[None, :] + r * (2.0 * z - 1.0), 0.0, 1.0))
+        U = np.empty((len(cen) * per, d))
+        for i in range(len(cen)):
+            for p in range(per):
+                U[i * per + p] = np.clip(cen[i] + r * (2.0 * z[i * per + p] - 1.0), 0.0, 1.0)
+        v = np.asarray(fun(U), np.float64)
+        evaluations += len(U)
+        ku, kv = _best_of_round(U, v, per_step)
+        pool_u += list(ku)
+        pool_v += list(kv)
+        for i in range(len(cen)):
+            j = max(range(per), key=lambda p: (v[i * per + p], -p))   # first of the round's best
+            if v[i * per + j] > cval[i]:
+                cen[i] = U[i * per + j].copy()
+                cval[i] = v[i * per + j]
         z = 4.0 * z * (1.0 - z)
         r *= shrink
-    return best_u, best_f
+    pick = _greedy(pool_u, pool_v, q, exclusion, list(np.asarray(taken, np.float64).reshape(-1, d)))
+    return np.array([pool_u[i] for i in pick]).reshape(-1, d), float(max(pool_v)), evaluations

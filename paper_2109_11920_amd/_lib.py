@@ -62,6 +62,8 @@ _SIGNATURES = {
     "boac_ctx_kernel_stats": (c_int32, [_P, c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "boac_ctx_reset_stats": (c_int32, [_P]),
+    "boac_ctx_graph_stats": (c_int32, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
 }
 
 _lib = None

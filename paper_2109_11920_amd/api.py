@@ -220,6 +220,12 @@ class Context:
     def reset_stats(self):
         check(self.lib.boac_ctx_reset_stats(self.handle))
 
+    def graph_stats(self):
+        """(graphs held, captures, replays, scratch generation) of the batch graph cache."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(self.lib.boac_ctx_graph_stats(self.handle, *[ctypes.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)
+
 
 @dataclass
 class SliceBatch:
@@ -278,15 +284,20 @@ def gp_fit(u: np.ndarray, y: np.ndarray, lengths: Sequence[float], n_select: int
 class BoacObjective(torch.autograd.Function):
     """J(theta) for a batch of candidates theta [C, 8] with an exact hand-written adjoint.
 
-    forward(ctx_obj, geom, meas, delta_r, n_iter, ckpt_every, theta) -> J [C]; the gradient is computed
-    together with J by the library's reverse sweep and applied in backward."""
+    forward(ctx_obj, geom, meas, delta_r, n_iter, ckpt_every, theta) -> J [C]; when theta requires a
+    gradient it is computed together with J by the library's reverse sweep and applied in backward,
+    otherwise only the objective is evaluated."""
 
     @staticmethod
     def forward(fctx, boac: Context, geom: Geometry, meas: torch.Tensor, delta_r: float, n_iter: int,
                 ckpt_every: int, theta: torch.Tensor):
         th = theta.detach().to(torch.float32).contiguous()
-        J, grad, status = boac.objective_grad(geom, meas, th, delta_r, n_iter, ckpt_every)
-        fctx.save_for_backward(grad)
+        if fctx.needs_input_grad[6]:
+            J, grad, status = boac.objective_grad(geom, meas, th, delta_r, n_iter, ckpt_every)
+            fctx.save_for_backward(grad)
+        else:
+            J, _, status = boac.objective(geom, meas, th, delta_r, n_iter)
+            fctx.save_for_backward(None)
         fctx.status = status
         return J.to(theta.dtype)
 

@@ -81,16 +81,69 @@ def greedy_select(U: np.ndarray, score: np.ndarray, q: int, exclusion: float, ta
 
 
 def _select_top(U, score, q, exclusion, taken, pool_per_pick: int = 16):
-    """greedy_select over the k best scores, k = pool_per_pick * q growing 4-fold until q picks qualify
-    (the same picks as over everything, which is the last resort)."""
+    """greedy_select over the k best scores (ties by lower index), k = pool_per_pick * q growing 4-fold
+    until q picks qualify: the same picks as over everything, which is the last resort."""
+    order = np.argsort(-np.asarray(score, np.float64), kind="stable")
     k = pool_per_pick * q
     while len(score) > k:
-        top = np.sort(np.argpartition(-score, k)[:k])
+        top = np.sort(order[:k])
         pick = greedy_select(U[top], score[top], q, exclusion, taken)
         if len(pick) == q:
             return [int(top[i]) for i in pick]
         k *= 4
     return greedy_select(U, score, q, exclusion, taken)
+
+
+def chaotic_acquire(ei_of, z: np.ndarray, q: int, taken, *, n_global: int, n_local: int, centres: int,
+                    radius0: float, shrink: float, exclusion: float, per_step: int):
+    """Step 5's search for q proposals maximising the acquisition ei_of (rows of a [m, d] unit-box array
+    -> [m] values), from the chains z [P, d] in (0, 1) of the logistic map z <- 4 z (1 - z).
+
+    Global stage: n_global rounds over the chains' points. Centres: the best evaluated points at least
+    `exclusion` apart, max(centres, q) of them. Local stage: n_local rounds; chains split evenly over the
+    centres sample boxes of half-width radius0 shrink^t around them, and a centre moves to its best point
+    of a round when that beats it. Each round keeps its per_step best points (ties by lower index); the
+    proposals are taken greedily from that pool, each at least `exclusion` from the points taken and from
+    `taken`. Returns (proposals [<= q, d], largest value evaluated, number of evaluations)."""
+    z = np.array(z, dtype=np.float64)
+    P, d = z.shape
+    pts, vals = [], []
+    n_queries = 0
+
+    def keep(U, e):
+        if len(e) > per_step:
+            top = np.sort(np.argsort(-e, kind="stable")[:per_step])
+            U, e = U[top], e[top]
+        pts.append(U.copy())
+        vals.append(e)
+
+    for _ in range(n_global):
+        e = np.asarray(ei_of(z), np.float64)
+        n_queries += P
+        keep(z, e)
+        z = 4.0 * z * (1.0 - z)
+    allU, allE = np.concatenate(pts), np.concatenate(vals)
+    cidx = _select_top(allU, allE, min(max(centres, q), P), exclusion, None)
+    C = allU[cidx].copy()
+    Ce = allE[cidx].copy()
+    per = max(1, P // max(1, len(C)))
+    r = radius0
+    for _ in range(n_local):
+        zz = z[:per * len(C)].reshape(len(C), per, d)
+        U = np.clip(C[:, None, :] + r * (2.0 * zz - 1.0), 0.0, 1.0).reshape(-1, d)
+        e = np.asarray(ei_of(U), np.float64)
+        n_queries += len(U)
+        keep(U, e)
+        e2 = e.reshape(len(C), per)
+        j = np.argmax(e2, axis=1)
+        better = e2[np.arange(len(C)), j] > Ce
+        C[better] = U.reshape(len(C), per, d)[better, j[better]]
+        Ce[better] = e2[better, j[better]]
+        z = 4.0 * z * (1.0 - z)
+        r *= shrink
+    allU, allE = np.concatenate(pts), np.concatenate(vals)
+    pick = _select_top(allU, allE, q, exclusion, taken)
+    return allU[pick], float(allE.max()), n_queries
 
 
 def line_search_points(u0: np.ndarray, grad_u: np.ndarray, steps=LINE_STEPS) -> np.ndarray:
@@ -211,49 +264,13 @@ class BOAC:
         d = self.lo.size
         rng = self._rng(cycle, 1)
         z = rng.uniform(0.01, 0.99, size=(self.chains, d))
-        pts, eis = [], []
-        n_queries = 0
-        per_step = max(4 * q, 256)   # points of each step kept for the batch selection
 
         def ei_of(U):
-            nonlocal n_queries
-            n_queries += len(U)
-            e = self.ctx.gp_ei(model, torch.as_tensor(U, device=self.ctx.device), best, self.xi)
-            return e.cpu().numpy()
+            return self.ctx.gp_ei(model, torch.as_tensor(U, device=self.ctx.device), best, self.xi).cpu().numpy()
 
-        def keep(U, e):
-            if len(e) > per_step:
-                top = np.sort(np.argpartition(-e, per_step)[:per_step])
-                U, e = U[top], e[top]
-            pts.append(U.copy())
-            eis.append(e)
-
-        for _ in range(self.n_global):
-            keep(z, ei_of(z))
-            z = 4.0 * z * (1.0 - z)
-        allU, allE = np.concatenate(pts), np.concatenate(eis)
-        # local stages around the best distinct points found so far (one per proposal wanted, at least
-        # `centres`), chains split evenly among them
-        cidx = _select_top(allU, allE, min(max(self.centres, q), self.chains), self.exclusion, None)
-        C = allU[cidx].copy()
-        Ce = allE[cidx].copy()
-        per = max(1, self.chains // max(1, len(C)))
-        r = self.radius0
-        for _ in range(self.n_local):
-            zz = z[:per * len(C)].reshape(len(C), per, d)
-            U = np.clip(C[:, None, :] + r * (2.0 * zz - 1.0), 0.0, 1.0).reshape(-1, d)
-            e = ei_of(U)
-            keep(U, e)
-            e2 = e.reshape(len(C), per)
-            j = np.argmax(e2, axis=1)
-            better = e2[np.arange(len(C)), j] > Ce
-            C[better] = U.reshape(len(C), per, d)[better, j[better]]
-            Ce[better] = e2[better, j[better]]
-            z = 4.0 * z * (1.0 - z)
-            r *= self.shrink
-        allU, allE = np.concatenate(pts), np.concatenate(eis)
-        pick = _select_top(allU, allE, q, self.exclusion, taken)
-        return allU[pick], float(allE.max()), n_queries
+        return chaotic_acquire(ei_of, z, q, taken, n_global=self.n_global, n_local=self.n_local,
+                               centres=self.centres, radius0=self.radius0, shrink=self.shrink,
+                               exclusion=self.exclusion, per_step=max(4 * q, 256))
 
     # ---- the loop -------------------------------------------------------------------------------
     def step(self) -> Cycle:
@@ -317,4 +334,4 @@ class BOAC:
         return self.best()
 
 
-__all__ = ["BOAC", "Cycle", "greedy_select", "line_search_points", "DEFAULT_LO", "DEFAULT_HI"]
+__all__ = ["BOAC", "Cycle", "chaotic_acquire", "greedy_select", "line_search_points", "DEFAULT_LO", "DEFAULT_HI"]

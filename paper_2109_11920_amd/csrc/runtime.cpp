@@ -111,6 +111,7 @@ struct Plan {
 struct GraphEntry {
     std::vector<uint64_t> key;
     hipGraphExec_t exec = nullptr;
+    uint64_t scratch_gen = 0;  // scratch generation the graph's kernels were captured against
 };
 
 struct boac_ctx {
@@ -128,7 +129,10 @@ struct boac_ctx {
     double stat_bytes[BOAC_K_COUNT] = {};
     std::vector<GraphEntry> graphs;
     bool capturing = false;
-    bool scratch_changed = false;
+    // bumped whenever a scratch buffer is freed and reallocated: a graph captured under an older
+    // generation may hold pointers to freed memory and is never replayed
+    uint64_t scratch_gen = 0;
+    int64_t graph_captures = 0, graph_replays = 0;
     std::string ns;                    // scratch namespace of the work being emitted (batch lane)
     std::vector<hipStream_t> lanes;    // concurrent streams of the batch scheduler
     std::vector<hipEvent_t> lane_done;
@@ -154,7 +158,7 @@ static boac_status ensure(boac_ctx *ctx, const char *name, size_t bytes, void **
             return fail(BOAC_ENOMEM, "scratch '%s': hipMalloc(%zu) failed: %s", name, want, hipGetErrorString(e));
         }
         b.bytes = want;
-        ctx->scratch_changed = true;
+        ++ctx->scratch_gen;
     }
     *out = b.p;
     return BOAC_OK;
@@ -1462,6 +1466,15 @@ static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_
     return rs;
 }
 
+// Destroy every cached graph captured under an older scratch generation (its kernels may address
+// buffers that were freed when scratch grew since).
+static void drop_stale_graphs(boac_ctx *ctx) {
+    auto stale = [&](const GraphEntry &g) { return g.scratch_gen != ctx->scratch_gen; };
+    for (auto &g : ctx->graphs)
+        if (stale(g) && g.exec) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.erase(std::remove_if(ctx->graphs.begin(), ctx->graphs.end(), stale), ctx->graphs.end());
+}
+
 boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
                                 int32_t n_iter, int32_t ckpt_every, void *stream) {
     if (!h_slices) return fail(BOAC_EINVAL, "h_slices is NULL");
@@ -1504,22 +1517,18 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
     const bool use_graph = (st != nullptr) && !ctx->profiling && std::getenv("BOAC_NO_GRAPH") == nullptr;
     if (!use_graph) return batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st);
 
+    drop_stale_graphs(ctx);
     for (auto &g : ctx->graphs) {
-        if (g.key == key && g.exec && !ctx->scratch_changed) {
+        if (g.key == key && g.exec) {
             HIP_TRY(hipGraphLaunch(g.exec, st));
+            ++ctx->graph_replays;
             return BOAC_OK;
         }
     }
-    // first call for this shape: run eagerly (sizes scratch, uploads tables), then capture
-    ctx->scratch_changed = false;
+    // first call for this shape: run eagerly (sizes scratch, uploads tables), then capture; graphs of
+    // other shapes whose scratch the eager run reallocated are dropped
     BOAC_TRY(batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st));
-    if (ctx->scratch_changed) {
-        // scratch moved: earlier graphs hold stale pointers
-        for (auto &g : ctx->graphs)
-            if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        ctx->graphs.clear();
-        ctx->scratch_changed = false;
-    }
+    drop_stale_graphs(ctx);
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     ctx->capturing = true;
@@ -1533,6 +1542,7 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
     if (ce != hipSuccess) return fail(BOAC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ce));
     GraphEntry ge;
     ge.key = key;
+    ge.scratch_gen = ctx->scratch_gen;
     hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(BOAC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
@@ -1541,6 +1551,7 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
         ctx->graphs.erase(ctx->graphs.begin());
     }
     ctx->graphs.push_back(ge);
+    ++ctx->graph_captures;
     // the eager run above already produced this call's results
     return BOAC_OK;
 }
@@ -1560,6 +1571,16 @@ boac_status boac_ctx_kernel_stats(boac_ctx *ctx, int32_t kind, int64_t *count, d
     if (count) *count = ctx->stat_count[kind];
     if (total_ms) *total_ms = ctx->stat_ms[kind];
     if (total_bytes) *total_bytes = ctx->stat_bytes[kind];
+    return BOAC_OK;
+}
+
+boac_status boac_ctx_graph_stats(boac_ctx *ctx, int64_t *graphs, int64_t *captures, int64_t *replays,
+                                 int64_t *scratch_generation) {
+    if (!ctx) return fail(BOAC_EINVAL, "context is NULL");
+    if (graphs) *graphs = (int64_t)ctx->graphs.size();
+    if (captures) *captures = ctx->graph_captures;
+    if (replays) *replays = ctx->graph_replays;
+    if (scratch_generation) *scratch_generation = (int64_t)ctx->scratch_gen;
     return BOAC_OK;
 }
 

@@ -80,7 +80,9 @@ def scores(F, activity):
     return {"ssim": ssim(F, activity), "cnr": cnr(F, hot, bg), "psnr": psnr(F, activity)}
 
 
-def run_case(ctx: Context, d, k: int, n_iter: int, cycles: int, gradient, seed: int):
+def run_case(ctx: Context, d, k: int, n_iter: int, cycles: int, gradient, seed: int, return_images: bool = False):
+    """Scores of case k; with return_images also the three reconstructions ("images": boac, nac,
+    ac_true_head, in activity units) and the BOAC head parameters' float32 values ("theta_boac_f32")."""
     n, na, nb, nt = (int(v) for v in d[f"case{k}_geometry"])
     g = Geometry(n, na, nb, nt, float(d[f"case{k}_pixel"]))
     dev = ctx.device
@@ -106,6 +108,9 @@ def run_case(ctx: Context, d, k: int, n_iter: int, cycles: int, gradient, seed: 
            "J_boac": float(Jc[0]), "J_true_head": float(Jc[1]), "bo_seconds": round(secs, 3), "kappa": kappa,
            "evaluations": int(sum(len(c.J) for c in bo.cycles)),
            "boac": scores(F[0], act), "nac": scores(F_nac, act), "ac_true_head": scores(F[1], act)}
+    if return_images:
+        out["images"] = {"boac": F[0], "nac": F_nac, "ac_true_head": F[1]}
+        out["theta_boac_f32"] = cand[0].double().cpu().numpy()
     return out
 
 

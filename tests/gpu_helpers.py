@@ -24,11 +24,23 @@ def rel_l2(got, ref):
     return num / den if den > 0 else num
 
 
+def max_rel(got, ref):
+    """max |got - ref| over max |ref|: a localised error (one pixel, a tile or band edge) shows here at
+    full size, where the relative L2 error dilutes it by the square root of the element count."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.abs(ref).max() if ref.size else 0.0
+    num = np.abs(got - ref).max() if ref.size else 0.0
+    return num / den if den > 0 else num
+
+
 def report(name, got, ref, tol):
+    """Print both errors of got against ref and assert each is within tol."""
     e = rel_l2(got, ref)
-    print(f"[parity] {name}: rel_l2={e:.3e} (tol {tol:.0e}) max_abs={np.abs(np.asarray(got, np.float64) - ref).max():.3e}",
-          flush=True)
+    m = max_rel(got, ref)
+    print(f"[parity] {name}: rel_l2={e:.3e} max_abs/max|ref|={m:.3e} (tol {tol:.0e})", flush=True)
     assert e <= tol, f"{name}: relative L2 error {e:.3e} > {tol:.0e}"
+    assert m <= tol, f"{name}: max |error| / max |ref| = {m:.3e} > {tol:.0e}"
     return e
 
 

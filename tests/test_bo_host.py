@@ -35,3 +35,31 @@ def test_cycle_journal_record_round_trips():
     assert r.index == 2 and r.kind == ["ei", "line"] and r.grad is None
     np.testing.assert_array_equal(r.theta, c.theta)
     np.testing.assert_array_equal(r.J, c.J)
+
+
+def test_acquisition_search_equals_the_oracle_search():
+    # the library's chaotic search (step 5) and the oracle's reading of it, from the same chains, on a
+    # closed-form acquisition with distinct values: identical proposals, largest value and evaluation count
+    import oracle.bo as obo
+    from paper_2109_11920_amd.bo import chaotic_acquire
+
+    d = 8
+    a = np.linspace(0.2, 0.8, d)
+    b = np.full(d, 0.35)
+
+    def acq(U):
+        U = np.asarray(U, np.float64)
+        return (np.exp(-np.sum((U - a) ** 2, axis=1) / 0.08) + 0.6 * np.exp(-np.sum((U - b) ** 2, axis=1) / 0.02)
+                + 1e-3 * (1.0 + U[:, 0] + 0.37 * U[:, 3]))
+
+    rng = np.random.default_rng(2024)
+    for q, chains, exclusion in ((12, 512, 0.02), (3, 300, 0.2)):
+        z = rng.uniform(0.01, 0.99, size=(chains, d))
+        taken = rng.uniform(size=(40, d))
+        kw = dict(n_global=6, n_local=10, centres=8, radius0=0.1, shrink=0.85, exclusion=exclusion,
+                  per_step=max(4 * q, 64))
+        U, best, m = chaotic_acquire(acq, z, q, taken, **kw)
+        Ur, best_r, m_r = obo.chaotic_search(acq, z, q, taken, **kw)
+        assert m == m_r and best == best_r
+        np.testing.assert_array_equal(U, Ur)
+        assert len(U) == q

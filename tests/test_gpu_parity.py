@@ -165,19 +165,21 @@ def test_objective_plain_config(ctx, slice128):
 
 def test_objective_batch_matches_oracle_samples(ctx, slice128):
     # the 256-candidate batch, 30 iterations, in the launch configuration of the bench; the oracle
-    # scores three sampled candidates one by one
+    # scores 16 candidates spread over the batch (every candidate group and XCD slot of the gather's
+    # grid is touched by one of them) one by one, objective and reconstruction
     g, og = geom_pair(128, 128, pixel=0.2)
     S = slice128["meas"].astype(np.float64)
     import synth
     th = f32(synth.draw_candidates(synth.candidate_stream(0), 256))
-    J, _, st = ctx.objective(g, dev(S), dev(th), DR, 30)
+    J, F, st = ctx.objective(g, dev(S), dev(th), DR, 30, want_image=True)
     J = J.cpu().numpy()
     st = st.cpu().numpy()
     assert np.all(np.isfinite(J))
     assert np.all((st & 3) == 0)
-    for c in (0, 137, 255):
-        Jr = oracle.evaluate(og, S, th[c], DR, 30)[0]
+    for c in (0, 17, 34, 51, 68, 85, 102, 119, 137, 154, 171, 188, 205, 222, 239, 255):
+        Jr, Fr, _ = oracle.evaluate(og, S, th[c], DR, 30)
         report(f"batch256 J cand {c}", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"batch256 F^K cand {c}", F[c].cpu().numpy(), Fr, TOL)
 
 
 def test_objective_paper72_samples(ctx):

@@ -1,6 +1,7 @@
 """GPU parity on the uneven batch: 48 slices with N in {96,128,192,256} and 64-256 angles, 32 candidates
 each, 40 MLEM iterations, objective and gradient (checkpoint every 5), in one captured batch. The oracle
-scores sampled (slice, candidate) pairs one by one; the rest is checked through properties."""
+scores sampled (slice, candidate) pairs one by one, including the 192- and 256-pixel slices whose ray
+kernels run in row bands; the rest is checked through properties."""
 import os
 
 import numpy as np
@@ -81,7 +82,7 @@ def test_uneven_batch_objective_samples(uneven, n, na, c):
            np.array([Jr]), TOL)
 
 
-@pytest.mark.parametrize("n,na,c", [(96, 64, 7), (128, 96, 21)])
+@pytest.mark.parametrize("n,na,c", [(96, 64, 7), (128, 96, 21), (192, 64, 9), (256, 64, 13)])
 def test_uneven_batch_gradient_samples(uneven, n, na, c):
     ctx, slices, host, w, _ = uneven
     s = _pick(host, n, na)

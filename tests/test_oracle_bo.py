@@ -106,12 +106,44 @@ def test_logistic_map_closed_form():
     assert np.all((seq > 0) & (seq < 1))
 
 
+def _search(fun, z0, q=1, taken=(), **kw):
+    args = dict(n_global=20, n_local=60, centres=4, radius0=0.1, shrink=0.85, exclusion=0.02, per_step=256)
+    args.update(kw)
+    return bo.chaotic_search(fun, z0, q, np.asarray(taken, np.float64).reshape(-1, z0.shape[1]), **args)
+
+
 def test_chaotic_search_finds_a_known_maximum():
     target = np.array([0.31, 0.77, 0.52])
     fun = lambda U: -np.sum((U - target) ** 2, axis=1)
     z0 = np.random.default_rng(4).uniform(0.05, 0.95, size=(64, 3))
-    u, f = bo.chaotic_search(fun, z0, 20, 60)
-    assert np.abs(u - target).max() < 2e-3 and f > -1e-5
+    U, f, m = _search(fun, z0)
+    assert m == 20 * 64 + 60 * 64
+    assert np.abs(U[0] - target).max() < 2e-3 and f > -1e-5 and fun(U)[0] == f
+
+
+def test_chaotic_search_finds_both_modes_and_respects_exclusion():
+    # two separated maxima of different heights: with q = 2 the proposals are the two peaks (in order
+    # of height), and a third proposal is at least `exclusion` from both and from `taken`
+    a, b = np.array([0.2, 0.3]), np.array([0.8, 0.7])
+    fun = lambda U: (np.exp(-np.sum((U - a) ** 2, axis=1) / 0.001)
+                     + 0.5 * np.exp(-np.sum((U - b) ** 2, axis=1) / 0.001))
+    z0 = np.random.default_rng(5).uniform(0.05, 0.95, size=(256, 2))
+    # exclusion 0.1: the first peak's shoulder there is exp(-10), below the second peak's 0.5
+    U, f, _ = _search(fun, z0, q=3, taken=[[0.5, 0.5]], exclusion=0.1)
+    assert np.abs(U[0] - a).max() < 5e-3 and np.abs(U[1] - b).max() < 5e-3
+    assert f == pytest.approx(1.0, abs=1e-4)
+    pts = np.vstack([U, [[0.5, 0.5]]])
+    d2 = np.sum((pts[:, None] - pts[None]) ** 2, axis=-1) + np.eye(len(pts))
+    assert d2.min() >= 0.1 ** 2
+
+
+def test_planted_centre_never_moving_fails_the_maximum_pin(monkeypatch):
+    # a local stage whose radius never shrinks (shrink = 1) cannot refine to the known maximum
+    target = np.array([0.31, 0.77, 0.52])
+    fun = lambda U: -np.sum((U - target) ** 2, axis=1)
+    z0 = np.random.default_rng(4).uniform(0.05, 0.95, size=(64, 3))
+    U, f, _ = _search(fun, z0, shrink=1.0)
+    assert not (np.abs(U[0] - target).max() < 2e-3 and f > -1e-5)
 
 
 def test_planted_sign_error_in_gamma_breaks_the_integral_pin():

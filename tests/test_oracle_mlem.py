@@ -1,5 +1,5 @@
 """Pins for the oracle's MLEM and objective (Eq. 5, BOAC step 3): dense explicit-matrix MLEM from the
-brute-force system matrix, count preservation, monotone likelihood (Shepp-Vardi), fixed point, scale
+brute-force system matrix (8 x 8, and 16 x 16 with 16 and 24 angles), count preservation, monotone likelihood (Shepp-Vardi), fixed point, scale
 invariance of the first iterate, and the Poisson log-pmf from scipy."""
 import math
 
@@ -9,9 +9,9 @@ import scipy.stats
 
 import oracle
 from oracle.mlem import log_factorial, mlem, neg_log_likelihood
-from oracle.projector import attenuation, project, sensitivity
+from oracle.projector import attenuation, backproject, project, sensitivity
 
-from test_oracle_projector import dense_system_bruteforce
+from test_oracle_projector import dense_system_bruteforce, dense_system_direct
 
 
 def _dense_mlem(A, S, n_iter):
@@ -35,6 +35,52 @@ def test_dense_explicit_matrix_mlem(na):
     ref = _dense_mlem(A, S, 12)
     got = mlem(g, attenuation(g, mu), S.reshape(na, n), 12)
     np.testing.assert_allclose(got.ravel(), ref, rtol=1e-11, atol=1e-13)
+
+
+def _dense_16(na, seed):
+    """16 x 16 problem: the system matrix from plain loops, from the projector's columns and from the
+    backprojector's rows, and a Poisson sinogram."""
+    n = 16
+    g = oracle.Geometry(n, na, n, n, 0.5)
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(0, 0.3, (n, n))
+    A = dense_system_direct(g, mu)
+    att = attenuation(g, mu)
+    cols = np.stack([project(g, att, np.eye(n * n)[j].reshape(n, n)).ravel() for j in range(n * n)], 1)
+    rows = np.stack([backproject(g, att, np.eye(g.n_rays)[i].reshape(na, n)).ravel() for i in range(g.n_rays)], 0)
+    S = rng.poisson(A @ rng.uniform(0.5, 2.0, n * n)).astype(float)
+    return g, mu, att, A, cols, rows, S
+
+
+def _pin_dense_mlem_16(g, att, A, S, K=15):
+    ref = _dense_mlem(A, S, K)
+    got = mlem(g, att, S.reshape(g.n_angles, g.n_bins), K)
+    np.testing.assert_allclose(got.ravel(), ref, rtol=1e-11, atol=1e-13 * ref.max())
+
+
+@pytest.mark.parametrize("na", [16, 24])
+def test_dense_explicit_matrix_mlem_16(na):
+    # the plain-loop matrix equals the projector's columns and the backprojector's rows (so the two are
+    # transposes), and dense NumPy MLEM on it equals the matrix-free oracle MLEM
+    g, mu, att, A, cols, rows, S = _dense_16(na, seed=na)
+    np.testing.assert_allclose(cols, A, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(rows, A, rtol=1e-12, atol=1e-14)
+    _pin_dense_mlem_16(g, att, A, S)
+
+
+@pytest.mark.parametrize("mistake", ["unattenuated_sensitivity", "unguarded_ratio"])
+def test_planted_mlem_mistakes_fail_the_dense_pin(monkeypatch, mistake):
+    import importlib
+    om = importlib.import_module("oracle.mlem")   # the module (the package re-exports a function of that name)
+    g, mu, att, A, cols, rows, S = _dense_16(16, seed=16)
+    if mistake == "unattenuated_sensitivity":
+        # s computed from the plain Radon transform instead of A^T 1
+        monkeypatch.setattr(om, "sensitivity", lambda gg, a: sensitivity(gg, np.ones_like(a)))
+    else:
+        # r = S / y everywhere, with zero counts replaced by one (a mistaken zero-count rule)
+        monkeypatch.setattr(om, "ratio", lambda m, y: np.maximum(m, 1.0) / y)
+    with pytest.raises(AssertionError):
+        _pin_dense_mlem_16(g, att, A, S)
 
 
 def _problem(n=24, na=24, seed=0):
