@@ -80,23 +80,120 @@ def kernel_name(kind, C):
     return "k_back (MLEM gather)"
 
 
-def cpu_baseline(workload_S, n_cand, n_iter):
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample of the batch."""
+_WORKER = {}
+
+
+def _oracle_worker_init(S):
+    import numpy as np
+
+    import oracle
+    og = oracle.Geometry(128, 128, 128, 128, 0.2)
+    oracle.sampling_matrix(og)  # geometry setup outside the timed sample
+    _WORKER.update(og=og, S=np.asarray(S, np.float64))
+
+
+def _oracle_worker_eval(args):
+    import oracle
+    theta, n_iter = args
+    return oracle.evaluate(_WORKER["og"], _WORKER["S"], theta, DELTA_R, n_iter)[0]
+
+
+def cpu_baseline(workload_S, n_cand, n_iter, workers):
+    """The FP64 oracle as it stands on a bounded sample of the batch: one thread, then one process per
+    host core (candidate-parallel, the core count the box grants this job)."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import oracle
     import synth
     og = oracle.Geometry(128, 128, 128, 128, 0.2)
-    th = synth.draw_candidates(synth.candidate_stream(0), 256)[:n_cand]
+    th = synth.draw_candidates(synth.candidate_stream(0), 256)
     S = workload_S.astype(np.float64)
     oracle.sampling_matrix(og)  # geometry setup outside the timed sample
     t0 = time.perf_counter()
     for c in range(n_cand):
         oracle.evaluate(og, S, th[c], DELTA_R, n_iter)
     dt = time.perf_counter() - t0
-    return {"value": n_cand * n_iter / dt, "unit": "cand·it/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cand} of the 256 candidates, {n_iter} MLEM iterations + objective each, "
-                      f"FP64 NumPy/SciPy single thread, {dt:.1f} s"}
+    single = n_cand * n_iter / dt
+    # all cores: one process per core (fresh interpreters), each evaluating whole candidates
+    n_par = 4 * workers
+    with mp.get_context("spawn").Pool(workers, initializer=_oracle_worker_init, initargs=(S,)) as pool:
+        pool.map(_oracle_worker_eval, [(th[c], 1) for c in range(workers)], chunksize=1)   # warm every worker
+        t1 = time.perf_counter()
+        pool.map(_oracle_worker_eval, [(th[c], n_iter) for c in range(n_par)], chunksize=1)
+        dt_par = time.perf_counter() - t1
+    par = n_par * n_iter / dt_par
+    return {"value": round(par, 2), "unit": "cand·it/s", "cores": workers, "kind": "oracle",
+            "host_cores": os.cpu_count(),
+            "sample": f"{n_par} of the 256 candidates, {n_iter} MLEM iterations + objective each, FP64 NumPy/"
+                      f"SciPy, one single-threaded process per core on {workers} cores, {dt_par:.1f} s",
+            "single_thread": {"value": round(single, 2), "unit": "cand·it/s", "cores": 1,
+                              "sample": f"{n_cand} candidates on one thread, {dt:.1f} s"}}
+
+
+def survey_bytes(n, na, nb, nt, K, paired):
+    """Algorithmic HBM bytes of one candidate's evaluation (K MLEM iterations + objective):
+    (2K+3) V + (4K+3) I + (3K+1) Y with V the attenuation tensor, I an image, Y a sinogram (FP32);
+    with opposed-ray pairing the tensor is half the angles plus exp(-T) per held ray."""
+    V = 4.0 * na * nb * nt
+    I = 4.0 * n * n
+    Y = 4.0 * na * nb
+    if paired:
+        V = V / 2 + Y / 2
+    return (2 * K + 3) * V + (4 * K + 3) * I + (3 * K + 1) * Y
+
+
+def gather_survey_bytes(n, na, nb, nt):
+    """Algorithmic bytes of one candidate's MLEM backprojection-and-update (V + Y + 3I, full tensor)."""
+    return 4.0 * (na * nb * nt + na * nb + 3 * n * n)
+
+
+def plain_line(ctx, g, S, theta, dev, reps=10):
+    """The plain GPU method, unbatched: one candidate (the true head), 50 MLEM iterations + objective on
+    the 128^2 / 128-angle slice, with the roofline of its dominant kernel from per-launch HIP events."""
+    import numpy as np
+    import torch
+
+    cand = torch.as_tensor(np.asarray(theta, np.float32)[None], device=dev).contiguous()
+    K = 50
+    obj = torch.empty(1, device=dev)
+    status = torch.empty(1, device=dev, dtype=torch.int32)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(2):
+        ctx.objective(g, S, cand, DELTA_R, K, obj=obj, status=status)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.objective(g, S, cand, DELTA_R, K, obj=obj, status=status)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert bool(torch.isfinite(obj).all())
+    ctx.reset_stats()
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        ctx.objective(g, S, cand, DELTA_R, K, obj=obj, status=status)
+    torch.cuda.synchronize()
+    ks = {k: ctx.kernel_stats(k) for k in ("att", "fwd", "back", "reduce")}
+    ctx.set_profiling(False)
+    dom = max(("fwd", "back"), key=lambda k: ks[k][1])
+    cnt, kms, by = ks[dom]
+    avg = kms / max(cnt, 1)
+    ach = by / max(cnt, 1) / (avg / 1e3) / 1e9
+    paired = os.environ.get("BOAC_OPPOSED_RAYS", "1") != "0"
+    step = survey_bytes(128, 128, 128, 128, K, paired)
+    return {"value": round(K / (ms / 1e3), 1), "unit": "cand·it/s", "ms_per_evaluation": round(ms, 3),
+            "us_per_iteration": round(1e3 * ms / K, 2),
+            "kernel_ms_per_evaluation": {k: round(v[1] / reps, 4) for k, v in ks.items() if v[0]},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg, 4),
+                         "bytes_per_launch": by / max(cnt, 1),
+                         "step_frac_paired_bytes": round(step / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "what": "plain_n128: one candidate (true head), 128^2, 128 angles, 50 MLEM iterations + objective, "
+                    "one call (C = 1)"}
 
 
 def paper72_line(ctx, dev, reps=5):
@@ -299,8 +396,11 @@ def main():
         print("bench.py measures one GPU: candidates are independent and this build has no multi-GPU "
               "path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    # host cores granted to this job (the box's share, which OMP_NUM_THREADS states there), for the
+    # all-cores oracle leg: one single-threaded process per core
+    workers = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1))
     for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[var] = "1"   # the CPU oracle baseline is single-threaded
+        os.environ[var] = "1"   # every oracle process is single-threaded
 
     import numpy as np
     import torch
@@ -368,10 +468,24 @@ def main():
     avg_ms = ms / max(cnt, 1)
     bytes_per_launch = by / max(cnt, 1)
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    paired = os.environ.get("BOAC_OPPOSED_RAYS", "1") != "0"
+    survey_launch = C * gather_survey_bytes(128, 128, 128, 128)
+    step_survey = C * survey_bytes(128, 128, 128, 128, K, False)
+    step_paired = C * survey_bytes(128, 128, 128, 128, K, paired)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, "batch256_n128"),
             "kernel": kernel_name(dom, C), "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bytes_per_launch,
-            "launches": cnt}
+            "launches": cnt,
+            "bytes_convention": "achieved/frac: the bytes this kernel must move as built (with opposed-ray "
+                                "pairing the held half of the attenuation tensor plus exp(-T) per ray, the "
+                                "ratio sinogram, F and s read, F written); frac_survey_bytes: the full-tensor "
+                                "count V + Y + 3I per candidate over the same time",
+            "frac_survey_bytes": round(survey_launch / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step": {"survey_bytes": step_survey, "paired_bytes": step_paired,
+                     "frac_survey_bytes": round(step_survey / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_paired_bytes": round(step_paired / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "what": "whole step: (2K+3) V + (4K+3) I + (3K+1) Y per candidate over the step time; "
+                             "paired: V -> V/2 + exp(-T) per held ray"}}
     kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in kstats.items() if v[0]}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "cand·it/s", "n_gpus": 1,
@@ -421,6 +535,7 @@ def main():
         out["batched_over_plain"] = round(value / plain_rate, 2)
 
         out.update(grad_lines(ctx, g, S, dev, args.steps))
+        out["plain_n128"] = plain_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64), dev)
 
     if not args.only_main:
         out["paper72"] = paper72_line(ctx, dev)
@@ -432,7 +547,7 @@ def main():
         out["bo"] = bo_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64))
 
     if not args.no_cpu and not args.only_main:
-        out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K)
+        out["cpu_baseline"] = cpu_baseline(S_np, args.cpu_cands, K, workers)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -24,7 +24,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
     th = cands(11, 4)
     stream = torch.cuda.Stream()
     with Context(0) as ctx:
-        sb = SliceBatch.make(g, meas, torch.as_tensor(th, device="cuda"), with_grad=False)
+        sb = SliceBatch.make(g, meas, torch.as_tensor(th, dtype=torch.float32, device="cuda"), with_grad=False)
         with torch.cuda.stream(stream):
             ctx.evaluate_batch([sb], DR, 6)          # eager run, then capture
         stream.synchronize()
@@ -33,7 +33,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
         assert (graphs, captures, replays) == (1, 1, 0)
 
         # a larger objective call grows the shared scratch: the captured graph's buffers are freed
-        big = torch.as_tensor(cands(12, 64), device="cuda")
+        big = torch.as_tensor(cands(12, 64), dtype=torch.float32, device="cuda")
         with torch.cuda.stream(stream):
             ctx.objective(g, meas, big, DR, 2)
         stream.synchronize()
