@@ -130,6 +130,21 @@ boac_status boac_objective(boac_ctx *ctx, const boac_geom *geom, const float *d_
                            int32_t C, float delta_r_cm, int32_t n_iter, float *d_obj, float *d_img_out,
                            uint32_t *d_status, void *stream);
 
+/* boac_objective for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). Same arguments, results and validation as
+ * boac_objective; every scratch buffer and table is carved from a fixed device array of
+ * BOAC_NOALLOC_SCRATCH_BYTES that the library holds per device until the process ends, so the call makes
+ * no hipMalloc / hipFree and allocates nothing on the device (the tables are copied in with
+ * hipMemcpyAsync on `stream` from host copies the context keeps). Candidates are evaluated in chunks
+ * that fit the array; BOAC_ENOMEM when even one candidate of the geometry does not fit (at 128 x 128,
+ * 128 angles, about 4.6 MB per candidate). Every call on one device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (other streams, other contexts, other
+ * threads) race and must be serialised by the caller. */
+#define BOAC_NOALLOC_SCRATCH_BYTES (64u << 20)
+boac_status boac_objective_noalloc(boac_ctx *ctx, const boac_geom *geom, const float *d_meas,
+                                   const boac_cand *d_cand, int32_t C, float delta_r_cm, int32_t n_iter,
+                                   float *d_obj, float *d_img_out, uint32_t *d_status, void *stream);
+
 /* Eq. (6) with the inner problem solved by the fixed number of MLEM iterations of BOAC step 3: the
  * objective and its exact gradient dJ/d(c_0..c_5, mu_b, mu_c) through the unrolled MLEM iterations
  * (reverse mode; the MLEM state is checkpointed every ckpt_every iterations and recomputed between

@@ -49,6 +49,8 @@ _SIGNATURES = {
     "boac_mlem": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_int32, _P, _P]),
     "boac_objective": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, _P, _P, _P,
                                  _P]),
+    "boac_objective_noalloc": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, _P, _P,
+                                         _P, _P]),
     "boac_objective_grad": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, c_int32,
                                       _P, _P, _P, _P]),
     "boac_objective_grad_ex": (c_int32, [_P, ctypes.POINTER(BoacGeom), _P, _P, c_int32, c_float, c_int32, c_int32,

@@ -144,6 +144,20 @@ class Context:
                                       _ptr(status, "status", dtype=torch.int32, shape=(C,)), _stream(self.device)))
         return obj, img, status
 
+    def objective_noalloc(self, geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, delta_r: float,
+                          n_iter: int, obj: torch.Tensor, status: torch.Tensor, img: Optional[torch.Tensor] = None):
+        """boac_objective_noalloc: as objective(), with the library's fixed per-device scratch and no device
+        allocation by the library; the caller provides every output. Returns (obj, img, status)."""
+        C = cand.shape[0]
+        check(self.lib.boac_objective_noalloc(self.handle, ctypes.byref(geom.c()),
+                                              _ptr(meas, "meas", shape=geom.sino_shape),
+                                              _ptr(cand, "cand", shape=(C, 8)), C, float(delta_r), int(n_iter),
+                                              _ptr(obj, "obj", shape=(C,)),
+                                              _ptr(img, "img", shape=(C,) + geom.image_shape),
+                                              _ptr(status, "status", dtype=torch.int32, shape=(C,)),
+                                              _stream(self.device)))
+        return obj, img, status
+
     def objective_grad(self, geom: Geometry, meas: torch.Tensor, cand: torch.Tensor, delta_r: float, n_iter: int,
                        ckpt_every: int = 5, obj=None, grad=None, status=None):
         """Returns (J [C], dJ/dtheta [C, 8], status [C] int32)."""

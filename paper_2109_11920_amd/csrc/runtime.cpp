@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,35 @@ static boac_status fail(boac_status st, const char *fmt, ...) {
         boac_status _s = (expr);          \
         if (_s != BOAC_OK) return _s;     \
     } while (0)
+
+// ------------------------------------------------------------------ no-allocation scratch
+// File-scope device array behind boac_objective_noalloc: each device the library runs on holds its own
+// copy until the process ends. In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address is taken once per device with hipGetSymbolAddress (noalloc_base) and only
+// that address is passed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[BOAC_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static std::map<int, void *> g_noalloc_base;  // device -> device address of `scratch`
+
+// Device address of this device's `scratch` (the device must be current); looked up once per device.
+static boac_status noalloc_base(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_base.find(device);
+    if (it != g_noalloc_base.end()) {
+        *out = it->second;
+        return BOAC_OK;
+    }
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(BOAC_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device, hipGetErrorString(e));
+    }
+    g_noalloc_base[device] = ptr;
+    *out = ptr;
+    return BOAC_OK;
+}
 
 // ------------------------------------------------------------------ validation (no HIP calls)
 static constexpr size_t kLdsBudget = 160 * 1024 - 256;  // gfx950: 160 KiB of LDS per workgroup
@@ -108,6 +138,15 @@ struct Plan {
     BackCfg back;
 };
 
+// Bump allocation from a fixed device region (the no-allocation entry point): named buffers of one call
+// are carved in request order, and a name requested again gets its earlier range when that is large
+// enough. No HIP call is made.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    std::map<std::string, std::pair<size_t, size_t>> named;  // name -> (offset, bytes)
+};
+
 struct GraphEntry {
     std::vector<uint64_t> key;
     hipGraphExec_t exec = nullptr;
@@ -134,12 +173,34 @@ struct boac_ctx {
     uint64_t scratch_gen = 0;
     int64_t graph_captures = 0, graph_replays = 0;
     std::string ns;                    // scratch namespace of the work being emitted (batch lane)
+    void *noalloc = nullptr;           // device address of this device's no-allocation scratch
+    Arena *arena = nullptr;            // set during a no-allocation call: scratch and tables come from it
+    hipStream_t arena_stream = nullptr;
+    std::map<std::vector<int>, std::vector<int4>> host_rects;   // host copies uploaded into an arena
+    std::map<int, std::vector<float2>> host_trig;
     std::vector<hipStream_t> lanes;    // concurrent streams of the batch scheduler
     std::vector<hipEvent_t> lane_done;
     hipEvent_t fork = nullptr;
 };
 
+static boac_status arena_take(Arena &a, const std::string &name, size_t bytes, void **out) {
+    auto it = a.named.find(name);
+    if (it != a.named.end() && it->second.second >= bytes) {
+        *out = a.base + it->second.first;
+        return BOAC_OK;
+    }
+    const size_t off = (a.used + 255) & ~(size_t)255;
+    if (off + bytes > a.cap)
+        return fail(BOAC_ENOMEM, "scratch '%s' (%zu bytes at offset %zu) exceeds the %zu-byte no-allocation scratch",
+                    name.c_str(), bytes, off, a.cap);
+    a.used = off + bytes;
+    a.named[name] = {off, bytes};
+    *out = a.base + off;
+    return BOAC_OK;
+}
+
 static boac_status ensure(boac_ctx *ctx, const char *name, size_t bytes, void **out) {
+    if (ctx->arena) return arena_take(*ctx->arena, ctx->ns + name, bytes, out);
     DevBuf &b = ctx->bufs[ctx->ns + name];
     if (b.bytes < bytes) {
         if (ctx->capturing) return fail(BOAC_EDEVICE, "scratch '%s' must grow during graph capture", name);
@@ -176,6 +237,16 @@ static boac_status host_trig(int na, std::vector<float2> &h);
 
 // cos/sin of 2 pi a / na in double, exact at multiples of 90 degrees, rounded to float
 static boac_status trig_table(boac_ctx *ctx, int na, const float2 **out) {
+    if (ctx->arena) {
+        // host copy kept in the context (the source of an asynchronous upload must outlive it)
+        std::vector<float2> &h = ctx->host_trig[na];
+        if (h.empty()) BOAC_TRY(host_trig(na, h));
+        void *d = nullptr;
+        BOAC_TRY(arena_take(*ctx->arena, "#trig", sizeof(float2) * na, &d));
+        HIP_TRY(hipMemcpyAsync(d, h.data(), sizeof(float2) * na, hipMemcpyHostToDevice, ctx->arena_stream));
+        *out = (const float2 *)d;
+        return BOAC_OK;
+    }
     std::vector<int> key{na};
     auto it = ctx->trig.find(key);
     if (it != ctx->trig.end()) {
@@ -232,9 +303,20 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc, in
         bc->angt = bc->slid ? bc->rectf + 2 * nent : nullptr;
     };
     auto it = ctx->rects.find(key);
-    if (it != ctx->rects.end()) {
+    if (!ctx->arena && it != ctx->rects.end()) {
         point(it->second);
         return BOAC_OK;
+    }
+    if (ctx->arena) {
+        auto hit = ctx->host_rects.find(key);
+        if (hit != ctx->host_rects.end()) {
+            void *d = nullptr;
+            BOAC_TRY(arena_take(*ctx->arena, "#rects", sizeof(int4) * hit->second.size(), &d));
+            HIP_TRY(hipMemcpyAsync(d, hit->second.data(), sizeof(int4) * hit->second.size(), hipMemcpyHostToDevice,
+                                   ctx->arena_stream));
+            point((int4 *)d);
+            return BOAC_OK;
+        }
     }
     if (ctx->capturing) return fail(BOAC_EDEVICE, "rectangle table upload during graph capture");
     std::vector<float2> trig;
@@ -321,6 +403,16 @@ static boac_status rect_table(boac_ctx *ctx, const boac_geom &g, BackCfg *bc, in
             h.push_back(w[0]);
             h.push_back(w[1]);
         }
+    }
+    if (ctx->arena) {
+        // host copy kept in the context (the source of an asynchronous upload must outlive it)
+        std::vector<int4> &keep = ctx->host_rects[key];
+        keep = std::move(h);
+        void *d = nullptr;
+        BOAC_TRY(arena_take(*ctx->arena, "#rects", sizeof(int4) * keep.size(), &d));
+        HIP_TRY(hipMemcpyAsync(d, keep.data(), sizeof(int4) * keep.size(), hipMemcpyHostToDevice, ctx->arena_stream));
+        point((int4 *)d);
+        return BOAC_OK;
     }
     int4 *d = nullptr;
     HIP_TRY(hipMalloc(&d, sizeof(int4) * h.size()));
@@ -532,7 +624,7 @@ static hipEvent_t take_event(boac_ctx *ctx) {
 
 template <typename F>
 static boac_status timed(boac_ctx *ctx, int kind, double bytes, hipStream_t st, F &&launch) {
-    const bool t = ctx->profiling && !ctx->capturing;
+    const bool t = ctx->profiling && !ctx->capturing && !ctx->arena;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t) {
         e0 = take_event(ctx);
@@ -669,13 +761,31 @@ static int cand_chunk(const Sizes &z, int C, int tensors) {
     return std::min(m, C);
 }
 
+// Candidates per chunk of a forward evaluation that fit the no-allocation scratch: an upper bound of
+// the per-candidate buffers (mu, att, exp(-T), s, two images, the ratio sinogram, one partial per ray
+// chunk of the smallest plan) against what the fixed buffers (tables, status, reductions) leave.
+// 0 when not even one candidate fits.
+static int arena_chunk(const boac_geom &g, int C, size_t cap) {
+    const Sizes z = sizes_of(g);
+    const double nrays = (double)g.n_angles * g.n_bins;
+    const double per = 4.0 * (4.0 * z.I + (double)z.VS + (double)z.Y + (double)z.Y) + 8.0 * std::ceil(nrays / 64.0) +
+                       8 * 256.0;
+    const double tiles = std::ceil(g.n / 16.0) * std::ceil(g.n / 16.0);
+    const double fixed = 8.0 * g.n_angles + 48.0 * tiles * g.n_angles + 32.0 * g.n_angles + 4.0 * C + 64.0 +
+                         16 * 256.0;
+    if ((double)cap < fixed + per) return 0;
+    return (int)std::min<double>(C, std::floor(((double)cap - fixed) / per));
+}
+
 // Forward evaluation of C candidates of one slice. With env_grad set, also the envelope gradient:
 // dJ/dtheta with the reconstruction F^K held fixed (one projection adjoint after the objective),
 // ncomp components per candidate (8, or 9 with dR).
 static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *meas, const float *cand, int C,
                                 float delta_r, int K, float *obj, float *img_out, uint32_t *status, hipStream_t st,
                                 float *env_grad = nullptr, int ncomp = 8) {
-    const int Cc = cand_chunk(sizes_of(g), C, env_grad ? 2 : 1);
+    const int Cc = ctx->arena ? arena_chunk(g, C, ctx->arena->cap) : cand_chunk(sizes_of(g), C, env_grad ? 2 : 1);
+    if (Cc < 1) return fail(BOAC_ENOMEM, "one candidate of this geometry needs more than the %zu-byte no-allocation "
+                            "scratch", ctx->arena ? ctx->arena->cap : (size_t)0);
     DevGeom dg;
     Plan p;
     Sizes z;
@@ -1056,6 +1166,7 @@ boac_status boac_ctx_create(int32_t device, const char *tune_cache_path, boac_ct
     auto ctx = std::make_unique<boac_ctx>();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    BOAC_TRY(noalloc_base(device, &ctx->noalloc));
     load_tune(ctx.get(), tune_cache_path);
     *out = ctx.release();
     return BOAC_OK;
@@ -1224,6 +1335,38 @@ boac_status boac_objective(boac_ctx *ctx, const boac_geom *geom, const float *d_
     CTX_CHECK();
     return eval_forward(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, d_obj, d_img_out, d_status,
                         (hipStream_t)stream);
+}
+
+boac_status boac_objective_noalloc(boac_ctx *ctx, const boac_geom *geom, const float *d_meas,
+                                   const boac_cand *d_cand, int32_t C, float delta_r_cm, int32_t n_iter,
+                                   float *d_obj, float *d_img_out, uint32_t *d_status, void *stream) {
+    BOAC_TRY(check_geom(geom));
+    BOAC_TRY(check_count(C));
+    BOAC_TRY(check_ptr(d_meas, "d_meas"));
+    BOAC_TRY(check_ptr(d_cand, "d_cand"));
+    BOAC_TRY(check_ptr(d_obj, "d_obj"));
+    BOAC_TRY(check_ptr(d_img_out, "d_img_out", true));
+    BOAC_TRY(check_ptr(d_status, "d_status", true));
+    if (n_iter < 0 || n_iter > 100000) return fail(BOAC_EINVAL, "n_iter = %d outside [0, 100000]", n_iter);
+    if (!(delta_r_cm > 0.f) || !std::isfinite(delta_r_cm)) return fail(BOAC_EINVAL, "delta_r_cm must be > 0");
+    if (arena_chunk(*geom, C, BOAC_NOALLOC_SCRATCH_BYTES) < 1)
+        return fail(BOAC_ENOMEM, "boac_objective_noalloc: %d candidates of a %dx%d image, %d angles x %d bins x %d "
+                    "samples need more than the %u-byte no-allocation scratch",
+                    C, geom->n, geom->n, geom->n_angles, geom->n_bins, geom->n_samples,
+                    (unsigned)BOAC_NOALLOC_SCRATCH_BYTES);
+    CTX_CHECK();
+    if (!ctx->noalloc) return fail(BOAC_EDEVICE, "no-allocation scratch address unknown");
+    Arena arena;
+    arena.base = (char *)ctx->noalloc;
+    arena.cap = BOAC_NOALLOC_SCRATCH_BYTES;
+    ctx->arena = &arena;
+    ctx->arena_stream = (hipStream_t)stream;
+    ctx->ns.clear();
+    const boac_status r = eval_forward(ctx, *geom, d_meas, (const float *)d_cand, C, delta_r_cm, n_iter, d_obj,
+                                       d_img_out, d_status, (hipStream_t)stream);
+    ctx->arena = nullptr;
+    ctx->arena_stream = nullptr;
+    return r;
 }
 
 boac_status boac_objective_grad(boac_ctx *ctx, const boac_geom *geom, const float *d_meas, const boac_cand *d_cand,

@@ -110,3 +110,14 @@ def test_gp_entry_points_validate_before_the_device(lib):
     assert lib.boac_gp_ei(*args(16)) == 1 and b"context" in lib.boac_last_error()
     assert lib.boac_gp_fit(None, None, 0, 8, None, 1, 0, 1e-6, None, None, None) == 1
 
+
+
+def test_noalloc_rejects_a_geometry_beyond_its_scratch_before_the_device(lib):
+    # 1024 x 1024, 512 angles: one candidate's attenuation tensor alone is 2 GB, beyond the fixed array
+    g = BoacGeom(1024, 512, 1024, 1024, 0.025)
+    st = lib.boac_objective_noalloc(None, ctypes.byref(g), ALIGNED, ALIGNED, 1, 0.8, 5, ALIGNED, None, None, None)
+    assert st == 3 and b"no-allocation scratch" in lib.boac_last_error()
+    # valid sizes, no context: refused before any device call
+    st = lib.boac_objective_noalloc(None, ctypes.byref(_good()), ALIGNED, ALIGNED, 4, 0.8, 5, ALIGNED, None, None,
+                                    None)
+    assert st == 1 and b"context" in lib.boac_last_error()
