@@ -204,6 +204,50 @@ __device__ __forceinline__ void stage_band(const float *__restrict__ img, int n,
     }
 }
 
+// The whole n x n image (n a multiple of 4) into lds with the layout of stage_band's single band (rows
+// and columns -1..n+1, pitch n+3, zero border): 16-byte loads, U of them in flight per thread, so a
+// small workgroup stages an image in a few memory round trips. Falls back to stage_band otherwise.
+template <int U = 8>
+__device__ __forceinline__ void stage_whole(const float *__restrict__ img, int n, const Band &band, float *lds) {
+    if ((n & 3) != 0 || band.alo != -1 || band.ahi != n + 1) {
+        stage_band<1>(img, n, band, lds);
+        return;
+    }
+    const int pitch = n + 3;
+    // zero border: rows -1, n, n+1 and columns -1, n, n+1 of every staged row
+    for (int t = threadIdx.x; t < 3 * pitch; t += blockDim.x) {
+        const int r = t / pitch, c = t - r * pitch;
+        lds[(r == 0 ? 0 : n + r) * pitch + c] = 0.f;
+    }
+    for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) {
+        const int r = t / 3, c = t - 3 * r;
+        lds[(r + 1) * pitch + (c == 0 ? 0 : n + c)] = 0.f;
+    }
+    const int q = n >> 2;  // 16-byte groups per row
+    const int total = n * q;
+    const float4 *src = reinterpret_cast<const float4 *>(img);
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            v[u] = (idx < total) ? src[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) {
+                const int r = idx / q, c = 4 * (idx - r * q);
+                float *d = lds + (r + 1) * pitch + c + 1;
+                d[0] = v[u].x;
+                d[1] = v[u].y;
+                d[2] = v[u].z;
+                d[3] = v[u].w;
+            }
+        }
+    }
+}
+
 // Two images staged interleaved (float2: first image, second image) with the same zero border.
 __device__ __forceinline__ void stage_band_pair(const float *__restrict__ img0, const float *__restrict__ img1, int n,
                                                 const Band &band, float *lds) {

@@ -578,6 +578,23 @@ __device__ __forceinline__ void load_cands(const float *p, float (&v)[CG]) {
     }
 }
 
+// The gather's epilogue for output element o: v is the compensated sum over the angles.
+__device__ __forceinline__ void back_epilogue(const DevGeom &g, const BackArgs &A, int mode, size_t o, float v) {
+    if (mode == BACK_FIELD) {
+        A.out[o] = v;
+    } else if (mode == BACK_MLEM) {
+        const float b = g.dx * v;
+        const float sv = A.s[o];
+        const float Q = (sv > 0.f) ? b / sv : 0.f;
+        A.out[o] = A.F[o] * Q;
+        if (A.q_out) A.q_out[o] = Q;
+    } else if (mode == BACK_ADJ) {
+        A.out[o] = fmaf(g.dx, v, A.aux[o]);
+    } else {
+        A.out[o] = g.dx * v;
+    }
+}
+
 // Column-group variant of the slid-block gather (n_samples a multiple of 4). The host aligns the
 // block's first sample row to a multiple of 4, so the 4 samples k..k+3 (k = first row + 4 j) of a bin
 // are one aligned 16-byte load in the attenuation layout (sample fastest inside a 4 x 8 block): thread
@@ -595,7 +612,7 @@ __device__ __forceinline__ void load_cands(const float *p, float (&v)[CG]) {
 // The ray weights reach the staging threads through a small LDS table (one load per bin and
 // candidate, one angle ahead), and the per-angle trigonometry and block origins through scalar loads
 // of host tables (BackCfg::angt, BackCfg::rectf).
-template <int CG, bool WEIGHTED, bool PAIRED>
+template <int CG, bool WEIGHTED, bool PAIRED, bool SPLIT>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
     constexpr int PL = kSlidPitch;
@@ -605,11 +622,17 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     extern __shared__ float lds[];  // [PLANES][P rows][PL slots][V], then the ray weights wz, we
     const int ntiles = T.tiles_x * T.tiles_y;
     const int ngroups = (A.C + CG - 1) / CG;
-    const int total = ntiles * ngroups;
+    const int nsplit = SPLIT ? T.asplit : 1;
+    const int total = ntiles * ngroups * nsplit;
     int id = blockIdx.x;
     if (T.xcd_remap && (total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
-    const int grp = id / ntiles;
-    const int tile = id - grp * ntiles;
+    const int grp = id / (ntiles * nsplit);
+    const int rem = id - grp * (ntiles * nsplit);
+    const int tile = rem / nsplit;
+    // angle split: this workgroup gathers the held angles [a_lo, a_hi), whole 8-angle blocks
+    const int split = rem - tile * nsplit;
+    const int bps = ((g.nah + 7) / 8 + nsplit - 1) / nsplit;
+    const int a_lo = min(split * bps * 8, g.nah), a_hi = min((split + 1) * bps * 8, g.nah);
     const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
     const int l0 = tx * 16, i0 = ty * 16;
     const int c0 = grp * CG;
@@ -706,16 +729,19 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
         }
     };
 
-    int4 cur = const_ld(rects, 0);
-    wload(0, cur);
-    prefetch(0, cur);
+    int4 cur = make_int4(0, 0, 0, 0);
+    if (a_lo < a_hi) {
+        cur = const_ld(rects, a_lo);
+        wload(a_lo, cur);
+        prefetch(a_lo, cur);
+    }
     const bool field = (mode == BACK_FIELD);
 
-    for (int a = 0; a < g.nah; ++a) {
+    for (int a = a_lo; a < a_hi; ++a) {
         // the gather's per-angle constants, loaded here so the staging hides their latency
         const float4 t0 = const_ld(T.angt, 2 * a), t1 = const_ld(T.angt, 2 * a + 1);
         const float4 f0 = const_ld(rectf, 2 * a), f1 = const_ld(rectf, 2 * a + 1);
-        if (a == 0) wstore();  // later angles' weights are stored after the previous gather
+        if (a == a_lo) wstore();  // later angles' weights are stored after the previous gather
         __syncthreads();  // previous gather done with the LDS
         // this thread's bin: z and (PAIRED) the opposed ray's factor exp(-T) z'
         float zv[CG], ez[CG];
@@ -756,7 +782,7 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
             }
         }
         __syncthreads();
-        if (a + 1 < g.nah) {
+        if (a + 1 < a_hi) {
             cur = const_ld(rects, a + 1);
             wload(a + 1, cur);
             prefetch(a + 1, cur);
@@ -799,54 +825,79 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
                 if (db < 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        if (a + 1 < g.nah) wstore();  // the weights of angle a + 1, for its staging
+        if (a + 1 < a_hi) wstore();  // the weights of angle a + 1, for its staging
         if ((a & 7) == 7 || a == g.nah - 1) {
+            if constexpr (SPLIT) {
+                // angle split: the block's sum goes to the partial buffer [block][candidate][pixel];
+                // k_back_combine adds the blocks in order, as the loop below would
+                if (pv) {
+                    const size_t pix = (size_t)i * g.n + l;
 #pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                comp_add(acc[q], blk[q]);
-                blk[q] = 0.f;
+                    for (int q = 0; q < CG; ++q)
+                        if (q < ncg) A.blk_out[((size_t)(a >> 3) * A.C + c0 + q) * A.img_cs + pix] = blk[q];
+                }
+#pragma unroll
+                for (int q = 0; q < CG; ++q) blk[q] = 0.f;
+            } else {
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    comp_add(acc[q], blk[q]);
+                    blk[q] = 0.f;
+                }
             }
         }
     }
 
-    if (!pv) return;
+    if (!pv || SPLIT) return;
     const size_t pix = (size_t)i * g.n + l;
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
         if (q >= ncg) break;
-        const size_t o = (size_t)(c0 + q) * A.img_cs + pix;
-        const float v = comp_value(acc[q]);
-        if (mode == BACK_FIELD) {
-            A.out[o] = v;
-        } else if (mode == BACK_MLEM) {
-            const float b = g.dx * v;
-            const float sv = A.s[o];
-            const float Q = (sv > 0.f) ? b / sv : 0.f;
-            A.out[o] = A.F[o] * Q;
-            if (A.q_out) A.q_out[o] = Q;
-        } else if (mode == BACK_ADJ) {
-            A.out[o] = fmaf(g.dx, v, A.aux[o]);
-        } else {
-            A.out[o] = g.dx * v;
-        }
+        back_epilogue(g, A, mode, (size_t)(c0 + q) * A.img_cs + pix, comp_value(acc[q]));
+    }
+}
+
+// Second pass of the angle-split gather: per (candidate, pixel) the 8-angle block sums, added in angle
+// order to a compensated total exactly as the unsplit gather adds them, then the same epilogue.
+__global__ __launch_bounds__(256) void k_back_combine(DevGeom g, BackArgs A, int nblk, int mode) {
+    const size_t npix = (size_t)g.n * g.n;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)A.C * npix) return;
+    const size_t c = t / npix, pix = t - c * npix;
+    const size_t o = c * A.img_cs + pix;
+    Comp acc{0.f, 0.f};
+    for (int b = 0; b < nblk; ++b) comp_add(acc, A.blk_out[((size_t)b * A.C + c) * A.img_cs + pix]);
+    back_epilogue(g, A, mode, o, comp_value(acc));
+}
+
+template <int CG, bool SPLIT>
+static void back_col4_go(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
+    const int ngroups = (a.C + CG - 1) / CG;
+    const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups * (SPLIT ? bc.asplit : 1)));
+    const bool weighted = !(mode == BACK_SENS || mode == BACK_FIELD);
+    if (a.E) {
+        if (weighted)
+            hipLaunchKernelGGL((k_back_col4<CG, true, true, SPLIT>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+        else
+            hipLaunchKernelGGL((k_back_col4<CG, false, true, SPLIT>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    } else if (weighted) {
+        hipLaunchKernelGGL((k_back_col4<CG, true, false, SPLIT>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    } else {
+        hipLaunchKernelGGL((k_back_col4<CG, false, false, SPLIT>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
     }
 }
 
 template <int CG>
 static hipError_t back_col4(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
-    const int ngroups = (a.C + CG - 1) / CG;
-    const dim3 grid((unsigned)(bc.tiles_x * bc.tiles_y * ngroups));
-    const bool weighted = !(mode == BACK_SENS || mode == BACK_FIELD);
-    if (a.E) {
-        if (g.nah * 2 != g.na) return hipErrorInvalidValue;
-        if (weighted)
-            hipLaunchKernelGGL((k_back_col4<CG, true, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
-        else
-            hipLaunchKernelGGL((k_back_col4<CG, false, true>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
-    } else if (weighted) {
-        hipLaunchKernelGGL((k_back_col4<CG, true, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+    if (bc.asplit < 1 || (bc.asplit > 1 && !a.blk_out)) return hipErrorInvalidValue;
+    if (a.E && g.nah * 2 != g.na) return hipErrorInvalidValue;
+    if (bc.asplit > 1) {
+        back_col4_go<CG, true>(g, bc, a, mode, st);
+        const size_t n = (size_t)a.C * g.n * g.n;
+        hipLaunchKernelGGL(k_back_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, a,
+                           (g.nah + 7) / 8, mode);
     } else {
-        hipLaunchKernelGGL((k_back_col4<CG, false, false>), grid, dim3(256), bc.lds, st, g, bc, a, mode);
+        back_col4_go<CG, false>(g, bc, a, mode, st);
     }
     return hipGetLastError();
 }

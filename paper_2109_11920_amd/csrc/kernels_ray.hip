@@ -158,6 +158,94 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
     }
 }
 
+// Attenuation build with each ray's scan spread over kScanLanes lanes of one wave (single-stage images).
+// The ray is walked from the detector end in rounds of kScanLanes 4-sample groups, lane j taking the
+// j-th group of the round counted from the detector: each lane samples its 4 values m_k = (W mu)_k from
+// the staged image and sums them (compensated); a Kogge-Stone scan over the 8 lanes (3 shuffle steps of
+// compensated merges) gives each lane the sum of the groups nearer the detector in this round, to which
+// the carry of the earlier rounds is merged; the lane then scans its own 4 samples toward the source,
+// L_k = dx (m_k / 2 + sum_{k'>k} m_k'), and stores att = exp(-L) (no smaller than the smallest normal
+// float) as one 16-byte store, and the round's total joins the carry. The 8 lanes of a ray and the 8
+// rays of a wave (consecutive bins) write whole 128-byte lines of the 4 x 8-block layout. The carry
+// ends as the ray total: exp(-T) for opposed-ray pairing. passes: rays per lane group handled in turn,
+// so that one image stage serves many rays.
+constexpr int kScanLanes = 8;
+
+__global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int passes, int chunks, int C,
+                                                  const float *__restrict__ mu, float *__restrict__ att,
+                                                  size_t img_cs, size_t att_cs, float *__restrict__ E,
+                                                  size_t e_cs) {
+    extern __shared__ float lds[];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    stage_whole(mu + cand * img_cs, g.n, band, lds);
+    __syncthreads();
+    const int nrays = g.nah * g.nb;
+    const int rpp = blockDim.x / kScanLanes;
+    const int lane = threadIdx.x & (kScanLanes - 1);
+    const int base = (threadIdx.x & (kWave - 1)) & ~(kScanLanes - 1);
+    const int ng = (g.nt + 3) >> 2;
+    const int rounds = (ng + kScanLanes - 1) / kScanLanes;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(att + cand * att_cs, (unsigned)(4 * att_cs));
+    for (int ps = 0; ps < passes; ++ps) {
+        const int ray = (chunk * passes + ps) * rpp + (int)threadIdx.x / kScanLanes;
+        const bool live = ray < nrays;
+        const int a = live ? ray / g.nb : 0, b = live ? ray - a * g.nb : 0;
+        const float2 cs = g.trig[a];
+        float Ub, Vb;
+        ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+        const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+        Comp carry{0.f, 0.f};
+        for (int r = 0; r < rounds; ++r) {
+            const int grp = ng - 1 - (r * kScanLanes + lane);
+            float m[4];
+            Comp own{0.f, 0.f};
+#pragma unroll
+            for (int q = 3; q >= 0; --q) {
+                const int k = 4 * grp + q;
+                m[q] = 0.f;
+                if (live && grp >= 0 && k < g.nt) {
+                    float U, V;
+                    sample_uv(Ub, Vb, tau_of(g, k), cs.x, cs.y, U, V);
+                    m[q] = bilinear_whole(lds, U, V, nf, pitch);
+                    comp_add(own, m[q]);
+                }
+            }
+            // inclusive scan over the lanes of the ray (lane 0 nearest the detector)
+            Comp inc = own;
+#pragma unroll
+            for (int off = 1; off < kScanLanes; off <<= 1) {
+                const Comp o{__shfl(inc.s, base + ((lane - off) & (kScanLanes - 1)), kWave),
+                             __shfl(inc.e, base + ((lane - off) & (kScanLanes - 1)), kWave)};
+                if (lane >= off) comp_merge(inc, o);
+            }
+            const Comp prev{__shfl(inc.s, base + ((lane - 1) & (kScanLanes - 1)), kWave),
+                            __shfl(inc.e, base + ((lane - 1) & (kScanLanes - 1)), kWave)};
+            const Comp total{__shfl(inc.s, base + kScanLanes - 1, kWave), __shfl(inc.e, base + kScanLanes - 1, kWave)};
+            Comp T = carry;
+            if (lane > 0) comp_merge(T, prev);
+            if (live && grp >= 0) {
+                float e[4];
+#pragma unroll
+                for (int q = 3; q >= 0; --q) {
+                    const int k = 4 * grp + q;
+                    e[q] = 0.f;
+                    if (k < g.nt) {
+                        const float L = g.dx * (fmaf(0.5f, m[q], T.s) + T.e);
+                        e[q] = fmaxf(expf(-L), kMinNormal);
+                        comp_add(T, m[q]);
+                    }
+                }
+                buffer_st4(rs, roff + 4u * att_row(g, 4 * grp), 0u, make_float4(e[0], e[1], e[2], e[3]));
+            }
+            comp_merge(carry, total);
+        }
+        if (E && live && lane == 0) E[cand * e_cs + ray] = expf(-g.dx * comp_value(carry));
+    }
+}
+
 // ------------------------------------------------------------------ forward projection
 // The epilogue of one ray: y, or the MLEM ratio, or (returned) the NLL term; zero_proj is set where
 // S > 0 meets y <= 0.
@@ -905,11 +993,97 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
     }
 }
 
+// Forward projection for few candidates (a grid of one-thread-per-ray workgroups would leave most of the
+// GPU idle): each ray is split over kSplitLanes lanes of one wave, lane j taking the 16-sample chunks j,
+// j + kSplitLanes, ... of the ray. A chunk is summed exactly as in k_fwd's single-stage path (same
+// positions, same bilinear reads, FMAs in sample order), and the chunk sums are then added to the
+// compensated total in chunk order after a shuffle, so every ray's result equals k_fwd's and
+// k_fwd_pair's bit for bit. Single-stage images, n_samples <= 16 kSplitLanes kSplitCpl; epilogues y and
+// the MLEM ratio (the likelihood keeps its per-workgroup partials in k_fwd).
+constexpr int kSplitLanes = 8;
+constexpr int kSplitCpl = 2;  // chunks per lane
+
+template <int MODE, bool PAIRED>
+__global__ __launch_bounds__(256) void k_fwd_split(DevGeom g, Band band, int chunks, int C, FwdArgs A) {
+    static_assert(MODE != FWD_NLL, "the likelihood epilogue runs in k_fwd");
+    extern __shared__ float lds[];
+    int cand, chunk;
+    ray_block(chunks, C, cand, chunk);
+    const int nrays = g.nah * g.nb;
+    const int pitch = g.n + 3;
+    const float nf = (float)g.n;
+    const int lane = threadIdx.x & (kSplitLanes - 1);
+    const int ray = chunk * (blockDim.x / kSplitLanes) + threadIdx.x / kSplitLanes;
+    const bool live = ray < nrays;
+    stage_whole(A.img + cand * A.img_cs, g.n, band, lds);
+    __syncthreads();
+
+    constexpr int KC = 16, KG = KC / 4;
+    const int a = live ? ray / g.nb : 0, b = live ? ray - a * g.nb : 0;
+    const float2 cs = g.trig[a];
+    float Ub, Vb;
+    ray_base(g, sigma_of(g, b), cs.x, cs.y, Ub, Vb);
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(A.att + cand * A.att_cs, (unsigned)(4 * A.att_cs));
+    const unsigned roff = 4u * (unsigned)att_base(g, a, b);
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float e_ray = (PAIRED && live) ? A.E[cand * A.e_cs + ray] : 0.f;
+    const int nck = (g.nt + KC - 1) / KC;
+    float part[kSplitCpl], part2[kSplitCpl];
+#pragma unroll
+    for (int h = 0; h < kSplitCpl; ++h) {
+        part[h] = part2[h] = 0.f;
+        const int ck = lane + h * kSplitLanes;
+        if (!live || ck >= nck) continue;
+        const int k0 = ck * KC;
+        float4 v[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) v[q] = (k0 + 4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, k0 + 4 * q)) : z4;
+        float tau = (float)k0 - g.cT;
+        float p = 0.f, p2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            if (k0 + q < g.nt) {
+                float U, V;
+                sample_uv(Ub, Vb, tau, cs.x, cs.y, U, V);
+                const float at = f4at(v[q >> 2], q & 3);
+                const float w = bilinear_whole(lds, U, V, nf, pitch);
+                p = fmaf(at, w, p);
+                if constexpr (PAIRED) p2 = fmaf(opposed_att(e_ray, at), w, p2);
+            }
+            tau += 1.f;
+        }
+        part[h] = p;
+        part2[h] = p2;
+    }
+    // the compensated total over the chunks in order (chunk ck is in lane ck % L, slot ck / L)
+    const int base = (threadIdx.x & (kWave - 1)) & ~(kSplitLanes - 1);
+    Comp c{0.f, 0.f}, c2{0.f, 0.f};
+    for (int ck = 0; ck < nck; ++ck) {
+        const int h = ck / kSplitLanes;
+        const float mine = (h == 0) ? part[0] : part[kSplitCpl - 1];
+        kahan_add(c, __shfl(mine, base + ck % kSplitLanes, kWave));
+        if constexpr (PAIRED) {
+            const float mine2 = (h == 0) ? part2[0] : part2[kSplitCpl - 1];
+            kahan_add(c2, __shfl(mine2, base + ck % kSplitLanes, kWave));
+        }
+    }
+    if (!live || lane != 0) return;
+    bool zero_proj = false;
+    fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(c), zero_proj);
+    if constexpr (PAIRED) fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(c2), zero_proj);
+}
+
 // ------------------------------------------------------------------ launchers
 static dim3 ray_grid(const RayCfg &rc, int C) { return dim3((unsigned)(rc.chunks * C)); }
 
 hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
                       size_t img_cs, size_t att_cs, float *E, size_t e_cs, int C, hipStream_t st) {
+    if (rc.single && rc.scan_passes > 0) {
+        if (rc.scan_block % 64 != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_att_scan, dim3((unsigned)(rc.scan_chunks * C)), dim3(rc.scan_block), rc.lds, st, g,
+                           bands.b[0], rc.scan_passes, rc.scan_chunks, C, mu, att, img_cs, att_cs, E, e_cs);
+        return hipGetLastError();
+    }
     if (rc.single)
         hipLaunchKernelGGL(k_att<true>, ray_grid(rc, C), dim3(rc.block), rc.lds, st, g, bands, rc.rpt, rc.chunks, C,
                            mu, att, img_cs, att_cs, E, e_cs);
@@ -922,6 +1096,13 @@ hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, co
 template <int MODE, bool PAIRED>
 static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                      hipStream_t st) {
+    if constexpr (MODE != FWD_NLL) {
+        if (rc.split_chunks > 0 && rc.single && a.img_comps == 1 && g.nt <= 16 * kSplitLanes * kSplitCpl) {
+            hipLaunchKernelGGL((k_fwd_split<MODE, PAIRED>), dim3((unsigned)(rc.split_chunks * C)), dim3(256), rc.lds,
+                               st, g, bands.b[0], rc.split_chunks, C, a);
+            return;
+        }
+    }
     if (rc.pair && rc.single && a.img_comps == 1 && C >= 2)
         hipLaunchKernelGGL((k_fwd_pair<MODE, PAIRED>), dim3((unsigned)(rc.chunks * ((C + 1) / 2))), dim3(rc.block),
                            2 * rc.lds, st, g, bands, rc.rpt, rc.chunks, C, a);

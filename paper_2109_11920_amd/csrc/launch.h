@@ -24,6 +24,11 @@ struct RayCfg {
     size_t lds;  // dynamic LDS bytes of one image stage
     bool single; // whole image staged at once
     bool pair;   // forward projection of two candidates per workgroup (single stage, 2 lds bytes)
+    int split_chunks;  // > 0: few candidates: the projection (not the likelihood) splits each ray over 8
+                       // lanes, 32 rays per 256-thread workgroup, split_chunks workgroups per candidate
+    // attenuation build with the scan over 8 lanes per ray (single stage; scan_passes 0 = one thread per
+    // ray): scan_block threads, scan_passes rays per lane group, scan_chunks workgroups per candidate
+    int scan_block, scan_passes, scan_chunks;
 };
 
 enum FwdMode { FWD_PROJ = 0, FWD_RATIO = 1, FWD_NLL = 2 };
@@ -92,6 +97,8 @@ struct BackCfg {
     int slid;             // 16 x 16 tiles, one-bin half window: fixed 32 x 32 staging block slid inside
                           // the sinogram; rects then hold (b0, k0, u0 bits, v0 bits). 1: staging by
                           // 4-byte slots; 2: by aligned 4-sample column groups (k0 a multiple of 4)
+    int asplit;           // column-group gather: workgroups per (tile, candidate group) splitting the held
+                          // angles in whole 8-angle blocks (1 = none; > 1 needs BackArgs::blk_out)
 };
 
 constexpr int kSlidBlock = 32;  // staged bins and samples of the slid-block backprojection
@@ -106,6 +113,7 @@ struct BackArgs {
     const float *aux;     // ADJ: direct part of F_bar
     float *out;           // [C][n][n]
     float *q_out;         // MLEM: update factor b/s (nullable)
+    float *blk_out;       // angle split: [ceil(nah / 8)][C][img_cs] per-8-angle-block sums (else null)
     size_t att_cs, sino_cs, img_cs;
     size_t e_cs;          // E stride per candidate
     int C;

@@ -470,6 +470,10 @@ static std::string shape_key(const char *kind, const boac_geom &g, int C, int ex
     return buf;
 }
 
+// Candidate counts up to this one get the few-candidate plans (ray-split projection, angle-split
+// gather): the unbatched evaluation and small calls, where a plan for many candidates leaves CUs idle.
+constexpr int kFewCand = 8;
+
 // nah: angles whose rays the kernels walk (n_angles, or half of them with opposed-ray pairing).
 static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands, int nah) {
     make_bands(g.n, comps, rc, bands);
@@ -502,6 +506,28 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
         if (it->second.size() >= 3) rc->pair = pair_fits && it->second[2] != 0;
     }
     rc->chunks = (nrays + rc->block * rc->rpt - 1) / (rc->block * rc->rpt);
+    // few candidates (at most kFewCand): the projection splits each ray over 8 lanes when one thread per
+    // ray would not give every CU a workgroup (single-stage images, up to 256 samples; each 32-ray
+    // workgroup stages the whole image, which pays only while the GPU would otherwise idle;
+    // BOAC_FWD_SPLIT=0 turns it off)
+    rc->split_chunks = 0;
+    const char *es = std::getenv("BOAC_FWD_SPLIT");
+    const bool split_on = !(es && es[0] == '0');
+    if (split_on && C <= kFewCand && comps == 1 && rc->single && g.n_samples <= 256 &&
+        (long)rc->chunks * C < ctx->n_cu)
+        rc->split_chunks = (nrays + 31) / 32;
+    // attenuation build: the scan of each ray spread over 8 lanes (single stage, up to 256 samples;
+    // BOAC_ATT_SCAN=0: one thread per ray); 1024-thread workgroups when there are rays enough, and as
+    // many rays per lane group as still give every CU two workgroups (at most 32)
+    rc->scan_block = rc->scan_passes = rc->scan_chunks = 0;
+    const char *ea = std::getenv("BOAC_ATT_SCAN");
+    if (!(ea && ea[0] == '0') && comps == 1 && rc->single && g.n_samples <= 256) {
+        rc->scan_block = ((long)nrays * C >= 64L * ctx->n_cu * 128) ? 1024 : 256;
+        const int rpp = rc->scan_block / 8;
+        const long total = (nrays + rpp - 1) / rpp;
+        rc->scan_passes = (int)std::min<long>(32, std::max<long>(1, total * C / (2L * ctx->n_cu)));
+        rc->scan_chunks = (int)((total + rc->scan_passes - 1) / rc->scan_passes);
+    }
 }
 
 static void back_fill(const boac_geom &g, BackCfg *bc) {
@@ -553,7 +579,8 @@ static bool slid_ok(const boac_geom &g, const BackCfg &b) {
 
 static bool plan_ok(const boac_geom &g, const BackCfg &b) { return b.slid ? slid_ok(g, b) : back_cfg_ok(b); }
 
-static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
+// nah: angles the gather walks (n_angles, or half of them with opposed-ray pairing)
+static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc, int nah) {
     // preference order: the slid-block kernel where it applies, then the general one; big candidate
     // groups amortise the footprint staging and the window weights, and the choice falls back while
     // the grid would not fill the GPU twice over
@@ -600,13 +627,24 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc) {
         back_fill(g, &t);
         if (plan_ok(g, t)) *bc = t;
     }
+    // few candidates (at most kFewCand): the column-group gather splits the angles in whole 8-angle
+    // blocks over more workgroups (a second pass adds the blocks in order) while the grid would not fill
+    // the GPU twice over (BOAC_GATHER_SPLIT=0 turns it off)
+    bc->asplit = 1;
+    const char *eg = std::getenv("BOAC_GATHER_SPLIT");
+    if (bc->slid == 2 && C <= kFewCand && !(eg && eg[0] == '0')) {
+        const long wgs = (long)bc->tiles_x * bc->tiles_y * ((C + bc->cg - 1) / bc->cg);
+        const int nblk = (nah + 7) / 8;
+        if (wgs < 2L * ctx->n_cu)
+            bc->asplit = (int)std::min<long>(nblk, (2L * ctx->n_cu + wgs - 1) / wgs);
+    }
 }
 
 static boac_status make_plan(boac_ctx *ctx, const boac_geom &g, int C, Plan *p, int nah = -1) {
     if (nah < 0) nah = g.n_angles;
     ray_plan(ctx, g, C, 1, &p->ray1, &p->bands1, nah);
     ray_plan(ctx, g, C, 2, &p->ray2, &p->bands2, nah);
-    back_plan(ctx, g, C, &p->back);
+    back_plan(ctx, g, C, &p->back, nah);
     return rect_table(ctx, g, &p->back, nah);
 }
 
@@ -720,8 +758,15 @@ static boac_status run_fwd(boac_ctx *ctx, int mode, const DevGeom &dg, const Pla
 
 static boac_status run_back(boac_ctx *ctx, int mode, const DevGeom &dg, const Plan &p, const Sizes &z,
                             const BackArgs &a, hipStream_t st) {
-    return timed(ctx, BOAC_K_BACK, bytes_back(z, a.C, mode), st,
-                 [&] { return launch_back(mode, dg, p.back, a, st); });
+    BackArgs b = a;
+    double bytes = bytes_back(z, a.C, mode);
+    if (p.back.asplit > 1) {
+        // angle split: one partial image per 8-angle block, written by the gather, read by the combine pass
+        const size_t nblk = (size_t)(dg.nah + 7) / 8;
+        BOAC_TRY(ensure_t(ctx, "blk", nblk * a.C * z.I, &b.blk_out));
+        bytes += 8.0 * nblk * a.C * z.I;
+    }
+    return timed(ctx, BOAC_K_BACK, bytes, st, [&] { return launch_back(mode, dg, p.back, b, st); });
 }
 
 static FwdArgs fwd_args(const Sizes &z, const float *att, const float *img, const float *meas,

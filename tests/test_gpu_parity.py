@@ -546,3 +546,53 @@ def test_launch_configurations_agree(slice64, tmp_path):
     Jr, Gr = oracle.objective_and_grad(og, slice64["meas"].astype(np.float64), cands(22, C)[0], DR, 3)
     report("launch configs J cand 0", ref[1][:1], np.array([Jr]), TOL)
     report("launch configs dJ cand 0", ref[2][0], Gr, TOL_GRAD)
+
+
+@pytest.mark.parametrize("shape,pixel", [((128, 128, 128, 128), 0.2), ((64, 64, 64, 64), 0.4), ((40, 24, 40, 40), None),
+                                         ((70, 30, 70, 70), None)])
+def test_few_candidate_plans_equal_the_unsplit_kernels(ctx, shape, pixel, monkeypatch):
+    # few candidates: the projection splits each ray over 8 lanes and the column-group gather splits its
+    # angles over workgroups (a second pass adds the 8-angle blocks in order); both reproduce the
+    # one-thread-per-ray projection and the unsplit gather bit for bit, in every entry point
+    g, og = geom_pair(*shape, pixel=pixel)
+    S, _ = make_slice(og, seed=51)
+    th = cands(52, 2)
+    th[1] = f32(th[1] + np.array([0.3, 0.2, -0.2, 0.1, 0.1, -0.1, 0.01, -0.02]))
+    runs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BOAC_FWD_SPLIT", flag)
+        monkeypatch.setenv("BOAC_GATHER_SPLIT", flag)
+        J, F, _ = ctx.objective(g, dev(S), dev(th), DR, 7, want_image=True)
+        J1, F1, _ = ctx.objective(g, dev(S), dev(th[1:]), DR, 7, want_image=True)
+        mu = ctx.rasterize_mu(g, dev(th), DR)
+        y = ctx.project(g, mu, F)
+        x = ctx.backproject(g, mu, y)
+        Jg, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 3, 2, mode="unrolled")
+        runs[flag] = [t.cpu().numpy() for t in (J, F, J1, F1, y, x, Jg, G)]
+    for name, a, b in zip(("J", "F^K", "J C=1", "F^K C=1", "A f", "A^T y", "J grad", "dJ"), runs["1"], runs["0"]):
+        report(f"few-candidate plans {shape} {name}", a, b, 1e-6)
+        assert np.array_equal(a, b), name
+    # one candidate at a time equals the batch of two
+    assert np.array_equal(runs["1"][2][0], runs["1"][0][1]) and np.array_equal(runs["1"][3][0], runs["1"][1][1])
+    Jr, Fr, _ = oracle.evaluate(og, S, th[1], DR, 7)
+    report(f"few-candidate plans {shape} J vs oracle", runs["1"][2], np.array([Jr]), TOL)
+    report(f"few-candidate plans {shape} F^K vs oracle", runs["1"][3][0], Fr, TOL)
+
+
+@pytest.mark.parametrize("shape,pixel", [((128, 128, 128, 128), 0.2), ((40, 24, 40, 40), None), ((36, 16, 36, 50), None),
+                                         ((96, 64, 96, 96), None)])
+def test_lane_parallel_attenuation_scan(ctx, shape, pixel, monkeypatch):
+    # the attenuation scan spread over 8 lanes per ray against the one-thread-per-ray scan (same samples,
+    # another compensated summation order) and against the oracle, through the projector
+    g, og = geom_pair(*shape, pixel=pixel)
+    th = cands(53, 3)
+    mus = f32(np.stack([oracle.rasterize_mu(og, th[c], DR) for c in range(3)]))
+    imgs = f32(np.random.default_rng(54).uniform(0.0, 2.0, (3, og.n, og.n)))
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BOAC_ATT_SCAN", flag)
+        out[flag] = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    report(f"att scan lanes vs thread {shape}", out["1"], out["0"], 2e-6)
+    for c in range(3):
+        ref = oracle.project(og, oracle.attenuation(og, mus[c]), imgs[c])
+        report(f"att scan lanes {shape} cand {c} vs oracle", out["1"][c], ref, TOL)
