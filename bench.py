@@ -260,6 +260,60 @@ def uneven_line(ctx, dev):
                     "objective + gradient, checkpoint 5, one graph replay"}
 
 
+def persistent_line(ctx, g, S, cand, K, dev, steps):
+    """The batch schedules side by side: the 256-candidate batch and the 48-slice uneven batch, each as one
+    persistent launch (device work queue, per-lane completion counters) against the stream-lane graph,
+    both timed as graph replays on one stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_11920_amd.api import Geometry, SliceBatch
+    C = cand.shape[0]
+    out = {}
+    stream = torch.cuda.Stream(dev)
+
+    def timed(slices, k, ck, reps):
+        with torch.cuda.stream(stream):
+            ctx.evaluate_batch(slices, DELTA_R, k, ck)   # eager run, then capture
+            ctx.evaluate_batch(slices, DELTA_R, k, ck)   # replay (warm)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ctx.evaluate_batch(slices, DELTA_R, k, ck)
+            e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    sb = [SliceBatch(g, S, cand, torch.empty(C, device=dev), None, torch.empty(C, device=dev, dtype=torch.int32))]
+    du = np.load(os.path.join(ROOT, "tests", "golden", "uneven48.npz"))
+    wu = synth.workload("uneven48")
+    cu = synth.workload_candidates(wu)
+    us = []
+    for s in range(int(du["n_slices"])):
+        n, na, nb, nt = (int(v) for v in du[f"s{s:02d}_geometry"])
+        gs = Geometry(n, na, nb, nt, float(du[f"s{s:02d}_pixel"]))
+        us.append(SliceBatch.make(gs, torch.as_tensor(du[f"s{s:02d}_meas"].astype(np.float32), device=dev),
+                                  torch.as_tensor(cu[s].astype(np.float32), device=dev), with_grad=True))
+    for mode in ("lanes", "persistent"):
+        ctx.set_batch_mode(mode)
+        b_ms = timed(sb, K, 5, steps)
+        J = sb[0].obj.clone()
+        u_ms = timed(us, wu.n_iter, wu.ckpt_every, 1)
+        out[mode] = {"batch256_ms_per_step": round(b_ms, 3), "batch256_cand_it_per_s": round(C * K / (b_ms / 1e3), 1),
+                     "uneven48_ms_per_batch": round(u_ms, 2),
+                     "uneven48_obj_grad_evals_per_s": round(sum(x.cand.shape[0] for x in us) / (u_ms / 1e3), 1)}
+        out[mode]["_J"] = J
+    ctx.set_batch_mode("lanes")
+    d = out["persistent"].pop("_J") - out["lanes"].pop("_J")
+    out["batch256_J_max_abs_diff"] = float(d.abs().max())
+    out["what"] = ("graph replays on one stream: batch256_n128 (256 candidates, 30 iterations + objective) and "
+                   "uneven48 (objective + gradient); persistent = one launch of one 1024-thread workgroup per CU "
+                   "taking tasks from a device queue; lanes = concurrent stream lanes")
+    return out
+
+
 def bo_line(ctx, g, S, truth):
     """The BOAC outer loop on the 128^2 slice: 64 initial candidates, then cycles of 64 proposals (EI by
     chaotic search; with the envelope gradient, part of each batch is a line search along -grad J),
@@ -389,6 +443,7 @@ def main():
     ap.add_argument("--only-grad", action="store_true", help="the gradient lines only (for profiler runs)")
     ap.add_argument("--only-gp", action="store_true", help="the acquisition-kernel line only (for profiler runs)")
     ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
+    ap.add_argument("--only-schedules", action="store_true", help="the batch-schedule comparison only")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
     args = ap.parse_args()
@@ -419,6 +474,11 @@ def main():
     C, K = cand.shape[0], w.n_iter
     ctx = Context(0)
     stream = torch.cuda.current_stream(dev)
+    if args.only_schedules:
+        print(json.dumps({"batch_schedules": persistent_line(ctx, g, S, cand, K, dev, max(3, args.steps // 2))}),
+              flush=True)
+        ctx.close()
+        return
     if args.only_uneven or args.only_gp or args.only_grad:
         out = {}
         if args.only_uneven:
@@ -542,6 +602,7 @@ def main():
 
     if not args.only_main and not args.no_uneven:
         out["uneven48"] = uneven_line(ctx, dev)
+        out["batch_schedules"] = persistent_line(ctx, g, S, cand, K, dev, max(3, args.steps // 2))
 
     if not args.only_main and not args.no_bo:
         out["bo"] = bo_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64))

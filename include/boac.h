@@ -58,7 +58,7 @@ typedef enum {
     BOAC_ESHAPE = 2,   /* geometry out of the supported range */
     BOAC_ENOMEM = 3,   /* device scratch allocation failed */
     BOAC_EDEVICE = 4,  /* a HIP call failed (message in boac_last_error) */
-    BOAC_ETIMEOUT = 5, /* reserved: bounded device wait expired */
+    BOAC_ETIMEOUT = 5, /* a bounded device wait expired (persistent batch execution) */
     BOAC_ENOTSUP = 6   /* device is not gfx950 / feature not built */
 } boac_status;
 
@@ -191,6 +191,21 @@ typedef struct {
  * gradient use ckpt_every as in boac_objective_grad. */
 boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
                                 int32_t n_iter, int32_t ckpt_every, void *stream);
+
+/* Execution of boac_evaluate_batch (BOAC step 3 for many candidate sets at once).
+ * BOAC_BATCH_LANES (the default): the slices run on concurrent stream lanes and the launch sequence is
+ *   captured into a HIP graph per batch shape.
+ * BOAC_BATCH_PERSISTENT: the batch's launches are recorded as tasks and run by ONE persistent launch of
+ *   one 1024-thread workgroup per CU that takes work items from a queue in device memory; each task waits
+ *   for its predecessor on the same lane through completion counters (release / acquire at device scope).
+ *   A wait is bounded: after spin_limit polls (spin_limit <= 0: 2^26) the executor stops every workgroup
+ *   and the call returns BOAC_ETIMEOUT with incomplete results. In this mode boac_evaluate_batch waits for
+ *   the launch before returning. Batches whose plans the executor cannot run (a backprojection outside the
+ *   column-group gather, more than four candidates per gather workgroup) return BOAC_ENOTSUP.
+ * The mode stays set on the context. */
+#define BOAC_BATCH_LANES 0
+#define BOAC_BATCH_PERSISTENT 1
+boac_status boac_ctx_set_batch_mode(boac_ctx *ctx, int32_t mode, int64_t spin_limit);
 
 /* ---- Surrogate model of the BOAC outer loop (Eqs. 7-10) ----
  * The negative log-likelihood J of a candidate is modelled as a Gaussian process (Eq. 7) over unit-box

@@ -64,6 +64,7 @@ _SIGNATURES = {
     "boac_ctx_kernel_stats": (c_int32, [_P, c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "boac_ctx_reset_stats": (c_int32, [_P]),
+    "boac_ctx_set_batch_mode": (c_int32, [_P, c_int32, ctypes.c_int64]),
     "boac_ctx_graph_stats": (c_int32, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
 }

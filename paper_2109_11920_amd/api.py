@@ -219,6 +219,14 @@ class Context:
         check(self.lib.boac_evaluate_batch(self.handle, arr, len(slices), float(delta_r), int(n_iter),
                                            int(ckpt_every), _stream(self.device)))
 
+    def set_batch_mode(self, mode: str, spin_limit: int = 0):
+        """evaluate_batch execution: "lanes" (stream lanes captured in a graph) or "persistent" (one
+        persistent launch with a device work queue; spin_limit bounds each dependency wait)."""
+        modes = {"lanes": 0, "persistent": 1}
+        if mode not in modes:
+            raise ValueError(f"mode must be one of {sorted(modes)}")
+        check(self.lib.boac_ctx_set_batch_mode(self.handle, modes[mode], int(spin_limit)))
+
     # ---- instrumentation ------------------------------------------------------------------------
     def set_profiling(self, on: bool):
         check(self.lib.boac_ctx_set_profiling(self.handle, 1 if on else 0))

@@ -612,19 +612,24 @@ __device__ __forceinline__ void back_epilogue(const DevGeom &g, const BackArgs &
 // The ray weights reach the staging threads through a small LDS table (one load per bin and
 // candidate, one angle ahead), and the per-angle trigonometry and block origins through scalar loads
 // of host tables (BackCfg::angt, BackCfg::rectf).
+// Body of k_back_col4 for workgroup `bid` of the launch's grid, run by 256 threads (thread index tid)
+// on the LDS region lds. live = false: a stand-in workgroup beyond the grid (the persistent executor
+// runs workgroups four to a 1024-thread group) that takes part in every barrier and loads and writes
+// nothing.
 template <int CG, bool WEIGHTED, bool PAIRED, bool SPLIT>
-__global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
+__device__ __forceinline__ void k_back_col4_body(int bid, int tid, float *lds, bool live, DevGeom g, BackCfg T,
+                                                 BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
     constexpr int PL = kSlidPitch;
     constexpr int V = SlidLayout<CG>::V;
     constexpr int PLANES = SlidLayout<CG>::PLANES;
     constexpr int PLANE = SlidLayout<CG>::PLANE;
-    extern __shared__ float lds[];  // [PLANES][P rows][PL slots][V], then the ray weights wz, we
+    // lds: [PLANES][P rows][PL slots][V], then the ray weights wz, we
     const int ntiles = T.tiles_x * T.tiles_y;
     const int ngroups = (A.C + CG - 1) / CG;
     const int nsplit = SPLIT ? T.asplit : 1;
     const int total = ntiles * ngroups * nsplit;
-    int id = blockIdx.x;
+    int id = bid;
     if (T.xcd_remap && (total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
     const int grp = id / (ntiles * nsplit);
     const int rem = id - grp * (ntiles * nsplit);
@@ -636,14 +641,13 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     const int ty = tile / T.tiles_x, tx = tile - ty * T.tiles_x;
     const int l0 = tx * 16, i0 = ty * 16;
     const int c0 = grp * CG;
-    const int ncg = min(CG, A.C - c0);
-    const int tid = threadIdx.x;
+    const int ncg = live ? min(CG, A.C - c0) : 0;
     const int lane = tid & 63;
 
     // this thread's pixel: each 8 lanes of a wave take a 4 x 2 block, a wave a 16 x 4 band
     const int l = l0 + ((lane >> 3) & 3) * 4 + (lane & 3);
     const int i = i0 + (tid >> 6) * 4 + (lane >> 5) * 2 + ((lane >> 2) & 1);
-    const bool pv = (l < g.n) && (i < g.n);
+    const bool pv = live && (l < g.n) && (i < g.n);
     const float xc = (float)l - g.cN, yc = (float)i - g.cN;
     const float cB5 = g.cB + 0.5f, cT5 = g.cT + 0.5f;
 
@@ -857,6 +861,12 @@ __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArg
     }
 }
 
+template <int CG, bool WEIGHTED, bool PAIRED, bool SPLIT>
+__global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
+    extern __shared__ float lds[];
+    k_back_col4_body<CG, WEIGHTED, PAIRED, SPLIT>(blockIdx.x, threadIdx.x, lds, true, g, T, A, mode);
+}
+
 // Second pass of the angle-split gather: per (candidate, pixel) the 8-angle block sums, added in angle
 // order to a compensated total exactly as the unsplit gather adds them, then the same epilogue.
 __global__ __launch_bounds__(256) void k_back_combine(DevGeom g, BackArgs A, int nblk, int mode) {
@@ -930,6 +940,23 @@ static hipError_t back_tile(const DevGeom &g, const BackCfg &bc, const BackArgs 
 }
 
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        if (bc.slid != 2 || bc.asplit != 1 || !(bc.cg == 1 || bc.cg == 2 || bc.cg == 4) || bc.tw != 16 ||
+            bc.th != 16 || bc.hb != 1)
+            return record_unsupported(r, "backprojection outside the column-group gather (one to four candidates per "
+                                         "workgroup, no angle split)");
+        if (a.E && g.nah * 2 != g.na) return hipErrorInvalidValue;
+        const bool weighted = !(mode == BACK_SENS || mode == BACK_FIELD);
+        TaskRec t{};
+        t.kind = T_BACK_COL4;
+        t.variant = (bc.cg == 1 ? 0 : bc.cg == 2 ? 1 : 2) | (weighted ? 4 : 0) | (a.E ? 8 : 0);
+        t.u.back = {g, bc, a, mode};
+        t.grid = bc.tiles_x * bc.tiles_y * ((a.C + bc.cg - 1) / bc.cg);
+        t.items = (t.grid + 3) / 4;
+        t.sub_lds = (unsigned)((bc.lds + 15) / 16 * 16);
+        t.lds = 4 * t.sub_lds;
+        return record_task(r, t);
+    }
     // opposed-ray pairing exists in the column-group gather only
     if ((a.E || g.nah != g.na) && bc.slid != 2) return hipErrorInvalidValue;
     if (bc.slid == 2) {

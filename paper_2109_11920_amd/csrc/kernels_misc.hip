@@ -40,10 +40,9 @@ __device__ __forceinline__ float coverage_slope(float d, float inv_h) {
     return 6.f * x * (1.f - x) * inv_h;
 }
 
-__global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restrict__ cand, int C, float delta_r,
-                                                float *__restrict__ mu, size_t img_cs, uint32_t *status) {
-    const int cidx = blockIdx.y;
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+// mu of pixel pix of candidate cidx.
+__device__ __forceinline__ void raster_at(const DevGeom &g, const float *__restrict__ cand, float delta_r,
+                                          float *__restrict__ mu, size_t img_cs, uint32_t *status, int cidx, int pix) {
     if (pix >= g.n * g.n) return;
     const int i = pix / g.n, l = pix - i * g.n;
     const float *th = cand + (size_t)cidx * 8;
@@ -75,13 +74,17 @@ __global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restri
     if (status && (neg || !finite)) atomicOr(status + cidx, (neg ? 4u : 0u) | (finite ? 0u : 2u));
 }
 
+__global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restrict__ cand, int C, float delta_r,
+                                                float *__restrict__ mu, size_t img_cs, uint32_t *status) {
+    raster_at(g, cand, delta_r, mu, img_cs, status, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // grad_k = sum_j mubar_j dmu_j/dtheta_k for theta = (c_0..c_5, mu_b, mu_c, dR), one workgroup per
 // candidate, compensated per component; written as 9 values per candidate.
-__global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__restrict__ cand, float delta_r,
-                                                    const float *__restrict__ mubar, size_t img_cs,
-                                                    float *__restrict__ grad) {
-    __shared__ float red[16];
-    const int cidx = blockIdx.x;
+// One workgroup (any size up to 1024 threads) per candidate cidx; red: 32 floats of shared memory.
+__device__ __forceinline__ void k_raster_adj_body(int cidx, float *red, DevGeom g, const float *__restrict__ cand,
+                                                  float delta_r, const float *__restrict__ mubar, size_t img_cs,
+                                                  float *__restrict__ grad) {
     const float *th = cand + (size_t)cidx * 8;
     const float mub = th[6], muc = th[7];
     const float inv_h = 4.f / g.dx;
@@ -126,6 +129,13 @@ __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__re
     }
 }
 
+__global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__restrict__ cand, float delta_r,
+                                                    const float *__restrict__ mubar, size_t img_cs,
+                                                    float *__restrict__ grad) {
+    __shared__ float red[32];
+    k_raster_adj_body(blockIdx.x, red, g, cand, delta_r, mubar, img_cs, grad);
+}
+
 __global__ void k_fill(float *p, size_t count, float v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -144,19 +154,23 @@ __global__ void k_copy(const float *src, float *dst, size_t count) {
         dst[i] = src[i];
 }
 
-// Adjoint of the objective terms y - S ln y at y = y^K.
+// Adjoint of the objective terms y - S ln y at y = y^K (element t of C x nrays).
+__device__ __forceinline__ void ybar_final_at(const float *meas, const float *yK, float *ybar, int nrays,
+                                              size_t sino_cs, size_t t) {
+    const size_t c = t / nrays, i = t - c * nrays;
+    const float y = yK[c * sino_cs + i], S = meas[i];
+    ybar[c * sino_cs + i] = (y > 0.f) ? 1.f - S / y : (S == 0.f ? 1.f : 0.f);
+}
 __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs) {
     const size_t total = (size_t)C * nrays;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = t / nrays, i = t - c * nrays;
-        const float y = yK[c * sino_cs + i], S = meas[i];
-        ybar[c * sino_cs + i] = (y > 0.f) ? 1.f - S / y : (S == 0.f ? 1.f : 0.f);
-    }
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
+        ybar_final_at(meas, yK, ybar, nrays, sino_cs, t);
 }
 
-// sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup.
-__global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
-    __shared__ float red[16];
+// sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup (up to 1024
+// threads); red: 32 floats of shared memory.
+__device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas, int count, float2 *out,
+                                                  uint32_t *flag) {
     Comp c{0.f, 0.f};
     bool neg = false;
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
@@ -171,10 +185,14 @@ __global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count
     if (neg) atomicOr(flag, 8u);
 }
 
+__global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
+    __shared__ float red[32];
+    k_lgamma_sum_body(red, meas, count, out, flag);
+}
+
 // J[c] = sum of the per-workgroup NLL partials + the ln Gamma constant; status bits.
-__global__ void k_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
-                             float *obj, uint32_t *status) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void nll_finish_at(const float2 *partial, int chunks, int C, const float2 *lg,
+                                              const uint32_t *meas_flag, float *obj, uint32_t *status, int c) {
     if (c >= C) return;
     Comp acc{lg->x, lg->y};
     for (int j = 0; j < chunks; ++j) {
@@ -190,11 +208,15 @@ __global__ void k_nll_finish(const float2 *partial, int chunks, int C, const flo
     }
 }
 
+__global__ void k_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
+                             float *obj, uint32_t *status) {
+    nll_finish_at(partial, chunks, C, lg, meas_flag, obj, status, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Reverse of F^{n+1} = F^n Q^n (Q^n = b^n / s):
 //   bbar = Fbar F^n / s,  sbar -= Fbar F^{n+1} / s,  Fbar_direct = Fbar Q^n      (0 where s <= 0)
-__global__ void k_adj_elem(AdjElemArgs A) {
-    const size_t total = (size_t)A.npix * A.C;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void adj_elem_at(const AdjElemArgs &A, size_t t) {
+    {
         const size_t c = t / A.npix, j = t - c * A.npix;
         const size_t o = c * A.img_cs + j;
         const float fb = A.fbar[o], F = A.F[o], Q = A.Q[o], sv = A.s[o];
@@ -209,6 +231,12 @@ __global__ void k_adj_elem(AdjElemArgs A) {
     }
 }
 
+__global__ void k_adj_elem(AdjElemArgs A) {
+    const size_t total = (size_t)A.npix * A.C;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
+        adj_elem_at(A, t);
+}
+
 // (a, b) pairs; a NULL image stands for its constant
 __global__ void k_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -217,8 +245,8 @@ __global__ void k_pack_pair(const float *a, float a_const, const float *b, float
 
 // Copies the first ncomp of the kGradComps raster-adjoint components per candidate; status bit 2 if
 // any copied value is not finite.
-__global__ void k_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void grad_finish_at(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status,
+                                               int c) {
     if (c >= C) return;
     bool bad = false;
     for (int k = 0; k < ncomp; ++k) {
@@ -227,6 +255,10 @@ __global__ void k_grad_finish(const float *grad, int C, int ncomp, float *d_grad
         d_grad[(size_t)c * ncomp + k] = v;
     }
     if (bad && status) status[c] |= 2u;
+}
+
+__global__ void k_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status) {
+    grad_finish_at(grad, C, ncomp, d_grad, status, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -239,6 +271,14 @@ static unsigned fill_blocks(size_t count) {
 
 hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta_r, float *mu, size_t img_cs,
                          uint32_t *status, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_RASTER;
+        t.u.raster = {g, cand, delta_r, mu, img_cs, status, (g.n * g.n + 255) / 256};
+        t.grid = t.u.raster.nbx * C;
+        t.items = (t.grid + 3) / 4;
+        return record_task(r, t);
+    }
     for (int c0 = 0; c0 < C; c0 += 65535) {
         const int n = C - c0 < 65535 ? C - c0 : 65535;
         const dim3 grid((unsigned)((g.n * g.n + 255) / 256), (unsigned)n);
@@ -249,51 +289,142 @@ hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta
 }
 hipError_t launch_raster_adj(const DevGeom &g, const float *cand, int C, float delta_r, const float *mubar,
                              size_t img_cs, float *grad, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_RASTER_ADJ;
+        t.u.raster_adj = {g, cand, delta_r, mubar, img_cs, grad};
+        t.grid = t.items = C;
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_raster_adj, dim3((unsigned)C), dim3(256), 0, st, g, cand, delta_r, mubar, img_cs, grad);
     return hipGetLastError();
 }
 hipError_t launch_fill(float *p, size_t count, float v, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_FILL;
+        t.u.elem.out = p;
+        t.u.elem.fa = v;
+        t.u.elem.count = count;
+        t.grid = t.items = (int)((t.u.elem.count + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_fill, dim3(fill_blocks(count)), dim3(256), 0, st, p, count, v);
     return hipGetLastError();
 }
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_FILL_U32;
+        t.u.elem.out = p;
+        t.u.elem.u = v;
+        t.u.elem.count = count;
+        t.grid = t.items = (int)((t.u.elem.count + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(count)), dim3(256), 0, st, p, count, v);
     return hipGetLastError();
 }
 hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_MUL_COPY;
+        t.u.elem.out = out;
+        t.u.elem.a = a;
+        t.u.elem.b = b;
+        t.u.elem.count = count;
+        t.grid = t.items = (int)((t.u.elem.count + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_mul_copy, dim3(fill_blocks(count)), dim3(256), 0, st, a, b, out, count);
     return hipGetLastError();
 }
 hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_COPY;
+        t.u.elem.out = dst;
+        t.u.elem.a = src;
+        t.u.elem.count = count;
+        t.grid = t.items = (int)((t.u.elem.count + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_copy, dim3(fill_blocks(count)), dim3(256), 0, st, src, dst, count);
     return hipGetLastError();
 }
 hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
                              hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_YBAR;
+        t.u.ybar = {meas, yK, ybar, C, nrays, sino_cs};
+        t.grid = t.items = (int)(((size_t)C * nrays + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_ybar_final, dim3(fill_blocks((size_t)C * nrays)), dim3(256), 0, st, meas, yK, ybar, C, nrays,
                        sino_cs);
     return hipGetLastError();
 }
 hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_LGAMMA;
+        t.u.lgamma = {meas, count, out, flag};
+        t.grid = t.items = 1;
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_lgamma_sum, dim3(1), dim3(256), 0, st, meas, count, out, flag);
     return hipGetLastError();
 }
 hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
                              float *obj, uint32_t *status, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_NLL_FINISH;
+        t.u.nll = {partial, chunks, C, lg, meas_flag, obj, status};
+        t.grid = t.items = (C + kPersistThreads - 1) / kPersistThreads;
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_nll_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, partial, chunks, C, lg,
                        meas_flag, obj, status);
     return hipGetLastError();
 }
 hipError_t launch_adj_elem(const AdjElemArgs &a, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_ADJ_ELEM;
+        t.u.adj = a;
+        t.grid = t.items = (int)(((size_t)a.npix * a.C + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_adj_elem, dim3(fill_blocks((size_t)a.npix * a.C)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count,
                             hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_PACK_PAIR;
+        t.u.elem.out = out;
+        t.u.elem.a = a;
+        t.u.elem.b = b;
+        t.u.elem.fa = a_const;
+        t.u.elem.fb = b_const;
+        t.u.elem.count = count;
+        t.grid = t.items = (int)((t.u.elem.count + kPersistElems - 1) / kPersistElems);
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_pack_pair, dim3(fill_blocks(count)), dim3(256), 0, st, a, a_const, b, b_const, out, count);
     return hipGetLastError();
 }
 hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        t.kind = T_GRAD_FINISH;
+        t.u.gfin = {grad, C, ncomp, d_grad, status};
+        t.grid = t.items = (C + kPersistThreads - 1) / kPersistThreads;
+        return record_task(r, t);
+    }
     hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((C + 63) / 64)), dim3(64), 0, st, grad, C, ncomp, d_grad,
                        status);
     return hipGetLastError();

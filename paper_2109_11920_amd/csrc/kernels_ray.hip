@@ -21,9 +21,9 @@ namespace boac {
 
 // Map a flat workgroup id to (candidate, chunk) so that all chunks of one candidate run on the same
 // XCD (workgroups are dispatched round-robin over the 8 XCDs); they share the candidate's image in L2.
-__device__ __forceinline__ void ray_block(int chunks, int C, int &cand, int &chunk) {
+__device__ __forceinline__ void ray_block(int bid, int chunks, int C, int &cand, int &chunk) {
     const int total = chunks * C;
-    int id = blockIdx.x;
+    int id = bid;
     if ((total & 7) == 0) id = (id & 7) * (total >> 3) + (id >> 3);
     cand = id / chunks;
     chunk = id - cand * chunks;
@@ -34,12 +34,11 @@ constexpr int kBandChunk = 16;  // samples per load batch in the row-band paths
 
 // ------------------------------------------------------------------ attenuation
 template <bool SINGLE>
-__global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
+__device__ __forceinline__ void k_att_body(int bid, float *lds, DevGeom g, const Bands &bands, int rpt, int chunks, int C,
                                              const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
                                              size_t att_cs, float *__restrict__ E, size_t e_cs) {
-    extern __shared__ float lds[];
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(bid, chunks, C, cand, chunk);
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
@@ -158,6 +157,14 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
     }
 }
 
+template <bool SINGLE>
+__global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
+                                             const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
+                                             size_t att_cs, float *__restrict__ E, size_t e_cs) {
+    extern __shared__ float lds[];
+    k_att_body<SINGLE>(blockIdx.x, lds, g, bands, rpt, chunks, C, mu, att, img_cs, att_cs, E, e_cs);
+}
+
 // Attenuation build with each ray's scan spread over kScanLanes lanes of one wave (single-stage images).
 // The ray is walked from the detector end in rounds of kScanLanes 4-sample groups, lane j taking the
 // j-th group of the round counted from the detector: each lane samples its 4 values m_k = (W mu)_k from
@@ -171,13 +178,12 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
 // so that one image stage serves many rays.
 constexpr int kScanLanes = 8;
 
-__global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int passes, int chunks, int C,
+__device__ __forceinline__ void k_att_scan_body(int bid, float *lds, DevGeom g, Band band, int passes, int chunks, int C,
                                                   const float *__restrict__ mu, float *__restrict__ att,
                                                   size_t img_cs, size_t att_cs, float *__restrict__ E,
                                                   size_t e_cs) {
-    extern __shared__ float lds[];
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(bid, chunks, C, cand, chunk);
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
     stage_whole(mu + cand * img_cs, g.n, band, lds);
@@ -246,6 +252,14 @@ __global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int pas
     }
 }
 
+__global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int passes, int chunks, int C,
+                                                  const float *__restrict__ mu, float *__restrict__ att,
+                                                  size_t img_cs, size_t att_cs, float *__restrict__ E,
+                                                  size_t e_cs) {
+    extern __shared__ float lds[];
+    k_att_scan_body(blockIdx.x, lds, g, band, passes, chunks, C, mu, att, img_cs, att_cs, E, e_cs);
+}
+
 // ------------------------------------------------------------------ forward projection
 // The epilogue of one ray: y, or the MLEM ratio, or (returned) the NLL term; zero_proj is set where
 // S > 0 meets y <= 0.
@@ -288,11 +302,9 @@ __device__ __forceinline__ float opposed_att(float e_ray, float at) { return e_r
 // PAIRED (opposed-ray pairing, single stage only): each thread's ray (a, b), a < na/2, also gives the
 // projection of ray (a + na/2, nb-1-b) from the same samples and bilinear values.
 template <int MODE, bool SINGLE, bool PAIRED>
-__global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
-    extern __shared__ float lds[];
-    __shared__ float red[32];  // two floats per wave, up to 16 waves
+__device__ __forceinline__ void k_fwd_body(int bid, float *lds, float *red, DevGeom g, const Bands &bands, int rpt, int chunks, int C, FwdArgs A) {
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(bid, chunks, C, cand, chunk);
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
@@ -432,18 +444,23 @@ __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, i
     }
 }
 
+template <int MODE, bool SINGLE, bool PAIRED>
+__global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+    extern __shared__ float lds[];
+    __shared__ float red[32];  // two floats per wave, up to 16 waves
+    k_fwd_body<MODE, SINGLE, PAIRED>(blockIdx.x, lds, red, g, bands, rpt, chunks, C, A);
+}
+
 // Forward projection of two candidates per workgroup, both images staged at once (interleaved as
 // float2): each sample's position, clamp, tap index and bilinear fractions are computed once and
 // serve both candidates (one pair lerp, two FMAs), about half the vector work per candidate-sample of
 // k_fwd. Single-stage images only (the pair stage is twice the size). An odd batch's last pair
 // repeats its candidate and writes it once. PAIRED: opposed-ray pairing as in k_fwd.
 template <int MODE, bool PAIRED>
-__global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
-    extern __shared__ float lds[];
-    __shared__ float red[32];  // two floats per wave, up to 16 waves
+__device__ __forceinline__ void k_fwd_pair_body(int bid, float *lds, float *red, DevGeom g, const Bands &bands, int rpt, int chunks, int C, FwdArgs A) {
     const int npairs = (C + 1) >> 1;
     int pr, chunk;
-    ray_block(chunks, npairs, pr, chunk);
+    ray_block(bid, chunks, npairs, pr, chunk);
     const int c0 = 2 * pr;
     const bool two = (c0 + 1 < C);
     const int c1 = two ? c0 + 1 : c0;
@@ -556,6 +573,13 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
     }
 }
 
+template <int MODE, bool PAIRED>
+__global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
+    extern __shared__ float lds[];
+    __shared__ float red[32];  // two floats per wave, up to 16 waves
+    k_fwd_pair_body<MODE, PAIRED>(blockIdx.x, lds, red, g, bands, rpt, chunks, C, A);
+}
+
 // ------------------------------------------------------------------ fused reverse sweep
 // One reverse MLEM step n, per ray i (pair image = (bbar^n, F^{n+1}) staged in LDS):
 //   rbar_i   = dx sum_k att_ik (W bbar^n)_ik                          (adjoint of b^n = A^T r^n)
@@ -568,10 +592,9 @@ __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int r
 // way, and its attenuation adjoint c' = dx [ r^n_i' W bbar + ybar^{n+1}_i' W F^{n+1} ] reaches the
 // held tensors through att' = E / att: att_bar += -att' c' / att, E_bar += c' / att.
 template <bool SINGLE, bool PAIRED>
-__global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g, const Bands &bands, int rpt, int chunks, int C, SweepArgs A) {
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(bid, chunks, C, cand, chunk);
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
@@ -774,6 +797,12 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
     }
 }
 
+template <bool SINGLE, bool PAIRED>
+__global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
+    extern __shared__ float lds[];
+    k_adj_sweep_body<SINGLE, PAIRED>(blockIdx.x, lds, g, bands, rpt, chunks, C, A);
+}
+
 // ------------------------------------------------------------------ tail of the attenuation adjoint
 // att_bar (+)= dx (W G1 + rho_i W G2) with the pair image (G1, G2) = (s_bar, F^0) and rho = ybar^0
 // (the sensitivity adjoint and the last pending projection adjoint); then
@@ -784,10 +813,9 @@ __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int 
 // since T = dx sum_k m_k every sample's m_bar gains dx Tbar, written per ray in place of E_bar (the
 // field gather adds it).
 template <bool SINGLE, bool PAIRED>
-__global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, const Bands &bands, int rpt, int chunks, int C, TailArgs A) {
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(bid, chunks, C, cand, chunk);
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
@@ -993,6 +1021,12 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
     }
 }
 
+template <bool SINGLE, bool PAIRED>
+__global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
+    extern __shared__ float lds[];
+    k_tail_body<SINGLE, PAIRED>(blockIdx.x, lds, g, bands, rpt, chunks, C, A);
+}
+
 // Forward projection for few candidates (a grid of one-thread-per-ray workgroups would leave most of the
 // GPU idle): each ray is split over kSplitLanes lanes of one wave, lane j taking the 16-sample chunks j,
 // j + kSplitLanes, ... of the ray. A chunk is summed exactly as in k_fwd's single-stage path (same
@@ -1008,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(DevGeom g, Band band, int chu
     static_assert(MODE != FWD_NLL, "the likelihood epilogue runs in k_fwd");
     extern __shared__ float lds[];
     int cand, chunk;
-    ray_block(chunks, C, cand, chunk);
+    ray_block(blockIdx.x, chunks, C, cand, chunk);
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
@@ -1078,6 +1112,19 @@ static dim3 ray_grid(const RayCfg &rc, int C) { return dim3((unsigned)(rc.chunks
 
 hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, const float *mu, float *att,
                       size_t img_cs, size_t att_cs, float *E, size_t e_cs, int C, hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        TaskRec t{};
+        const bool scan = rc.single && rc.scan_passes > 0;
+        if ((scan ? rc.scan_block : rc.block) != kPersistThreads)
+            return record_unsupported(r, "attenuation build planned with other than 1024 threads");
+        t.kind = scan ? T_ATT_SCAN : T_ATT;
+        t.variant = rc.single ? 1 : 0;
+        t.u.att = {RayTask{g, bands, rc.rpt, scan ? rc.scan_chunks : rc.chunks, C}, mu, att, img_cs, att_cs, E, e_cs,
+                   rc.scan_passes};
+        t.grid = t.items = (scan ? rc.scan_chunks : rc.chunks) * C;
+        t.lds = (unsigned)rc.lds;
+        return record_task(r, t);
+    }
     if (rc.single && rc.scan_passes > 0) {
         if (rc.scan_block % 64 != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_att_scan, dim3((unsigned)(rc.scan_chunks * C)), dim3(rc.scan_block), rc.lds, st, g,
@@ -1116,6 +1163,18 @@ static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, con
 
 hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands &bands, const FwdArgs &a, int C,
                       hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        if (rc.block != kPersistThreads) return record_unsupported(r, "projection planned with other than 1024 threads");
+        if (mode != FWD_NLL && rc.split_chunks > 0) return record_unsupported(r, "ray-split projection");
+        TaskRec t{};
+        const bool pair = rc.pair && rc.single && a.img_comps == 1 && C >= 2;
+        t.kind = pair ? T_FWD_PAIR : T_FWD;
+        t.variant = mode | (rc.single ? 4 : 0) | (a.E ? 8 : 0);
+        t.u.fwd = {RayTask{g, bands, rc.rpt, rc.chunks, C}, a};
+        t.grid = t.items = rc.chunks * (pair ? (C + 1) / 2 : C);
+        t.lds = (unsigned)(pair ? 2 * rc.lds : rc.lds);
+        return record_task(r, t);
+    }
     const bool paired = a.E != nullptr;
     if (paired && g.nah * 2 != g.na) return hipErrorInvalidValue;
     switch (mode) {
@@ -1132,6 +1191,16 @@ hipError_t launch_fwd(int mode, const DevGeom &g, const RayCfg &rc, const Bands 
 
 hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &bands, const SweepArgs &a, int C,
                             hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        if (rc.block != kPersistThreads) return record_unsupported(r, "reverse sweep planned with other than 1024 threads");
+        TaskRec t{};
+        t.kind = T_SWEEP;
+        t.variant = (rc.single ? 1 : 0) | (a.E ? 2 : 0);
+        t.u.sweep = {RayTask{g, bands, rc.rpt, rc.chunks, C}, a};
+        t.grid = t.items = rc.chunks * C;
+        t.lds = (unsigned)rc.lds;
+        return record_task(r, t);
+    }
     const bool paired = a.E != nullptr;
     if (paired != (g.nah != g.na) || (paired && (g.nah * 2 != g.na || !a.Ebar))) return hipErrorInvalidValue;
     if (paired && rc.single)
@@ -1151,6 +1220,16 @@ hipError_t launch_adj_sweep(const DevGeom &g, const RayCfg &rc, const Bands &ban
 
 hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, const TailArgs &a, int C,
                        hipStream_t st) {
+    if (TaskRecorder *r = task_recorder()) {
+        if (rc.block != kPersistThreads) return record_unsupported(r, "adjoint tail planned with other than 1024 threads");
+        TaskRec t{};
+        t.kind = T_TAIL;
+        t.variant = (rc.single ? 1 : 0) | (a.E ? 2 : 0);
+        t.u.tail = {RayTask{g, bands, rc.rpt, rc.chunks, C}, a};
+        t.grid = t.items = rc.chunks * C;
+        t.lds = (unsigned)rc.lds;
+        return record_task(r, t);
+    }
     const bool paired = a.E != nullptr;
     if (paired != (g.nah != g.na) || (paired && (g.nah * 2 != g.na || !a.Ebar))) return hipErrorInvalidValue;
     if (paired && rc.single)

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "device_common.h"
 
 namespace boac {
@@ -149,6 +151,75 @@ struct GpEiArgs {
 
 // Raster-adjoint components per candidate: c_0..c_5, mu_b, mu_c, dR.
 constexpr int kGradComps = 9;
+
+// ---- persistent execution of a recorded launch sequence (kernels_persist.hip) ----
+// While a TaskRecorder is installed on the calling thread, every launcher below records its launch as a
+// task instead of launching it. The persistent executor then runs the tasks in one launch: workgroups
+// of kPersistThreads threads take work items from a queue in device memory, each task waiting for its
+// predecessor on the same lane (the order a stream would give). Ray-kernel tasks run a recorded
+// 1024-thread workgroup per item; 256-thread tasks run four recorded workgroups per item.
+constexpr int kPersistThreads = 1024;
+constexpr int kPersistElems = 16384;  // elements per item of an elementwise task
+
+enum TaskKind : int {
+    T_RASTER = 0, T_RASTER_ADJ, T_ATT, T_ATT_SCAN, T_FWD, T_FWD_PAIR, T_SWEEP, T_TAIL, T_BACK_COL4,
+    T_FILL, T_FILL_U32, T_MUL_COPY, T_COPY, T_YBAR, T_LGAMMA, T_NLL_FINISH, T_ADJ_ELEM, T_PACK_PAIR,
+    T_GRAD_FINISH, T_KINDS
+};
+
+struct RayTask {
+    DevGeom g;
+    Bands bands;
+    int rpt, chunks, C;
+};
+
+struct TaskRec {
+    int kind;
+    int variant;       // template switches of the recorded kernel (see kernels_persist.hip)
+    int grid;          // workgroups of the recorded launch
+    int items;         // work items of the persistent executor
+    int dep;           // task whose completion this one waits for (-1: none)
+    int lane;          // lane of the recorded sequence
+    unsigned lds;      // dynamic LDS bytes of one item (all of its recorded workgroups)
+    unsigned sub_lds;  // 256-thread tasks: dynamic LDS bytes of one recorded workgroup
+    union {
+        struct { DevGeom g; const float *cand; float delta_r; float *mu; size_t img_cs; uint32_t *status; int nbx; } raster;
+        struct { DevGeom g; const float *cand; float delta_r; const float *mubar; size_t img_cs; float *grad; } raster_adj;
+        struct { RayTask r; const float *mu; float *att; size_t img_cs, att_cs; float *E; size_t e_cs; int passes; } att;
+        struct { RayTask r; FwdArgs A; } fwd;
+        struct { RayTask r; SweepArgs A; } sweep;
+        struct { RayTask r; TailArgs A; } tail;
+        struct { DevGeom g; BackCfg T; BackArgs A; int mode; } back;
+        struct { void *out; const void *a; const void *b; size_t count; float fa, fb; uint32_t u; } elem;
+        struct { const float *meas; const float *yK; float *ybar; int C, nrays; size_t sino_cs; } ybar;
+        struct { const float *meas; int count; float2 *out; uint32_t *flag; } lgamma;
+        struct { const float2 *partial; int chunks, C; const float2 *lg; const uint32_t *flag; float *obj; uint32_t *status; } nll;
+        AdjElemArgs adj;
+        struct { const float *grad; int C, ncomp; float *d_grad; uint32_t *status; } gfin;
+    } u;
+};
+
+struct TaskRecorder {
+    std::vector<TaskRec> tasks;
+    int lane = 0;
+    bool unsupported = false;  // a launch the executor cannot run was requested
+    const char *why = "";
+};
+// The calling thread's recorder (null: launchers launch).
+TaskRecorder *&task_recorder();
+// Records t (dep and lane are set by the recorder's owner); always hipSuccess.
+hipError_t record_task(TaskRecorder *r, const TaskRec &t);
+hipError_t record_unsupported(TaskRecorder *r, const char *why);
+
+struct PersistArgs {
+    const TaskRec *tasks;
+    int ntasks;
+    int *state;            // [8 + 9 ntasks]: queue head, error, abort, ...; per-XCD claims [8 ntasks]; done [ntasks]
+    long long spin_limit;  // polls of an unfinished dependency before the executor gives up (error 1)
+};
+// Zeroes the queue state and runs the recorded tasks in one persistent launch of `workgroups`
+// workgroups with `lds` bytes of dynamic LDS each.
+hipError_t launch_persist(const PersistArgs &a, int workgroups, unsigned lds, hipStream_t st);
 
 // ---- launchers (each returns the hipError_t of the launch) ----
 hipError_t launch_raster(const DevGeom &g, const float *cand, int C, float delta_r, float *mu, size_t img_cs,

@@ -151,6 +151,7 @@ struct GraphEntry {
     std::vector<uint64_t> key;
     hipGraphExec_t exec = nullptr;
     uint64_t scratch_gen = 0;  // scratch generation the graph's kernels were captured against
+    void *aux = nullptr;       // persistent batches: the executor's state (error word at index 1)
 };
 
 struct boac_ctx {
@@ -178,6 +179,11 @@ struct boac_ctx {
     hipStream_t arena_stream = nullptr;
     std::map<std::vector<int>, std::vector<int4>> host_rects;   // host copies uploaded into an arena
     std::map<int, std::vector<float2>> host_trig;
+    // batch execution: 0 = concurrent stream lanes captured in a graph, 1 = one persistent launch
+    int batch_mode = 0;
+    long long spin_limit = 0;
+    bool persist_plans = false;        // plans for the persistent executor (1024-thread ray workgroups)
+    bool recording = false;            // launches are being recorded as tasks
     std::vector<hipStream_t> lanes;    // concurrent streams of the batch scheduler
     std::vector<hipEvent_t> lane_done;
     hipEvent_t fork = nullptr;
@@ -528,6 +534,25 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
         rc->scan_passes = (int)std::min<long>(32, std::max<long>(1, total * C / (2L * ctx->n_cu)));
         rc->scan_chunks = (int)((total + rc->scan_passes - 1) / rc->scan_passes);
     }
+    if (ctx->persist_plans) {
+        // the persistent executor runs ray kernels as 1024-thread items: the most rays per thread that
+        // still give every CU an item, no ray split
+        rc->block = 1024;
+        rc->rpt = 1;
+        for (int rpt : {4, 2, 1})
+            if ((long)((nrays + 1024 * rpt - 1) / (1024 * rpt)) * C >= ctx->n_cu || rpt == 1) {
+                rc->rpt = rpt;
+                break;
+            }
+        rc->chunks = (nrays + 1024 * rc->rpt - 1) / (1024 * rc->rpt);
+        rc->split_chunks = 0;
+        if (rc->scan_passes > 0) {
+            const long total = (nrays + 127) / 128;
+            rc->scan_block = 1024;
+            rc->scan_passes = (int)std::min<long>(32, std::max<long>(1, total * C / (long)ctx->n_cu));
+            rc->scan_chunks = (int)((total + rc->scan_passes - 1) / rc->scan_passes);
+        }
+    }
 }
 
 static void back_fill(const boac_geom &g, BackCfg *bc) {
@@ -631,8 +656,12 @@ static void back_plan(boac_ctx *ctx, const boac_geom &g, int C, BackCfg *bc, int
     // blocks over more workgroups (a second pass adds the blocks in order) while the grid would not fill
     // the GPU twice over (BOAC_GATHER_SPLIT=0 turns it off)
     bc->asplit = 1;
+    if (ctx->persist_plans && bc->slid == 2 && bc->cg > 4) {
+        bc->cg = 4;  // the persistent executor runs one to four candidates per gather workgroup
+        back_fill(g, bc);
+    }
     const char *eg = std::getenv("BOAC_GATHER_SPLIT");
-    if (bc->slid == 2 && C <= kFewCand && !(eg && eg[0] == '0')) {
+    if (bc->slid == 2 && C <= kFewCand && !ctx->persist_plans && !(eg && eg[0] == '0')) {
         const long wgs = (long)bc->tiles_x * bc->tiles_y * ((C + bc->cg - 1) / bc->cg);
         const int nblk = (nah + 7) / 8;
         if (wgs < 2L * ctx->n_cu)
@@ -662,7 +691,7 @@ static hipEvent_t take_event(boac_ctx *ctx) {
 
 template <typename F>
 static boac_status timed(boac_ctx *ctx, int kind, double bytes, hipStream_t st, F &&launch) {
-    const bool t = ctx->profiling && !ctx->capturing && !ctx->arena;
+    const bool t = ctx->profiling && !ctx->capturing && !ctx->arena && !ctx->recording;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t) {
         e0 = take_event(ctx);
@@ -1654,6 +1683,176 @@ static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_
     return rs;
 }
 
+// ------------------------------------------------------------------ persistent batch execution
+static void drop_stale_graphs(boac_ctx *ctx);
+
+static int persist_lanes() {
+    const char *e = std::getenv("BOAC_PERSIST_LANES");
+    int n = e ? std::atoi(e) : 8;
+    return std::min(std::max(n, 1), 64);
+}
+
+// Splits slices of at least kSplitMinCand candidates into two halves (as the stream lanes do).
+static std::vector<boac_slice> batch_parts(const boac_slice *h_in, int32_t ns_in, bool split) {
+    std::vector<boac_slice> parts;
+    for (int i = 0; i < ns_in; ++i) {
+        const boac_slice &s = h_in[i];
+        if (!split || s.C < kSplitMinCand) {
+            parts.push_back(s);
+            continue;
+        }
+        const int c0 = (s.C / 2) & ~3;  // keeps the second half's pointers 16-byte aligned
+        boac_slice a = s, b = s;
+        a.C = c0;
+        b.C = s.C - c0;
+        b.d_cand = s.d_cand + c0;
+        b.d_obj = s.d_obj + c0;
+        if (s.d_grad) b.d_grad = s.d_grad + (size_t)8 * c0;
+        if (s.d_status) b.d_status = s.d_status + c0;
+        parts.push_back(a);
+        parts.push_back(b);
+    }
+    return parts;
+}
+
+// Longest-first assignment of the parts to L lanes.
+static std::vector<std::vector<int>> assign_lanes(const std::vector<boac_slice> &h, int L, int K, int ck) {
+    std::vector<int> order(h.size());
+    for (size_t i = 0; i < h.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return slice_cost(h[a], K, ck) > slice_cost(h[b], K, ck); });
+    std::vector<double> load(L, 0.0);
+    std::vector<std::vector<int>> assign(L);
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        assign[l].push_back(i);
+        load[l] += slice_cost(h[i], K, ck);
+    }
+    return assign;
+}
+
+// Records the batch as tasks: the parts are assigned to lanes (each with its own scratch namespace),
+// every lane's launches are recorded in order, and the lanes' tasks are interleaved round-robin, each
+// task waiting for its predecessor on its lane. lds: the largest item's dynamic LDS.
+static boac_status persist_record(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_in, float delta_r, int32_t K,
+                                  int32_t ck, std::vector<TaskRec> &out, unsigned &lds) {
+    const std::vector<boac_slice> h = batch_parts(h_in, ns_in, true);
+    const int L = std::min(persist_lanes(), (int)h.size());
+    const auto assign = assign_lanes(h, L, K, ck);
+    TaskRecorder rec;
+    std::vector<std::vector<TaskRec>> lane_tasks(L);
+    task_recorder() = &rec;
+    ctx->recording = true;
+    ctx->persist_plans = true;
+    boac_status rs = BOAC_OK;
+    // two passes: the first sizes every scratch buffer (a buffer that grows is reallocated, which would
+    // leave earlier tasks with freed pointers), the second records against the final buffers
+    for (int pass = 0; pass < 2 && rs == BOAC_OK; ++pass) {
+        const uint64_t gen = ctx->scratch_gen;
+        rec.unsupported = false;
+        for (int l = 0; l < L && rs == BOAC_OK; ++l) {
+            rec.tasks.clear();
+            rec.lane = l;
+            ctx->ns = "P" + std::to_string(l) + ":";
+            for (int i : assign[l]) {
+                rs = eval_slice(ctx, h[i], delta_r, K, ck, nullptr);
+                if (rs != BOAC_OK) break;
+            }
+            lane_tasks[l] = rec.tasks;
+        }
+        if (pass == 1 && rs == BOAC_OK && ctx->scratch_gen != gen)
+            rs = fail(BOAC_EDEVICE, "internal: scratch grew while recording the persistent batch");
+    }
+    ctx->ns.clear();
+    ctx->recording = false;
+    ctx->persist_plans = false;
+    task_recorder() = nullptr;
+    BOAC_TRY(rs);
+    if (rec.unsupported) return fail(BOAC_ENOTSUP, "persistent batch: %s", rec.why);
+    out.clear();
+    lds = 0;
+    std::vector<int> prev(L, -1);
+    for (size_t k = 0;; ++k) {
+        bool any = false;
+        for (int l = 0; l < L; ++l) {
+            if (k >= lane_tasks[l].size()) continue;
+            any = true;
+            TaskRec t = lane_tasks[l][k];
+            t.dep = prev[l];
+            prev[l] = (int)out.size();
+            lds = std::max(lds, t.lds);
+            out.push_back(t);
+        }
+        if (!any) break;
+    }
+    if (lds > kLdsBudget - 1024)
+        return fail(BOAC_ENOTSUP, "persistent batch: an item needs %u bytes of LDS", lds);
+    return BOAC_OK;
+}
+
+// Waits for the persistent launch and reports an expired dependency wait (or an abort).
+static boac_status persist_finish(boac_ctx *ctx, int *state, hipStream_t st) {
+    HIP_TRY(hipStreamSynchronize(st));
+    int err = 0;
+    HIP_TRY(hipMemcpy(&err, state + 1, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) return fail(BOAC_ETIMEOUT, "persistent batch: a dependency wait exceeded %lld polls (or was aborted); "
+                                        "results are incomplete", ctx->spin_limit);
+    return BOAC_OK;
+}
+
+static long long persist_spin_limit(const boac_ctx *ctx) { return ctx->spin_limit > 0 ? ctx->spin_limit : (1ll << 26); }
+
+// One persistent launch for the batch; captured into a graph per batch shape and replayed (as the lane
+// schedule is). The call waits for the launch, to report BOAC_ETIMEOUT.
+static boac_status persist_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r,
+                                 int32_t K, int32_t ck, hipStream_t st, const std::vector<uint64_t> &key) {
+    drop_stale_graphs(ctx);
+    for (auto &g : ctx->graphs) {
+        if (g.key == key && g.exec) {
+            HIP_TRY(hipGraphLaunch(g.exec, st));
+            ++ctx->graph_replays;
+            return persist_finish(ctx, (int *)g.aux, st);
+        }
+    }
+    std::vector<TaskRec> tasks;
+    unsigned lds = 0;
+    BOAC_TRY(persist_record(ctx, h_slices, n_slices, delta_r, K, ck, tasks, lds));
+    TaskRec *d_tasks = nullptr;
+    int *d_state = nullptr;
+    BOAC_TRY(ensure_t(ctx, "#persist_tasks", tasks.size(), &d_tasks));
+    BOAC_TRY(ensure_t(ctx, "#persist_state", 8 + 9 * tasks.size(), &d_state));
+    HIP_TRY(hipMemcpy(d_tasks, tasks.data(), sizeof(TaskRec) * tasks.size(), hipMemcpyHostToDevice));
+    PersistArgs pa{d_tasks, (int)tasks.size(), d_state, persist_spin_limit(ctx)};
+    HIP_TRY(launch_persist(pa, ctx->n_cu, lds, st));
+    BOAC_TRY(persist_finish(ctx, d_state, st));
+    if (st == nullptr) return BOAC_OK;  // the null stream cannot be captured
+    drop_stale_graphs(ctx);
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    const hipError_t le = launch_persist(pa, ctx->n_cu, lds, st);
+    ctx->capturing = false;
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(BOAC_EDEVICE, "persistent batch capture: %s", hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    GraphEntry ge;
+    ge.key = key;
+    ge.scratch_gen = ctx->scratch_gen;
+    ge.aux = d_state;
+    hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(BOAC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    if (ctx->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(ge);
+    ++ctx->graph_captures;
+    return BOAC_OK;
+}
+
 // Destroy every cached graph captured under an older scratch generation (its kernels may address
 // buffers that were freed when scratch grew since).
 static void drop_stale_graphs(boac_ctx *ctx) {
@@ -1702,6 +1901,10 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
                                (uint64_t)(uintptr_t)s.d_cand, (uint64_t)(uintptr_t)s.d_obj,
                                (uint64_t)(uintptr_t)s.d_grad, (uint64_t)(uintptr_t)s.d_status});
     }
+    key.push_back((uint64_t)ctx->batch_mode);
+    key.push_back((uint64_t)persist_spin_limit(ctx));
+    if (ctx->batch_mode == BOAC_BATCH_PERSISTENT)
+        return persist_batch(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st, key);
     const bool use_graph = (st != nullptr) && !ctx->profiling && std::getenv("BOAC_NO_GRAPH") == nullptr;
     if (!use_graph) return batch_body(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st);
 
@@ -1741,6 +1944,15 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
     ctx->graphs.push_back(ge);
     ++ctx->graph_captures;
     // the eager run above already produced this call's results
+    return BOAC_OK;
+}
+
+boac_status boac_ctx_set_batch_mode(boac_ctx *ctx, int32_t mode, int64_t spin_limit) {
+    if (!ctx) return fail(BOAC_EINVAL, "context is NULL");
+    if (mode != BOAC_BATCH_LANES && mode != BOAC_BATCH_PERSISTENT)
+        return fail(BOAC_EINVAL, "batch mode %d is neither BOAC_BATCH_LANES nor BOAC_BATCH_PERSISTENT", mode);
+    ctx->batch_mode = mode;
+    ctx->spin_limit = spin_limit > 0 ? (long long)spin_limit : 0;
     return BOAC_OK;
 }
 
