@@ -18,9 +18,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libboac.so")
-# kernels_persist.hip includes kernels_ray.hip, kernels_back.hip and kernels_misc.hip (one translation unit,
-# so that the persistent executor can inline every kernel body)
-SOURCES = ["kernels_persist.hip", "kernels_gp.hip", "gp_host.cpp", "runtime.cpp"]
+# kernels_persist.hip includes kernels_ray.hip, kernels_back.hip and kernels_misc.hip for their kernel bodies
+# (the persistent executor inlines them); the kernels themselves are compiled from their own files
+SOURCES = ["kernels_persist.hip", "kernels_ray.hip", "kernels_back.hip", "kernels_misc.hip", "kernels_gp.hip",
+           "gp_host.cpp", "runtime.cpp"]
 ARCH = "gfx950"
 
 

@@ -82,6 +82,7 @@ struct StageSlots {
     static constexpr int value = (HB > 1) ? 8 : (TW == 16 && TH == 16) ? 4 : (TW == 32 && TH == 16) ? 8 : 11;
 };
 
+#ifndef BOAC_BODIES_ONLY
 template <int CG, int TW, int TH, int HB>
 __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int PPT = (TW * TH) / 256;
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
         }
     }
 }
+#endif
 
 // ---------------------------------------------------------------------------------------------------
 // Slid-block variant (16 x 16 pixel tiles, one-bin half window, at least 32 bins and samples).
@@ -355,6 +357,7 @@ struct SlidLayout {
     static constexpr int PLANE = kSlidBlock * kSlidPitch * V;  // floats per plane
 };
 
+#ifndef BOAC_BODIES_ONLY
 template <int CG, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArgs A, int mode) {
     constexpr int P = kSlidBlock;
@@ -554,6 +557,7 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
         }
     }
 }
+#endif
 
 // ---------------------------------------------------------------------------------------------------
 // CG consecutive floats from LDS into registers, as wide reads where CG allows (p aligned to CG floats
@@ -854,21 +858,23 @@ __device__ __forceinline__ void k_back_col4_body(int bid, int tid, float *lds, b
 
     if (!pv || SPLIT) return;
     const size_t pix = (size_t)i * g.n + l;
+    // a guard rather than a break: the loop must unroll, or acc[] would live in scratch memory
 #pragma unroll
-    for (int q = 0; q < CG; ++q) {
-        if (q >= ncg) break;
-        back_epilogue(g, A, mode, (size_t)(c0 + q) * A.img_cs + pix, comp_value(acc[q]));
-    }
+    for (int q = 0; q < CG; ++q)
+        if (q < ncg) back_epilogue(g, A, mode, (size_t)(c0 + q) * A.img_cs + pix, comp_value(acc[q]));
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <int CG, bool WEIGHTED, bool PAIRED, bool SPLIT>
 __global__ __launch_bounds__(256) void k_back_col4(DevGeom g, BackCfg T, BackArgs A, int mode) {
     extern __shared__ float lds[];
     k_back_col4_body<CG, WEIGHTED, PAIRED, SPLIT>(blockIdx.x, threadIdx.x, lds, true, g, T, A, mode);
 }
+#endif
 
 // Second pass of the angle-split gather: per (candidate, pixel) the 8-angle block sums, added in angle
 // order to a compensated total exactly as the unsplit gather adds them, then the same epilogue.
+#ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(256) void k_back_combine(DevGeom g, BackArgs A, int nblk, int mode) {
     const size_t npix = (size_t)g.n * g.n;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -879,7 +885,9 @@ __global__ __launch_bounds__(256) void k_back_combine(DevGeom g, BackArgs A, int
     for (int b = 0; b < nblk; ++b) comp_add(acc, A.blk_out[((size_t)b * A.C + c) * A.img_cs + pix]);
     back_epilogue(g, A, mode, o, comp_value(acc));
 }
+#endif
 
+#ifndef BOAC_BODIES_ONLY
 template <int CG, bool SPLIT>
 static void back_col4_go(const DevGeom &g, const BackCfg &bc, const BackArgs &a, int mode, hipStream_t st) {
     const int ngroups = (a.C + CG - 1) / CG;
@@ -996,5 +1004,7 @@ hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const Back
     if (bc.hb == 3) return back_go<1, 16, 16, 3>(g, bc, a, mode, st);
     return hipErrorInvalidValue;
 }
+
+#endif  // BOAC_BODIES_ONLY
 
 }  // namespace boac

@@ -74,10 +74,12 @@ __device__ __forceinline__ void raster_at(const DevGeom &g, const float *__restr
     if (status && (neg || !finite)) atomicOr(status + cidx, (neg ? 4u : 0u) | (finite ? 0u : 2u));
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(256) void k_raster(DevGeom g, const float *__restrict__ cand, int C, float delta_r,
                                                 float *__restrict__ mu, size_t img_cs, uint32_t *status) {
     raster_at(g, cand, delta_r, mu, img_cs, status, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
+#endif
 
 // grad_k = sum_j mubar_j dmu_j/dtheta_k for theta = (c_0..c_5, mu_b, mu_c, dR), one workgroup per
 // candidate, compensated per component; written as 9 values per candidate.
@@ -129,30 +131,40 @@ __device__ __forceinline__ void k_raster_adj_body(int cidx, float *red, DevGeom 
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(256) void k_raster_adj(DevGeom g, const float *__restrict__ cand, float delta_r,
                                                     const float *__restrict__ mubar, size_t img_cs,
                                                     float *__restrict__ grad) {
     __shared__ float red[32];
     k_raster_adj_body(blockIdx.x, red, g, cand, delta_r, mubar, img_cs, grad);
 }
+#endif
 
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_fill(float *p, size_t count, float v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+#endif
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_fill_u32(uint32_t *p, size_t count, uint32_t v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+#endif
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_mul_copy(const float *a, const float *b, float *out, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         out[i] = a[i] * b[i];
 }
+#endif
 
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_copy(const float *src, float *dst, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
 }
+#endif
 
 // Adjoint of the objective terms y - S ln y at y = y^K (element t of C x nrays).
 __device__ __forceinline__ void ybar_final_at(const float *meas, const float *yK, float *ybar, int nrays,
@@ -161,11 +173,13 @@ __device__ __forceinline__ void ybar_final_at(const float *meas, const float *yK
     const float y = yK[c * sino_cs + i], S = meas[i];
     ybar[c * sino_cs + i] = (y > 0.f) ? 1.f - S / y : (S == 0.f ? 1.f : 0.f);
 }
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs) {
     const size_t total = (size_t)C * nrays;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
         ybar_final_at(meas, yK, ybar, nrays, sino_cs, t);
 }
+#endif
 
 // sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup (up to 1024
 // threads); red: 32 floats of shared memory.
@@ -185,10 +199,12 @@ __device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas,
     if (neg) atomicOr(flag, 8u);
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
     __shared__ float red[32];
     k_lgamma_sum_body(red, meas, count, out, flag);
 }
+#endif
 
 // J[c] = sum of the per-workgroup NLL partials + the ln Gamma constant; status bits.
 __device__ __forceinline__ void nll_finish_at(const float2 *partial, int chunks, int C, const float2 *lg,
@@ -208,10 +224,12 @@ __device__ __forceinline__ void nll_finish_at(const float2 *partial, int chunks,
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
                              float *obj, uint32_t *status) {
     nll_finish_at(partial, chunks, C, lg, meas_flag, obj, status, blockIdx.x * blockDim.x + threadIdx.x);
 }
+#endif
 
 // Reverse of F^{n+1} = F^n Q^n (Q^n = b^n / s):
 //   bbar = Fbar F^n / s,  sbar -= Fbar F^{n+1} / s,  Fbar_direct = Fbar Q^n      (0 where s <= 0)
@@ -231,17 +249,21 @@ __device__ __forceinline__ void adj_elem_at(const AdjElemArgs &A, size_t t) {
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_adj_elem(AdjElemArgs A) {
     const size_t total = (size_t)A.npix * A.C;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x)
         adj_elem_at(A, t);
 }
+#endif
 
 // (a, b) pairs; a NULL image stands for its constant
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_pack_pair(const float *a, float a_const, const float *b, float b_const, float2 *out, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         out[i] = make_float2(a ? a[i] : a_const, b ? b[i] : b_const);
 }
+#endif
 
 // Copies the first ncomp of the kGradComps raster-adjoint components per candidate; status bit 2 if
 // any copied value is not finite.
@@ -257,10 +279,13 @@ __device__ __forceinline__ void grad_finish_at(const float *grad, int C, int nco
     if (bad && status) status[c] |= 2u;
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ void k_grad_finish(const float *grad, int C, int ncomp, float *d_grad, uint32_t *status) {
     grad_finish_at(grad, C, ncomp, d_grad, status, blockIdx.x * blockDim.x + threadIdx.x);
 }
+#endif
 
+#ifndef BOAC_BODIES_ONLY
 // ------------------------------------------------------------------ launchers
 static unsigned fill_blocks(size_t count) {
     size_t b = (count + 255) / 256;
@@ -429,5 +454,7 @@ hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad
                        status);
     return hipGetLastError();
 }
+
+#endif  // BOAC_BODIES_ONLY
 
 }  // namespace boac

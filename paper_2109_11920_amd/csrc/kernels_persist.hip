@@ -1,7 +1,8 @@
 // Persistent executor of a recorded launch sequence (BOAC step 3 for many candidate sets in one launch).
 //
-// This translation unit includes the kernel sources, so every kernel body can be inlined into one
-// persistent kernel. The runtime records a batch's launches as tasks (TaskRecorder, launch.h), each
+// This translation unit includes the kernel sources for their bodies only (BOAC_BODIES_ONLY: the
+// kernels and launchers themselves are compiled in their own translation units, whose code generation
+// the persistent kernel must not change), so every body can be inlined into one persistent kernel. The runtime records a batch's launches as tasks (TaskRecorder, launch.h), each
 // with the task it must wait for (its predecessor on the same lane). k_persist then runs them all in one
 // launch of one 1024-thread workgroup per CU:
 //
@@ -19,6 +20,7 @@
 //            four recorded 256-thread workgroups, each on its own quarter of the threads and of the LDS
 //            (a stand-in takes part in the barriers when the grid runs out); elementwise items cover
 //            kPersistElems elements; the small reductions run on the whole workgroup.
+#define BOAC_BODIES_ONLY
 #include "kernels_ray.hip"
 #include "kernels_back.hip"
 #include "kernels_misc.hip"
@@ -287,10 +289,16 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const TaskRec *__re
     }
 }
 
+// Zeroes the executor's queue state (a kernel, not a memset: the launch may be captured into a graph).
+__global__ void k_persist_zero(int *state, size_t words) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        state[i] = 0;
+}
+
 hipError_t launch_persist(const PersistArgs &a, int workgroups, unsigned lds, hipStream_t st) {
     const size_t words = 8 + 9 * (size_t)a.ntasks;
-    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(words)), dim3(256), 0, st, reinterpret_cast<uint32_t *>(a.state),
-                       words, 0u);
+    hipLaunchKernelGGL(k_persist_zero, dim3((unsigned)std::min<size_t>(1024, (words + 255) / 256)), dim3(256), 0, st,
+                       a.state, words);
     hipLaunchKernelGGL(k_persist, dim3((unsigned)workgroups), dim3(kPersistThreads), lds, st, a.tasks, a.ntasks, a.state,
                        a.spin_limit);
     return hipGetLastError();

@@ -157,6 +157,7 @@ __device__ __forceinline__ void k_att_body(int bid, float *lds, DevGeom g, const
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <bool SINGLE>
 __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, int chunks, int C,
                                              const float *__restrict__ mu, float *__restrict__ att, size_t img_cs,
@@ -164,6 +165,7 @@ __global__ __launch_bounds__(1024) void k_att(DevGeom g, Bands bands, int rpt, i
     extern __shared__ float lds[];
     k_att_body<SINGLE>(blockIdx.x, lds, g, bands, rpt, chunks, C, mu, att, img_cs, att_cs, E, e_cs);
 }
+#endif
 
 // Attenuation build with each ray's scan spread over kScanLanes lanes of one wave (single-stage images).
 // The ray is walked from the detector end in rounds of kScanLanes 4-sample groups, lane j taking the
@@ -252,6 +254,7 @@ __device__ __forceinline__ void k_att_scan_body(int bid, float *lds, DevGeom g, 
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int passes, int chunks, int C,
                                                   const float *__restrict__ mu, float *__restrict__ att,
                                                   size_t img_cs, size_t att_cs, float *__restrict__ E,
@@ -259,6 +262,7 @@ __global__ __launch_bounds__(1024) void k_att_scan(DevGeom g, Band band, int pas
     extern __shared__ float lds[];
     k_att_scan_body(blockIdx.x, lds, g, band, passes, chunks, C, mu, att, img_cs, att_cs, E, e_cs);
 }
+#endif
 
 // ------------------------------------------------------------------ forward projection
 // The epilogue of one ray: y, or the MLEM ratio, or (returned) the NLL term; zero_proj is set where
@@ -444,12 +448,14 @@ __device__ __forceinline__ void k_fwd_body(int bid, float *lds, float *red, DevG
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <int MODE, bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_fwd(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
     extern __shared__ float lds[];
     __shared__ float red[32];  // two floats per wave, up to 16 waves
     k_fwd_body<MODE, SINGLE, PAIRED>(blockIdx.x, lds, red, g, bands, rpt, chunks, C, A);
 }
+#endif
 
 // Forward projection of two candidates per workgroup, both images staged at once (interleaved as
 // float2): each sample's position, clamp, tap index and bilinear fractions are computed once and
@@ -573,12 +579,14 @@ __device__ __forceinline__ void k_fwd_pair_body(int bid, float *lds, float *red,
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <int MODE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_fwd_pair(DevGeom g, Bands bands, int rpt, int chunks, int C, FwdArgs A) {
     extern __shared__ float lds[];
     __shared__ float red[32];  // two floats per wave, up to 16 waves
     k_fwd_pair_body<MODE, PAIRED>(blockIdx.x, lds, red, g, bands, rpt, chunks, C, A);
 }
+#endif
 
 // ------------------------------------------------------------------ fused reverse sweep
 // One reverse MLEM step n, per ray i (pair image = (bbar^n, F^{n+1}) staged in LDS):
@@ -797,11 +805,13 @@ __device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g,
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_adj_sweep(DevGeom g, Bands bands, int rpt, int chunks, int C, SweepArgs A) {
     extern __shared__ float lds[];
     k_adj_sweep_body<SINGLE, PAIRED>(blockIdx.x, lds, g, bands, rpt, chunks, C, A);
 }
+#endif
 
 // ------------------------------------------------------------------ tail of the attenuation adjoint
 // att_bar (+)= dx (W G1 + rho_i W G2) with the pair image (G1, G2) = (s_bar, F^0) and rho = ybar^0
@@ -1021,11 +1031,13 @@ __device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, cons
     }
 }
 
+#ifndef BOAC_BODIES_ONLY
 template <bool SINGLE, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, int chunks, int C, TailArgs A) {
     extern __shared__ float lds[];
     k_tail_body<SINGLE, PAIRED>(blockIdx.x, lds, g, bands, rpt, chunks, C, A);
 }
+#endif
 
 // Forward projection for few candidates (a grid of one-thread-per-ray workgroups would leave most of the
 // GPU idle): each ray is split over kSplitLanes lanes of one wave, lane j taking the 16-sample chunks j,
@@ -1037,6 +1049,7 @@ __global__ __launch_bounds__(1024) void k_tail(DevGeom g, Bands bands, int rpt, 
 constexpr int kSplitLanes = 8;
 constexpr int kSplitCpl = 2;  // chunks per lane
 
+#ifndef BOAC_BODIES_ONLY
 template <int MODE, bool PAIRED>
 __global__ __launch_bounds__(256) void k_fwd_split(DevGeom g, Band band, int chunks, int C, FwdArgs A) {
     static_assert(MODE != FWD_NLL, "the likelihood epilogue runs in k_fwd");
@@ -1106,7 +1119,9 @@ __global__ __launch_bounds__(256) void k_fwd_split(DevGeom g, Band band, int chu
     fwd_emit<MODE>(A, cand, ray, g.dx * comp_value(c), zero_proj);
     if constexpr (PAIRED) fwd_emit<MODE>(A, cand, (a + g.nah) * g.nb + (g.nb - 1 - b), g.dx * comp_value(c2), zero_proj);
 }
+#endif
 
+#ifndef BOAC_BODIES_ONLY
 // ------------------------------------------------------------------ launchers
 static dim3 ray_grid(const RayCfg &rc, int C) { return dim3((unsigned)(rc.chunks * C)); }
 
@@ -1246,5 +1261,7 @@ hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, c
                            rc.chunks, C, a);
     return hipGetLastError();
 }
+
+#endif  // BOAC_BODIES_ONLY
 
 }  // namespace boac
