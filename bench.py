@@ -443,6 +443,7 @@ def main():
     ap.add_argument("--only-grad", action="store_true", help="the gradient lines only (for profiler runs)")
     ap.add_argument("--only-gp", action="store_true", help="the acquisition-kernel line only (for profiler runs)")
     ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
+    ap.add_argument("--only-bo", action="store_true", help="the BOAC outer-loop line only")
     ap.add_argument("--only-schedules", action="store_true", help="the batch-schedule comparison only")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
@@ -486,8 +487,12 @@ def main():
               flush=True)
         ctx.close()
         return
-    if args.only_uneven or args.only_gp or args.only_grad:
+    if args.only_uneven or args.only_gp or args.only_grad or args.only_bo:
         out = {}
+        if args.only_bo:
+            import numpy as np
+            d = np.load(os.path.join(ROOT, "tests", "golden", "slice_n128.npz"))
+            out["bo"] = bo_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64))
         if args.only_uneven:
             out["uneven48"] = uneven_line(ctx, dev)
         if args.only_grad:

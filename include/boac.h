@@ -243,6 +243,23 @@ boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_
                        const double *d_alpha, const double *d_q, int32_t M, double best, double xi, double *d_mu,
                        double *d_sigma, double *d_ei, void *stream);
 
+/* Device: the local stage of the acquisition search (Bayesian Optimization, step 5: the chaotic search,
+ * read as in the host search of the Python package), n_local rounds with no host round trip. The
+ * chains are split evenly over the centres, per = P / n_centres chains each (the first per * n_centres
+ * chains are used). Round t (r_0 = radius0, r_{t+1} = r_t * shrink):
+ *   U[c * per + k] = clip(C[c] + r_t * (2 z[c * per + k] - 1), 0, 1)   (FP64, in that operation order)
+ *   v = EI at U (as boac_gp_ei); centre c moves to its first chain of largest v when that v exceeds
+ *   centre_ei[c]; then every chain steps z <- 4 z (1 - z).
+ * d_z [P][d] chains in (0, 1), updated in place; d_centres [n_centres][d] and d_centre_ei [n_centres]
+ * updated in place; d_pts [n_local][per * n_centres][d] and d_vals [n_local][per * n_centres] receive
+ * every round's points and EI values. d = info->d; 1 <= n_centres <= P, 0 <= n_local <= 4096,
+ * per * n_centres <= 2^20, radius0 and shrink finite and >= 0. EI values are taken to be finite (NaN
+ * never wins a comparison). Scratch as boac_gp_ei. Asynchronous on stream. */
+boac_status boac_gp_chaos_local(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                                const double *d_alpha, double best, double xi, double *d_z, int32_t P,
+                                double *d_centres, double *d_centre_ei, int32_t n_centres, double radius0,
+                                double shrink, int32_t n_local, double *d_pts, double *d_vals, void *stream);
+
 /* Kernel-time instrumentation: when enabled, every launch is bracketed by HIP events on its stream
  * and its duration is accumulated per kernel kind after the caller synchronises. */
 typedef enum {

@@ -209,6 +209,28 @@ class Context:
                                   _ptr(ei, "ei", f64), _stream(self.device)))
         return (ei, mu, sd) if want_mu_sigma else ei
 
+    def gp_chaos_local(self, model: "GpModel", best: float, xi: float, z: torch.Tensor, centres: torch.Tensor,
+                       centre_ei: torch.Tensor, radius0: float, shrink: float, n_local: int):
+        """The acquisition search's local stage on the device (boac_gp_chaos_local): z [P, d], centres [nc, d]
+        and centre_ei [nc] (float64 device tensors) are updated in place; returns the rounds' points
+        [n_local, per * nc, d] and EI values [n_local, per * nc], per = P // nc."""
+        P, d = z.shape
+        nc = centres.shape[0]
+        m = (P // max(nc, 1)) * nc
+        dm = model.on(self.device)
+        f64 = torch.float64
+        pts = torch.empty((n_local, m, d), device=self.device, dtype=f64)
+        vals = torch.empty((n_local, m), device=self.device, dtype=f64)
+        check(self.lib.boac_gp_chaos_local(self.handle, ctypes.byref(model.info),
+                                           _ptr(dm["u"], "u", f64), _ptr(dm["linv"], "linv", f64),
+                                           _ptr(dm["alpha"], "alpha", f64), float(best), float(xi),
+                                           _ptr(z, "z", f64, (P, model.info.d)), P,
+                                           _ptr(centres, "centres", f64, (nc, model.info.d)),
+                                           _ptr(centre_ei, "centre_ei", f64, (nc,)), nc, float(radius0),
+                                           float(shrink), int(n_local), _ptr(pts, "pts", f64),
+                                           _ptr(vals, "vals", f64), _stream(self.device)))
+        return pts, vals
+
     def evaluate_batch(self, slices: Sequence["SliceBatch"], delta_r: float, n_iter: int, ckpt_every: int = 5):
         arr = (BoacSlice * len(slices))()
         for i, s in enumerate(slices):

@@ -95,7 +95,7 @@ def _select_top(U, score, q, exclusion, taken, pool_per_pick: int = 16):
 
 
 def chaotic_acquire(ei_of, z: np.ndarray, q: int, taken, *, n_global: int, n_local: int, centres: int,
-                    radius0: float, shrink: float, exclusion: float, per_step: int):
+                    radius0: float, shrink: float, exclusion: float, per_step: int, local=None):
     """Step 5's search for q proposals maximising the acquisition ei_of (rows of a [m, d] unit-box array
     -> [m] values), from the chains z [P, d] in (0, 1) of the logistic map z <- 4 z (1 - z).
 
@@ -104,7 +104,12 @@ def chaotic_acquire(ei_of, z: np.ndarray, q: int, taken, *, n_global: int, n_loc
     centres sample boxes of half-width radius0 shrink^t around them, and a centre moves to its best point
     of a round when that beats it. Each round keeps its per_step best points (ties by lower index); the
     proposals are taken greedily from that pool, each at least `exclusion` from the points taken and from
-    `taken`. Returns (proposals [<= q, d], largest value evaluated, number of evaluations)."""
+    `taken`. Returns (proposals [<= q, d], largest value evaluated, number of evaluations).
+
+    The global stage's points do not depend on the acquisition values, so its rounds go to ei_of in one
+    call (each query's value does not depend on the others). local(z, C, Ce, radius0) may run the whole
+    local stage elsewhere (the device: Context.gp_chaos_local) and return its rounds' points
+    [n_local, per * len(C), d] and values [n_local, per * len(C)], as the loop below would produce them."""
     z = np.array(z, dtype=np.float64)
     P, d = z.shape
     pts, vals = [], []
@@ -112,22 +117,37 @@ def chaotic_acquire(ei_of, z: np.ndarray, q: int, taken, *, n_global: int, n_loc
 
     def keep(U, e):
         if len(e) > per_step:
-            top = np.sort(np.argsort(-e, kind="stable")[:per_step])
+            # the per_step best, ties by lower index: every value above the per_step-th largest, then the
+            # lowest indices holding that value (a partition instead of a full sort)
+            thr = np.partition(e, len(e) - per_step)[len(e) - per_step]
+            above = np.flatnonzero(e > thr)
+            at = np.flatnonzero(e == thr)[:per_step - len(above)]
+            top = np.sort(np.concatenate([above, at]))
             U, e = U[top], e[top]
         pts.append(U.copy())
         vals.append(e)
 
+    Zs = []
     for _ in range(n_global):
-        e = np.asarray(ei_of(z), np.float64)
-        n_queries += P
-        keep(z, e)
+        Zs.append(z)
         z = 4.0 * z * (1.0 - z)
+    if Zs:
+        e_all = np.asarray(ei_of(np.concatenate(Zs)), np.float64)
+        for t, Z in enumerate(Zs):
+            keep(Z, e_all[t * P:(t + 1) * P])
+        n_queries += P * len(Zs)
     allU, allE = np.concatenate(pts), np.concatenate(vals)
     cidx = _select_top(allU, allE, min(max(centres, q), P), exclusion, None)
     C = allU[cidx].copy()
     Ce = allE[cidx].copy()
     per = max(1, P // max(1, len(C)))
     r = radius0
+    if local is not None and n_local > 0:
+        U_all, e_all = local(z, C, Ce, r)
+        for t in range(n_local):
+            keep(np.asarray(U_all[t], np.float64), np.asarray(e_all[t], np.float64))
+        n_queries += int(np.asarray(e_all).size)
+        n_local = 0
     for _ in range(n_local):
         zz = z[:per * len(C)].reshape(len(C), per, d)
         U = np.clip(C[:, None, :] + r * (2.0 * zz - 1.0), 0.0, 1.0).reshape(-1, d)
@@ -186,7 +206,7 @@ class BOAC:
                  seed: int = 0, chains: int = 4096, n_global: int = 16, n_local: int = 32, centres: int = 8,
                  radius0: float = 0.1, shrink: float = 0.85, exclusion: float = 0.02, ei_stop: Optional[float] = None,
                  gradient: Optional[str] = None, line_starts: int = 4, ckpt_every: int = 5, n_select: int = 256,
-                 noise: float = 1e-6, journal: Optional[str] = None):
+                 noise: float = 1e-6, journal: Optional[str] = None, device_search: bool = True):
         if gradient not in (None, "envelope", "unrolled"):
             raise ValueError("gradient must be None, 'envelope' or 'unrolled'")
         self.ctx, self.geom, self.meas = ctx, geom, meas
@@ -198,6 +218,9 @@ class BOAC:
         self.gradient, self.line_starts, self.ckpt_every = gradient, int(line_starts), int(ckpt_every)
         self.n_select, self.noise = int(n_select), float(noise)
         self.journal = journal
+        # the search's local stage on the device (one call, no host round trip per round); the same
+        # proposals as the host loop, so it is not part of the journal's configuration
+        self.device_search = bool(device_search)
         self.cycles: List[Cycle] = []
         if journal and os.path.exists(journal):
             self._replay(journal)
@@ -265,12 +288,23 @@ class BOAC:
         rng = self._rng(cycle, 1)
         z = rng.uniform(0.01, 0.99, size=(self.chains, d))
 
+        dev = self.ctx.device
+
         def ei_of(U):
-            return self.ctx.gp_ei(model, torch.as_tensor(U, device=self.ctx.device), best, self.xi).cpu().numpy()
+            return self.ctx.gp_ei(model, torch.as_tensor(U, device=dev), best, self.xi).cpu().numpy()
+
+        def local(zl, C, Ce, r0):
+            f64 = torch.float64
+            pts, vals = self.ctx.gp_chaos_local(model, best, self.xi, torch.tensor(zl, dtype=f64, device=dev),
+                                                torch.tensor(C, dtype=f64, device=dev),
+                                                torch.tensor(Ce, dtype=f64, device=dev), r0, self.shrink,
+                                                self.n_local)
+            return pts.cpu().numpy(), vals.cpu().numpy()
 
         return chaotic_acquire(ei_of, z, q, taken, n_global=self.n_global, n_local=self.n_local,
                                centres=self.centres, radius0=self.radius0, shrink=self.shrink,
-                               exclusion=self.exclusion, per_step=max(4 * q, 256))
+                               exclusion=self.exclusion, per_step=max(4 * q, 256),
+                               local=local if self.device_search else None)
 
     # ---- the loop -------------------------------------------------------------------------------
     def step(self) -> Cycle:

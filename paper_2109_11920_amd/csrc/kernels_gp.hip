@@ -119,6 +119,68 @@ __global__ __launch_bounds__(256) void k_gp_ei(GpEiArgs A) {
     }
 }
 
+// ------------------------------------------------------------------ acquisition search, local stage
+// (Bayesian Optimization, step 5: chaotic search). Per round: the query points of every centre's chains,
+// U = clip(C_c + r (2 z - 1), 0, 1) in FP64 with the host search's operation order (no contraction), so
+// the device search takes the same points as one run on the host; after the EI kernels, each centre
+// moves to the first of its chains' best points when that beats its value; then z <- 4 z (1 - z).
+__global__ __launch_bounds__(256) void k_chaos_points(const double *__restrict__ z, const double *__restrict__ C,
+                                                      double r, int per, int d, int count, double *__restrict__ U) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // element of U [nc * per][d]; z rows match U rows
+    if (t >= count) return;
+    const int row = t / d, k = t - row * d;
+    const double w = 2.0 * z[t] - 1.0;
+    const double v = C[(row / per) * d + k] + r * w;
+    const double m = v > 0.0 ? v : 0.0;  // clip to [0, 1] as max then min, comparisons only
+    U[t] = m < 1.0 ? m : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_chaos_centres(const double *__restrict__ U, const double *__restrict__ e,
+                                                       int per, int nc, int d, double *__restrict__ C,
+                                                       double *__restrict__ Ce) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *ec = e + (size_t)c * per;
+    int j = 0;
+    double best = ec[0];
+    for (int k = 1; k < per; ++k)
+        if (ec[k] > best) {
+            best = ec[k];
+            j = k;
+        }
+    if (best > Ce[c]) {
+        Ce[c] = best;
+        for (int k = 0; k < d; ++k) C[(size_t)c * d + k] = U[((size_t)c * per + j) * d + k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_chaos_step(double *__restrict__ z, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const double v = z[t];
+    z[t] = (4.0 * v) * (1.0 - v);
+}
+
+hipError_t launch_chaos_points(const double *z, const double *C, double r, int per, int nc, int d, double *U,
+                               hipStream_t st) {
+    const int count = per * nc * d;
+    hipLaunchKernelGGL(k_chaos_points, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, z, C, r, per, d,
+                       count, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_chaos_centres(const double *U, const double *e, int per, int nc, int d, double *C, double *Ce,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_chaos_centres, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, U, e, per, nc, d, C,
+                       Ce);
+    return hipGetLastError();
+}
+
+hipError_t launch_chaos_step(double *z, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_chaos_step, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, z, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_gp_ei(const GpEiArgs &a, hipStream_t st) {
     size_t blocks = ((size_t)a.M * a.npad + 255) / 256;
     if (blocks > 16384) blocks = 16384;

@@ -249,6 +249,11 @@ hipError_t launch_grad_finish(const float *grad, int C, int ncomp, float *d_grad
 hipError_t launch_mul_copy(const float *a, const float *b, float *out, size_t count, hipStream_t st);
 hipError_t launch_copy(const float *src, float *dst, size_t count, hipStream_t st);
 hipError_t launch_gp_ei(const GpEiArgs &a, hipStream_t st);
+hipError_t launch_chaos_points(const double *z, const double *C, double r, int per, int nc, int d, double *U,
+                               hipStream_t st);
+hipError_t launch_chaos_centres(const double *U, const double *e, int per, int nc, int d, double *C, double *Ce,
+                                hipStream_t st);
+hipError_t launch_chaos_step(double *z, int count, hipStream_t st);
 hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
                              hipStream_t st);
 

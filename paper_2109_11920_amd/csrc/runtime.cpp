@@ -1540,9 +1540,10 @@ boac_status boac_gp_fit(const double *h_u, const double *h_y, int32_t n, int32_t
     return BOAC_OK;
 }
 
-boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
-                       const double *d_alpha, const double *d_q, int32_t M, double best, double xi, double *d_mu,
-                       double *d_sigma, double *d_ei, void *stream) {
+// The EI launch arguments of a fitted surrogate for M queries, validated (no device call; the scratch
+// pointers are set by gp_ei_scratch).
+static boac_status gp_ei_args(const boac_gp_info *info, const double *d_u, const double *d_linv,
+                              const double *d_alpha, int32_t M, double best, double xi, GpEiArgs *out) {
     if (!info) return fail(BOAC_EINVAL, "info is NULL");
     if (info->n < 1 || info->n > 8192 || info->d < 1 || info->d > 64)
         return fail(BOAC_EINVAL, "info holds n = %d, d = %d outside the supported range", info->n, info->d);
@@ -1555,16 +1556,10 @@ boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_
     BOAC_TRY(check_ptr(d_u, "d_u"));
     BOAC_TRY(check_ptr(d_linv, "d_linv"));
     BOAC_TRY(check_ptr(d_alpha, "d_alpha"));
-    BOAC_TRY(check_ptr(d_q, "d_q"));
-    BOAC_TRY(check_ptr(d_ei, "d_ei"));
-    BOAC_TRY(check_ptr(d_mu, "d_mu", true));
-    BOAC_TRY(check_ptr(d_sigma, "d_sigma", true));
-    CTX_CHECK();
     GpEiArgs a{};
     a.u = d_u;
     a.linv = d_linv;
     a.alpha = d_alpha;
-    a.q = d_q;
     a.n = info->n;
     a.d = info->d;
     a.M = M;
@@ -1576,13 +1571,72 @@ boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_
     a.s = info->s;
     a.best = best;
     a.xi = xi;
+    *out = a;
+    return BOAC_OK;
+}
+
+static boac_status gp_ei_scratch(boac_ctx *ctx, GpEiArgs *a) {
+    BOAC_TRY(ensure_t(ctx, "gp_ks", (size_t)a->M * a->npad, &a->ks));
+    return ensure_t(ctx, "gp_part", (size_t)a->M * a->nti, &a->part);
+}
+
+boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                       const double *d_alpha, const double *d_q, int32_t M, double best, double xi, double *d_mu,
+                       double *d_sigma, double *d_ei, void *stream) {
+    GpEiArgs a{};
+    BOAC_TRY(gp_ei_args(info, d_u, d_linv, d_alpha, M, best, xi, &a));
+    BOAC_TRY(check_ptr(d_q, "d_q"));
+    BOAC_TRY(check_ptr(d_ei, "d_ei"));
+    BOAC_TRY(check_ptr(d_mu, "d_mu", true));
+    BOAC_TRY(check_ptr(d_sigma, "d_sigma", true));
+    CTX_CHECK();
+    BOAC_TRY(gp_ei_scratch(ctx, &a));
+    a.q = d_q;
     a.mu = d_mu;
     a.sd = d_sigma;
     a.ei = d_ei;
-    BOAC_TRY(ensure_t(ctx, "gp_ks", (size_t)M * a.npad, &a.ks));
-    BOAC_TRY(ensure_t(ctx, "gp_part", (size_t)M * a.nti, &a.part));
     const hipStream_t st = (hipStream_t)stream;
     return timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); });
+}
+
+boac_status boac_gp_chaos_local(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                                const double *d_alpha, double best, double xi, double *d_z, int32_t P,
+                                double *d_centres, double *d_centre_ei, int32_t n_centres, double radius0,
+                                double shrink, int32_t n_local, double *d_pts, double *d_vals, void *stream) {
+    if (P < 1 || n_centres < 1 || n_centres > P)
+        return fail(BOAC_EINVAL, "need 1 <= n_centres <= P (P = %d, n_centres = %d)", P, n_centres);
+    if (n_local < 0 || n_local > 4096) return fail(BOAC_EINVAL, "n_local = %d outside [0, 4096]", n_local);
+    if (!std::isfinite(radius0) || !(radius0 >= 0.0) || !std::isfinite(shrink) || !(shrink >= 0.0))
+        return fail(BOAC_EINVAL, "radius0 and shrink must be finite and >= 0");
+    BOAC_TRY(check_ptr(d_z, "d_z"));
+    BOAC_TRY(check_ptr(d_centres, "d_centres"));
+    BOAC_TRY(check_ptr(d_centre_ei, "d_centre_ei"));
+    BOAC_TRY(check_ptr(d_pts, "d_pts", n_local == 0));
+    BOAC_TRY(check_ptr(d_vals, "d_vals", n_local == 0));
+    const int per = P / n_centres;
+    const int M = per * n_centres;
+    GpEiArgs a{};
+    BOAC_TRY(gp_ei_args(info, d_u, d_linv, d_alpha, M, best, xi, &a));
+    const int d = a.d;
+    if ((long long)P * d >= (1LL << 31) || (long long)n_local * M * d >= (1LL << 40))
+        return fail(BOAC_EINVAL, "P x d or n_local x M x d too large");
+    CTX_CHECK();
+    BOAC_TRY(gp_ei_scratch(ctx, &a));
+    const hipStream_t st = (hipStream_t)stream;
+    double r = radius0;
+    for (int t = 0; t < n_local; ++t) {
+        double *U = d_pts + (size_t)t * M * d;
+        double *e = d_vals + (size_t)t * M;
+        HIP_TRY(launch_chaos_points(d_z, d_centres, r, per, n_centres, d, U, st));
+        a.q = U;
+        a.ei = e;
+        a.mu = a.sd = nullptr;
+        BOAC_TRY(timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); }));
+        HIP_TRY(launch_chaos_centres(U, e, per, n_centres, d, d_centres, d_centre_ei, st));
+        HIP_TRY(launch_chaos_step(d_z, P * d, st));
+        r *= shrink;
+    }
+    return BOAC_OK;
 }
 
 // Relative cost of a slice (algorithmic attenuation-tensor passes x tensor size x candidates).

@@ -121,3 +121,20 @@ def test_noalloc_rejects_a_geometry_beyond_its_scratch_before_the_device(lib):
     st = lib.boac_objective_noalloc(None, ctypes.byref(_good()), ALIGNED, ALIGNED, 4, 0.8, 5, ALIGNED, None, None,
                                     None)
     assert st == 1 and b"context" in lib.boac_last_error()
+
+
+def test_device_search_entry_point_validates_before_the_device(lib):
+    from paper_2109_11920_amd._lib import BoacGpInfo
+    info = BoacGpInfo(4, 8, 0.5, 1.0, 1e-6, 10.0, 2.0, -3.0)
+
+    def call(P, nc, n_local=3, r0=0.1, shrink=0.85):
+        return lib.boac_gp_chaos_local(None, ctypes.byref(info), ALIGNED, ALIGNED, ALIGNED, 1.0, 0.0, ALIGNED, P,
+                                       ALIGNED, ALIGNED, nc, r0, shrink, n_local, ALIGNED, ALIGNED, None)
+    assert call(4, 5) == 1 and b"n_centres" in lib.boac_last_error()
+    assert call(0, 1) == 1
+    assert call(64, 8, n_local=-1) == 1
+    assert call(64, 8, r0=float("nan")) == 1
+    assert call(64, 8, shrink=-0.5) == 1
+    assert call((1 << 21), 1) == 1 and b"M" in lib.boac_last_error()   # per x n_centres above 2^20
+    # valid arguments, no context: refused before any device call
+    assert call(64, 8) == 1 and b"context" in lib.boac_last_error()

@@ -63,3 +63,26 @@ def test_acquisition_search_equals_the_oracle_search():
         assert m == m_r and best == best_r
         np.testing.assert_array_equal(U, Ur)
         assert len(U) == q
+
+
+def test_round_pool_keeps_the_best_with_ties_by_lower_index():
+    # each round of the search keeps its per_step best points, ties by lower index: the same set as a
+    # stable sort in decreasing value, also with many tied values
+    from paper_2109_11920_amd.bo import chaotic_acquire
+    rng = np.random.default_rng(5)
+    for levels in (3, 40, 10 ** 6):
+        vals = rng.integers(0, levels, size=512).astype(np.float64)
+        z = rng.uniform(0.01, 0.99, size=(512, 2))
+        seen = []
+
+        def acq(U):
+            seen.append(np.asarray(U, np.float64).copy())
+            return vals[: len(U)] if len(U) == 512 else np.zeros(len(U))
+
+        # one global round, no local rounds: the pool is that round's kept points; q = per_step picks with no
+        # exclusion return exactly the kept set in decreasing value
+        U, best, m = chaotic_acquire(acq, z, 48, None, n_global=1, n_local=0, centres=1, radius0=0.1, shrink=0.85,
+                                     exclusion=0.0, per_step=48)
+        ref = np.sort(np.argsort(-vals, kind="stable")[:48])
+        order = ref[np.argsort(-vals[ref], kind="stable")]
+        np.testing.assert_array_equal(U, z[order])

@@ -64,3 +64,76 @@ def test_gp_ei_is_deterministic(ctx):
     a = ctx.gp_ei(m, q, float(y.min()), 0.0)
     b = ctx.gp_ei(m, q, float(y.min()), 0.0)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("P,nc,n_local", [(512, 8, 10), (300, 7, 6), (4096, 8, 32)])
+def test_device_local_search_equals_host_search(ctx, P, nc, n_local):
+    # the acquisition search's local stage on the device (boac_gp_chaos_local) against the host loop of
+    # the same search on the same surrogate: every round's points equal the host's bit for bit (FP64, same
+    # operation order) and its EI values equal boac_gp_ei at those points; the proposals of the whole
+    # search are the host search's
+    from paper_2109_11920_amd.api import gp_fit
+    from paper_2109_11920_amd.bo import chaotic_acquire
+    d = 8
+    U0, y = _obs(90, d, 7)
+    m = gp_fit(U0, y, obo.LENGTH_GRID, noise=obo.NOISE)
+    best = float(y.min())
+    rng = np.random.default_rng(P + nc)
+    z = rng.uniform(0.01, 0.99, size=(P, d))
+    C = rng.uniform(size=(nc, d))
+    f64 = torch.float64
+
+    def ei_of(Q):
+        return ctx.gp_ei(m, torch.as_tensor(np.ascontiguousarray(Q), device="cuda"), best, 0.0).cpu().numpy()
+
+    Ce = ei_of(C)
+    zt, Ct, Cet = (torch.tensor(a, dtype=f64, device="cuda") for a in (z, C, Ce))
+    pts, vals = ctx.gp_chaos_local(m, best, 0.0, zt, Ct, Cet, 0.1, 0.85, n_local)
+    torch.cuda.synchronize()
+    pts, vals = pts.cpu().numpy(), vals.cpu().numpy()
+    # the host loop
+    per = P // nc
+    zh, Ch, Ceh, r = z.copy(), C.copy(), Ce.copy(), 0.1
+    for t in range(n_local):
+        zz = zh[:per * nc].reshape(nc, per, d)
+        Uh = np.clip(Ch[:, None, :] + r * (2.0 * zz - 1.0), 0.0, 1.0).reshape(-1, d)
+        np.testing.assert_array_equal(pts[t], Uh)
+        eh = ei_of(Uh)
+        np.testing.assert_array_equal(vals[t], eh)
+        e2 = eh.reshape(nc, per)
+        j = np.argmax(e2, axis=1)
+        better = e2[np.arange(nc), j] > Ceh
+        Ch[better] = Uh.reshape(nc, per, d)[better, j[better]]
+        Ceh[better] = e2[better, j[better]]
+        zh = 4.0 * zh * (1.0 - zh)
+        r *= 0.85
+    np.testing.assert_array_equal(Ct.cpu().numpy(), Ch)
+    np.testing.assert_array_equal(Cet.cpu().numpy(), Ceh)
+    np.testing.assert_array_equal(zt.cpu().numpy(), zh)
+    # the whole search, with and without the device stage
+    def local(zl, Cl, Cel, r0):
+        a, b = ctx.gp_chaos_local(m, best, 0.0, torch.tensor(zl, dtype=f64, device="cuda"),
+                                  torch.tensor(Cl, dtype=f64, device="cuda"),
+                                  torch.tensor(Cel, dtype=f64, device="cuda"), r0, 0.85, n_local)
+        return a.cpu().numpy(), b.cpu().numpy()
+
+    taken = rng.uniform(size=(20, d))
+    kw = dict(n_global=4, n_local=n_local, centres=nc, radius0=0.1, shrink=0.85, exclusion=0.02, per_step=64)
+    Ua, ba, na = chaotic_acquire(ei_of, z, 6, taken, **kw)
+    Ub, bb, nb = chaotic_acquire(ei_of, z, 6, taken, local=local, **kw)
+    np.testing.assert_array_equal(Ua, Ub)
+    assert ba == bb and na == nb
+    print(f"[parity] device local search P={P} centres={nc} rounds={n_local}: points, EI, centres and "
+          f"proposals identical to the host search", flush=True)
+
+
+def test_device_local_search_rejects_bad_sizes(ctx):
+    from paper_2109_11920_amd.api import gp_fit
+    from paper_2109_11920_amd._lib import BoacError
+    U0, y = _obs(20, 8, 3)
+    m = gp_fit(U0, y, obo.LENGTH_GRID, noise=obo.NOISE)
+    f64 = torch.float64
+    z = torch.full((4, 8), 0.3, dtype=f64, device="cuda")
+    C = torch.full((5, 8), 0.5, dtype=f64, device="cuda")
+    with pytest.raises(BoacError):
+        ctx.gp_chaos_local(m, 0.0, 0.0, z, C, torch.zeros(5, dtype=f64, device="cuda"), 0.1, 0.85, 2)
