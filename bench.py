@@ -38,7 +38,8 @@ def source_digest(names):
 
 
 KERNEL_SOURCES = {"fwd": ["kernels_ray.hip", "device_common.h", "launch.h"],
-                  "back": ["kernels_back.hip", "device_common.h", "launch.h"]}
+                  "back": ["kernels_back.hip", "device_common.h", "launch.h"],
+                  "adj_ray": ["kernels_ray.hip", "device_common.h", "launch.h"]}
 
 
 def read_traffic(kind, workload):
@@ -224,9 +225,8 @@ def paper72_line(ctx, dev, reps=5):
             "what": "128^2, 72 angles x 128 bins, 2x-oversampled data, 256 candidates, 30 iterations + objective"}
 
 
-def uneven_line(ctx, dev):
-    """The 48-slice uneven batch: N 96-256, 64-256 angles, 32 candidates each, 40 iterations, objective
-    + gradient (checkpoint every 5), one captured batch over concurrent stream lanes; times one replay."""
+def uneven_slices(dev):
+    """The 48 slices of the uneven batch (measured data from tests/golden, seeded candidates)."""
     import numpy as np
     import torch
 
@@ -241,6 +241,64 @@ def uneven_line(ctx, dev):
         gs = Geometry(n, na, nb, nt, float(du[f"s{s:02d}_pixel"]))
         slices.append(SliceBatch.make(gs, torch.as_tensor(du[f"s{s:02d}_meas"].astype(np.float32), device=dev),
                                       torch.as_tensor(cu[s].astype(np.float32), device=dev), with_grad=True))
+    return slices, wu
+
+
+KINDS = ("raster", "att", "fwd", "back", "reduce", "adj_ray", "adj_pix", "other")
+KIND_KERNELS = {"fwd": "forward projections (k_fwd, k_fwd_pair)", "back": "backprojection gathers (k_back_col4)",
+                "adj_ray": "reverse ray sweeps (k_adj_sweep, k_tail)", "att": "attenuation builds"}
+
+
+def uneven_serial(ctx, dev, slices, wu, replay_ms=None):
+    """One eager evaluation of the uneven batch with its launches serialised (one stream lane) and timed
+    one by one with HIP events: kernel time and the library's algorithmic bytes per kind, the roofline
+    of the kind with the most time, and the whole batch's bytes over the replay time."""
+    import torch
+    old = os.environ.get("BOAC_BATCH_LANES")
+    os.environ["BOAC_BATCH_LANES"] = "1"
+    st = torch.cuda.Stream(dev)
+    try:
+        ctx.reset_stats()
+        ctx.set_profiling(True)
+        with torch.cuda.stream(st):
+            ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)
+        st.synchronize()
+        ks = {k: ctx.kernel_stats(k) for k in KINDS}
+    finally:
+        ctx.set_profiling(False)
+        if old is None:
+            del os.environ["BOAC_BATCH_LANES"]
+        else:
+            os.environ["BOAC_BATCH_LANES"] = old
+    per = {k: {"launches": c, "ms": round(ms, 2), "GB": round(by / 1e9, 3),
+               "TB/s": round(by / (ms / 1e3) / 1e12, 3) if ms > 0 else None}
+           for k, (c, ms, by) in ks.items() if c}
+    dom = max(("fwd", "back", "adj_ray"), key=lambda k: ks[k][1])
+    c, ms, by = ks[dom]
+    avg = ms / c
+    ach = by / c / (avg / 1e3) / 1e9
+    total_by = sum(v[2] for v in ks.values())
+    total_ms = sum(v[1] for v in ks.values())
+    out = {"kernel_ms_serial": round(total_ms, 1), "per_kind": per,
+           "roofline": {"bound": "hbm", "kernel": f"{dom}: {KIND_KERNELS[dom]}, all slices", "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "avg_launch_ms": round(avg, 4), "bytes_per_launch": by / c, "launches": c,
+                        "traffic": read_traffic(dom, "uneven48"),
+                        "what": "one eager evaluation, launches serialised on one stream and timed by HIP events; "
+                                "bytes: the library's algorithmic count per launch (attenuation tensors of the held "
+                                "angles, images and sinograms)"},
+           "batch_bytes_GB": round(total_by / 1e9, 2)}
+    if replay_ms:
+        out["step_frac_model_bytes"] = round(total_by / (replay_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def uneven_line(ctx, dev, serial=True):
+    """The 48-slice uneven batch: N 96-256, 64-256 angles, 32 candidates each, 40 iterations, objective
+    + gradient (checkpoint every 5), one captured batch over concurrent stream lanes; times one replay,
+    then (serial) one serialised eager evaluation for the per-kind roofline."""
+    import torch
+    slices, wu = uneven_slices(dev)
     ustream = torch.cuda.Stream(dev)
     with torch.cuda.stream(ustream):
         ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # runs eagerly, then captures
@@ -256,6 +314,7 @@ def uneven_line(ctx, dev):
     ok = all(bool(torch.isfinite(sb.obj).all()) and bool(torch.isfinite(sb.grad).all()) for sb in slices)
     return {"value": round(n_eval * wu.n_iter / (ums / 1e3), 1), "unit": "cand·it/s",
             "obj_grad_evals_per_s": round(n_eval / (ums / 1e3), 1), "ms_per_batch": round(ums, 2), "finite": ok,
+            **({"serialised": uneven_serial(ctx, dev, slices, wu, ums)} if serial else {}),
             "what": "48 slices N in {96,128,192,256}, 64-256 angles, 32 candidates each, 40 iterations, "
                     "objective + gradient, checkpoint 5, one graph replay"}
 
@@ -442,8 +501,11 @@ def main():
     ap.add_argument("--no-bo", action="store_true", help="skip the BOAC outer-loop line")
     ap.add_argument("--only-grad", action="store_true", help="the gradient lines only (for profiler runs)")
     ap.add_argument("--only-gp", action="store_true", help="the acquisition-kernel line only (for profiler runs)")
-    ap.add_argument("--only-uneven", action="store_true", help="the uneven-batch line only (for profiler runs)")
+    ap.add_argument("--only-uneven", action="store_true",
+                    help="the uneven batch's replay only, without the serialised pass (for profiler runs)")
     ap.add_argument("--only-bo", action="store_true", help="the BOAC outer-loop line only")
+    ap.add_argument("--only-uneven-serial", action="store_true",
+                    help="one serialised eager evaluation of the uneven batch (for profiler runs)")
     ap.add_argument("--only-schedules", action="store_true", help="the batch-schedule comparison only")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one 1 GiB device-to-device copy (counter calibration for profiler runs)")
@@ -487,6 +549,12 @@ def main():
               flush=True)
         ctx.close()
         return
+    if args.only_uneven_serial:
+        slices, wu = uneven_slices(dev)
+        uneven_serial(ctx, dev, slices, wu)   # the same pass once untimed: sizes scratch, uploads tables
+        print(json.dumps({"uneven48_serialised": uneven_serial(ctx, dev, slices, wu)}), flush=True)
+        ctx.close()
+        return
     if args.only_uneven or args.only_gp or args.only_grad or args.only_bo:
         out = {}
         if args.only_bo:
@@ -494,7 +562,8 @@ def main():
             d = np.load(os.path.join(ROOT, "tests", "golden", "slice_n128.npz"))
             out["bo"] = bo_line(ctx, g, S, np.asarray(d["theta"], dtype=np.float64))
         if args.only_uneven:
-            out["uneven48"] = uneven_line(ctx, dev)
+            # the replayed batch alone (the serialised pass has a mode of its own, --only-uneven-serial)
+            out["uneven48"] = uneven_line(ctx, dev, serial=False)
         if args.only_grad:
             out.update(grad_lines(ctx, g, S, dev, args.steps))
         if args.only_gp:
