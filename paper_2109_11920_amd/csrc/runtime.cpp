@@ -1666,31 +1666,49 @@ static boac_status eval_slice(boac_ctx *ctx, const boac_slice &s, float delta_r,
 // Batch scheduler: slices are assigned longest-first to the least-loaded of L concurrent stream
 // lanes (each with its own scratch namespace); the lanes fork from and join back into the caller's
 // stream through events, so a captured batch is one graph with L parallel branches.
-// A slice of at least this many candidates is evaluated as two halves on two lanes: a projection of
-// one half (bandwidth-bound) then overlaps a gather of the other (compute-bound). Per-candidate
-// arithmetic does not depend on the grouping, so the results are unchanged.
-constexpr int kSplitMinCand = 128;
+// A slice of many candidates can be evaluated as several parts on different lanes, so that a
+// projection of one part (bandwidth-bound) overlaps a gather of another (compute-bound). Parts hold at
+// least kSplitMinPart candidates (a multiple of 4, which keeps their pointers 16-byte aligned); a slice
+// is cut into at most batch_split() of them (BOAC_BATCH_SPLIT, default 1: whole slices). Per-candidate
+// arithmetic does not depend on the grouping, so the results are unchanged. Graph replays of the
+// 256-candidate batch as one slice: 17.9 ms per step whole, 18.0 ms in 2 parts, 18.6 ms in 4, 18.7 ms
+// in 8 (halves gained 5% before opposed-ray pairing halved the projections).
+constexpr int kSplitMinPart = 64;
 
-static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_in, float delta_r, int32_t K,
-                              int32_t ck, hipStream_t st) {
+static int batch_split() {
+    const char *e = std::getenv("BOAC_BATCH_SPLIT");
+    int n = e ? std::atoi(e) : 1;
+    return std::min(std::max(n, 1), 16);
+}
+
+static std::vector<boac_slice> batch_parts(const boac_slice *h_in, int32_t ns_in, bool split) {
     std::vector<boac_slice> parts;
     for (int i = 0; i < ns_in; ++i) {
         const boac_slice &s = h_in[i];
-        if (s.C < kSplitMinCand || batch_lanes() < 2) {
+        const int np = split ? std::min(batch_split(), s.C / kSplitMinPart) : 1;
+        if (np < 2) {
             parts.push_back(s);
             continue;
         }
-        const int c0 = (s.C / 2) & ~3;  // keeps the second half's pointers 16-byte aligned
-        boac_slice a = s, b = s;
-        a.C = c0;
-        b.C = s.C - c0;
-        b.d_cand = s.d_cand + c0;
-        b.d_obj = s.d_obj + c0;
-        if (s.d_grad) b.d_grad = s.d_grad + (size_t)8 * c0;
-        if (s.d_status) b.d_status = s.d_status + c0;
-        parts.push_back(a);
-        parts.push_back(b);
+        int c = 0;
+        for (int k = 0; k < np; ++k) {
+            const int c1 = (k == np - 1) ? s.C : (int)(((long)s.C * (k + 1) / np) & ~3L);
+            boac_slice p = s;
+            p.C = c1 - c;
+            p.d_cand = s.d_cand + c;
+            p.d_obj = s.d_obj + c;
+            if (s.d_grad) p.d_grad = s.d_grad + (size_t)8 * c;
+            if (s.d_status) p.d_status = s.d_status + c;
+            parts.push_back(p);
+            c = c1;
+        }
     }
+    return parts;
+}
+
+static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_in, float delta_r, int32_t K,
+                              int32_t ck, hipStream_t st) {
+    const std::vector<boac_slice> parts = batch_parts(h_in, ns_in, batch_lanes() >= 2);
     const boac_slice *h = parts.data();
     const int32_t ns = (int32_t)parts.size();
     const int L = std::min(batch_lanes(), (int)ns);
@@ -1746,29 +1764,6 @@ static int persist_lanes() {
     const char *e = std::getenv("BOAC_PERSIST_LANES");
     int n = e ? std::atoi(e) : 8;
     return std::min(std::max(n, 1), 64);
-}
-
-// Splits slices of at least kSplitMinCand candidates into two halves (as the stream lanes do).
-static std::vector<boac_slice> batch_parts(const boac_slice *h_in, int32_t ns_in, bool split) {
-    std::vector<boac_slice> parts;
-    for (int i = 0; i < ns_in; ++i) {
-        const boac_slice &s = h_in[i];
-        if (!split || s.C < kSplitMinCand) {
-            parts.push_back(s);
-            continue;
-        }
-        const int c0 = (s.C / 2) & ~3;  // keeps the second half's pointers 16-byte aligned
-        boac_slice a = s, b = s;
-        a.C = c0;
-        b.C = s.C - c0;
-        b.d_cand = s.d_cand + c0;
-        b.d_obj = s.d_obj + c0;
-        if (s.d_grad) b.d_grad = s.d_grad + (size_t)8 * c0;
-        if (s.d_status) b.d_status = s.d_status + c0;
-        parts.push_back(a);
-        parts.push_back(b);
-    }
-    return parts;
 }
 
 // Longest-first assignment of the parts to L lanes.
