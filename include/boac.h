@@ -260,6 +260,31 @@ boac_status boac_gp_chaos_local(boac_ctx *ctx, const boac_gp_info *info, const d
                                 double *d_centres, double *d_centre_ei, int32_t n_centres, double radius0,
                                 double shrink, int32_t n_local, double *d_pts, double *d_vals, void *stream);
 
+/* Device, synchronous: the whole acquisition search (Bayesian Optimization, step 5, read as above) for up
+ * to q proposals. The chains start at d_z0 [P][d] (not modified). Global stage: n_global rounds whose
+ * points are the chains themselves, then z <- 4 z (1 - z); their EI in one launch. Each round keeps a
+ * pool of its min(M, per_step) best points (larger EI first, lower index on ties; M the round's
+ * points). Centres: the greedy choice (below) over the global pools of min(max(centres, q), P) points,
+ * no exclusion from earlier points; then the local stage of boac_gp_chaos_local with radius0, shrink,
+ * n_local, the chains as left by the global stage, and P / (number of centres) chains per centre, its
+ * rounds pooled the same way. Proposals: the greedy choice over all pools (global rounds first, in
+ * round order) of up to q points, each at least `exclusion` from the d_taken [T][d] rows.
+ * Greedy choice: repeatedly the pool entry of largest EI (lowest pool position on ties) among those
+ * left, each entry nearer than `exclusion` (Euclidean, unit box) to a chosen one or to a taken row
+ * dropped. d_props [q][d] receives the proposals in choice order; *h_count their number (< q when the
+ * pool runs out), *h_max the largest EI of all pools (= of all points evaluated), *h_queries the number
+ * of EI evaluations. 1 <= P <= 8192, 1 <= n_global <= 4096, 0 <= n_local <= 4096, n_global * P <= 2^20,
+ * min(P, per_step) * (n_global + n_local) <= 32768; centres, q, per_step >= 1; radius0, shrink,
+ * exclusion finite and >= 0; d_taken may be NULL when T = 0. EI values are taken to be finite.
+ * Scratch lives in the context. The call waits for the stream (twice: the number of centres fixes the
+ * local stage's launches, and the counts are returned on the host). */
+boac_status boac_gp_chaos_search(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                                 const double *d_alpha, double best, double xi, const double *d_z0, int32_t P,
+                                 int32_t n_global, int32_t n_local, int32_t centres, int32_t q, double radius0,
+                                 double shrink, double exclusion, int32_t per_step, const double *d_taken,
+                                 int32_t T, double *d_props, int32_t *h_count, double *h_max, int64_t *h_queries,
+                                 void *stream);
+
 /* Kernel-time instrumentation: when enabled, every launch is bracketed by HIP events on its stream
  * and its duration is accumulated per kernel kind after the caller synchronises. */
 typedef enum {

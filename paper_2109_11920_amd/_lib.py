@@ -63,6 +63,11 @@ _SIGNATURES = {
     "boac_gp_chaos_local": (c_int32, [_P, ctypes.POINTER(BoacGpInfo), _P, _P, _P, ctypes.c_double, ctypes.c_double,
                                       _P, c_int32, _P, _P, c_int32, ctypes.c_double, ctypes.c_double, c_int32, _P,
                                       _P, _P]),
+    "boac_gp_chaos_search": (c_int32, [_P, ctypes.POINTER(BoacGpInfo), _P, _P, _P, ctypes.c_double, ctypes.c_double,
+                                       _P, c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, c_int32, _P, c_int32, _P,
+                                       ctypes.POINTER(c_int32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64), _P]),
     "boac_ctx_set_profiling": (c_int32, [_P, c_int32]),
     "boac_ctx_kernel_stats": (c_int32, [_P, c_int32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),

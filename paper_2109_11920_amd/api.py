@@ -231,6 +231,28 @@ class Context:
                                            _ptr(vals, "vals", f64), _stream(self.device)))
         return pts, vals
 
+    def gp_chaos_search(self, model: "GpModel", best: float, xi: float, z: torch.Tensor, taken: Optional[torch.Tensor],
+                        q: int, *, n_global: int, n_local: int, centres: int, radius0: float, shrink: float,
+                        exclusion: float, per_step: int):
+        """The whole acquisition search on the device (boac_gp_chaos_search): chains z [P, d] (float64 device
+        tensor, not modified), taken [T, d] or None. Returns (proposals [count, d] device tensor, largest EI
+        evaluated, number of EI evaluations)."""
+        P, d = z.shape
+        f64 = torch.float64
+        dm = model.on(self.device)
+        props = torch.empty((q, d), device=self.device, dtype=f64)
+        T = 0 if taken is None else taken.shape[0]
+        count, vmax, nq = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+        check(self.lib.boac_gp_chaos_search(self.handle, ctypes.byref(model.info), _ptr(dm["u"], "u", f64),
+                                            _ptr(dm["linv"], "linv", f64), _ptr(dm["alpha"], "alpha", f64),
+                                            float(best), float(xi), _ptr(z, "z", f64, (P, model.info.d)), P,
+                                            int(n_global), int(n_local), int(centres), int(q), float(radius0),
+                                            float(shrink), float(exclusion), int(per_step),
+                                            _ptr(taken, "taken", f64, (T, model.info.d)) if T else None, T,
+                                            _ptr(props, "props", f64), ctypes.byref(count), ctypes.byref(vmax),
+                                            ctypes.byref(nq), _stream(self.device)))
+        return props[: count.value], float(vmax.value), int(nq.value)
+
     def evaluate_batch(self, slices: Sequence["SliceBatch"], delta_r: float, n_iter: int, ckpt_every: int = 5):
         arr = (BoacSlice * len(slices))()
         for i, s in enumerate(slices):

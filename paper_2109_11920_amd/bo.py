@@ -6,11 +6,12 @@
      boac_objective_grad_ex when a gradient is wanted);
   4. the observations (unit-box coordinates, J) are fitted by the GP surrogate of Eqs. (7)-(8)
      (boac_gp_fit, native FP64 on the host);
-  5. new candidates maximise the expected improvement of Eqs. (9)-(10) (boac_gp_ei on the GPU), found by
-     a chaotic search driven by the logistic map z <- 4 z (1 - z): a global stage over the whole box,
-     then local stages around several incumbents with geometrically shrinking radii. A batch of
-     proposals is taken greedily from every evaluated point in decreasing EI, each at least `exclusion`
-     (unit-box distance) from those already taken;
+  5. new candidates maximise the expected improvement of Eqs. (9)-(10), found by a chaotic search driven
+     by the logistic map z <- 4 z (1 - z): a global stage over the whole box, then local stages around
+     several incumbents with geometrically shrinking radii. A batch of proposals is taken greedily from
+     every evaluated point in decreasing EI, each at least `exclusion` (unit-box distance) from those
+     already taken. The search runs on the GPU (boac_gp_chaos_search; chaotic_acquire is the same
+     search on the host around boac_gp_ei);
   6. the largest EI is recorded each cycle; the loop stops when it falls below `ei_stop` (relative to
      the surrogate's scale) or after the given number of cycles.
 
@@ -218,8 +219,8 @@ class BOAC:
         self.gradient, self.line_starts, self.ckpt_every = gradient, int(line_starts), int(ckpt_every)
         self.n_select, self.noise = int(n_select), float(noise)
         self.journal = journal
-        # the search's local stage on the device (one call, no host round trip per round); the same
-        # proposals as the host loop, so it is not part of the journal's configuration
+        # the whole acquisition search on the device (boac_gp_chaos_search); the same proposals as the
+        # host loop (chaotic_acquire), so it is not part of the journal's configuration
         self.device_search = bool(device_search)
         self.cycles: List[Cycle] = []
         if journal and os.path.exists(journal):
@@ -289,22 +290,23 @@ class BOAC:
         z = rng.uniform(0.01, 0.99, size=(self.chains, d))
 
         dev = self.ctx.device
+        per_step = max(4 * q, 256)
+        if self.device_search:
+            f64 = torch.float64
+            tk = None if taken is None or len(taken) == 0 else torch.tensor(np.asarray(taken, np.float64), dtype=f64,
+                                                                           device=dev)
+            props, vmax, nq = self.ctx.gp_chaos_search(model, best, self.xi, torch.tensor(z, dtype=f64, device=dev), tk,
+                                                      q, n_global=self.n_global, n_local=self.n_local,
+                                                      centres=self.centres, radius0=self.radius0, shrink=self.shrink,
+                                                      exclusion=self.exclusion, per_step=per_step)
+            return props.cpu().numpy(), vmax, nq
 
         def ei_of(U):
             return self.ctx.gp_ei(model, torch.as_tensor(U, device=dev), best, self.xi).cpu().numpy()
 
-        def local(zl, C, Ce, r0):
-            f64 = torch.float64
-            pts, vals = self.ctx.gp_chaos_local(model, best, self.xi, torch.tensor(zl, dtype=f64, device=dev),
-                                                torch.tensor(C, dtype=f64, device=dev),
-                                                torch.tensor(Ce, dtype=f64, device=dev), r0, self.shrink,
-                                                self.n_local)
-            return pts.cpu().numpy(), vals.cpu().numpy()
-
         return chaotic_acquire(ei_of, z, q, taken, n_global=self.n_global, n_local=self.n_local,
                                centres=self.centres, radius0=self.radius0, shrink=self.shrink,
-                               exclusion=self.exclusion, per_step=max(4 * q, 256),
-                               local=local if self.device_search else None)
+                               exclusion=self.exclusion, per_step=per_step)
 
     # ---- the loop -------------------------------------------------------------------------------
     def step(self) -> Cycle:

@@ -161,6 +161,205 @@ __global__ __launch_bounds__(256) void k_chaos_step(double *__restrict__ z, int 
     z[t] = (4.0 * v) * (1.0 - v);
 }
 
+// ------------------------------------------------------------------ pools and greedy choice
+// The order of the search's selections: larger value first, lower index on ties (as a stable sort in
+// decreasing value). Values are taken to be finite.
+__device__ __forceinline__ bool ranks_before(double va, int ia, double vb, int ib) {
+    return va > vb || (va == vb && ia < ib);
+}
+
+// Bitonic sort of n = 2^k (value, index) pairs in LDS by ranks_before (by_index: indices ascending).
+__device__ void lds_bitonic(double *sv, int *si, int n, bool by_index) {
+    for (int k = 2; k <= n; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n; t += blockDim.x) {
+                const int u = t ^ j;
+                if (u <= t) continue;
+                const bool asc = (t & k) == 0;  // this pair's run is ordered ascending in rank
+                const bool ut = by_index ? si[u] < si[t] : ranks_before(sv[u], si[u], sv[t], si[t]);
+                const bool tu = by_index ? si[t] < si[u] : ranks_before(sv[t], si[t], sv[u], si[u]);
+                if (asc ? ut : tu) {
+                    const double v = sv[t];
+                    sv[t] = sv[u];
+                    sv[u] = v;
+                    const int i = si[t];
+                    si[t] = si[u];
+                    si[u] = i;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// One workgroup per round: the `keep` highest-ranked of the round's M values, written in index order
+// (values and their points) to the round's pool slot of min(M, keep) entries. M <= kPoolMax.
+__global__ __launch_bounds__(1024) void k_pool_top(const double *__restrict__ pts, const double *__restrict__ vals,
+                                                   int M, int d, int keep, double *__restrict__ pool_pts,
+                                                   double *__restrict__ pool_vals) {
+    __shared__ double sv[kPoolMax];
+    __shared__ int si[kPoolMax];
+    const int r = blockIdx.x;
+    const int kept = M < keep ? M : keep;
+    const double *v = vals + (size_t)r * M;
+    const double *p = pts + (size_t)r * M * d;
+    double *ov = pool_vals + (size_t)r * kept;
+    double *op = pool_pts + (size_t)r * kept * d;
+    if (M > keep) {
+        int n = 1;
+        while (n < M) n <<= 1;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            sv[t] = t < M ? v[t] : -INFINITY;
+            si[t] = t < M ? t : 0x7fffffff;
+        }
+        __syncthreads();
+        lds_bitonic(sv, si, n, false);
+        // the first `keep` are the selection; put them back in index order
+        int m = 1;
+        while (m < keep) m <<= 1;
+        for (int t = keep + threadIdx.x; t < m; t += blockDim.x) si[t] = 0x7fffffff;
+        __syncthreads();
+        lds_bitonic(sv, si, m, true);
+    } else {
+        for (int t = threadIdx.x; t < M; t += blockDim.x) si[t] = t;
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < kept * d; t += blockDim.x) {
+        const int row = t / d, k = t - row * d;
+        op[t] = p[(size_t)si[row] * d + k];
+    }
+    for (int t = threadIdx.x; t < kept; t += blockDim.x) ov[t] = v[si[t]];
+}
+
+// Squared distance of two d-vectors, in coordinate order.
+__device__ __forceinline__ double dist2(const double *a, const double *b, int d) {
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double e = a[k] - b[k];
+        s += e * e;
+    }
+    return s;
+}
+
+// One workgroup: up to q pool entries in rank order, each at least sqrt(ex2) from the rows of `taken`
+// and from the entries chosen before it (a greedy choice: the best remaining entry is chosen and every
+// entry nearer than the exclusion to it is dropped). idx[0..count) receive the choices in order; *vmax
+// the largest pool value. N <= kGreedyMax.
+__global__ __launch_bounds__(1024) void k_greedy(const double *__restrict__ pts, const double *__restrict__ vals,
+                                                 int N, int d, const double *__restrict__ taken, int T, int q,
+                                                 double ex2, int *__restrict__ idx, int *__restrict__ count,
+                                                 double *__restrict__ vmax) {
+    __shared__ unsigned char alive[kGreedyMax];
+    __shared__ double wv[32];
+    __shared__ int wi[32];
+    __shared__ int pick;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    double mx = -INFINITY;
+    for (int i = tid; i < N; i += blockDim.x) {
+        const double *pi = pts + (size_t)i * d;
+        bool ok = true;
+        for (int t = 0; ok && t < T; ++t) ok = !(dist2(pi, taken + (size_t)t * d, d) < ex2);
+        alive[i] = ok ? 1 : 0;
+        mx = fmax(mx, vals[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (lane == 0) wv[wave] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = wv[0];
+        for (int w = 1; w < nw; ++w) m = fmax(m, wv[w]);
+        *vmax = m;
+    }
+    int n = 0;
+    for (int it = 0; it < q; ++it) {
+        __syncthreads();  // alive[] updated, wv[] free
+        double bv = -INFINITY;
+        int bi = 0x7fffffff;
+        for (int i = tid; i < N; i += blockDim.x)
+            if (alive[i] && ranks_before(vals[i], i, bv, bi)) {
+                bv = vals[i];
+                bi = i;
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ranks_before(ov, oi, bv, bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wv[wave] = bv;
+            wi[wave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = wv[0];
+            int i = wi[0];
+            for (int w = 1; w < nw; ++w)
+                if (ranks_before(wv[w], wi[w], v, i)) {
+                    v = wv[w];
+                    i = wi[w];
+                }
+            pick = (i == 0x7fffffff) ? -1 : i;
+            if (i != 0x7fffffff) idx[n] = i;
+        }
+        __syncthreads();
+        const int pk = pick;
+        if (pk < 0) break;
+        ++n;
+        const double *pp = pts + (size_t)pk * d;
+        for (int i = tid; i < N; i += blockDim.x)
+            if (alive[i] && (i == pk || dist2(pts + (size_t)i * d, pp, d) < ex2)) alive[i] = 0;
+    }
+    if (tid == 0) *count = n;
+}
+
+// dst rows r = src rows idx[r] (r < *count, at most rows), and the matching values if vdst.
+__global__ __launch_bounds__(256) void k_take_rows(const double *__restrict__ src, const double *__restrict__ vsrc,
+                                                   const int *__restrict__ idx, const int *__restrict__ count,
+                                                   int rows, int d, double *__restrict__ dst, double *__restrict__ vdst) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * d) return;
+    const int r = t / d, k = t - r * d;
+    if (r >= *count) return;
+    dst[t] = src[(size_t)idx[r] * d + k];
+    if (vdst && k == 0) vdst[r] = vsrc[idx[r]];
+}
+
+__global__ __launch_bounds__(256) void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] = src[t];
+}
+
+hipError_t launch_pool_top(const double *pts, const double *vals, int rounds, int M, int d, int keep, double *pool_pts,
+                           double *pool_vals, hipStream_t st) {
+    if (M > kPoolMax || keep < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pool_top, dim3((unsigned)rounds), dim3(1024), 0, st, pts, vals, M, d, keep, pool_pts,
+                       pool_vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_greedy(const double *pts, const double *vals, int N, int d, const double *taken, int T, int q,
+                         double ex2, int *idx, int *count, double *vmax, hipStream_t st) {
+    if (N > kGreedyMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(1024), 0, st, pts, vals, N, d, taken, T, q, ex2, idx, count, vmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_take_rows(const double *src, const double *vsrc, const int *idx, const int *count, int rows, int d,
+                            double *dst, double *vdst, hipStream_t st) {
+    const int n = rows * d;
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_take_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, vsrc, idx, count, rows,
+                       d, dst, vdst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_chaos_points(const double *z, const double *C, double r, int per, int nc, int d, double *U,
                                hipStream_t st) {
     const int count = per * nc * d;

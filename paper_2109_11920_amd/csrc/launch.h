@@ -254,6 +254,16 @@ hipError_t launch_chaos_points(const double *z, const double *C, double r, int p
 hipError_t launch_chaos_centres(const double *U, const double *e, int per, int nc, int d, double *C, double *Ce,
                                 hipStream_t st);
 hipError_t launch_chaos_step(double *z, int count, hipStream_t st);
+// Pools and greedy choice of the acquisition search (kernels_gp.hip)
+constexpr int kPoolMax = 8192;     // values per round a pool is taken from
+constexpr int kGreedyMax = 32768;  // pool entries of one greedy choice
+hipError_t launch_pool_top(const double *pts, const double *vals, int rounds, int M, int d, int keep, double *pool_pts,
+                           double *pool_vals, hipStream_t st);
+hipError_t launch_greedy(const double *pts, const double *vals, int N, int d, const double *taken, int T, int q,
+                         double ex2, int *idx, int *count, double *vmax, hipStream_t st);
+hipError_t launch_take_rows(const double *src, const double *vsrc, const int *idx, const int *count, int rows, int d,
+                            double *dst, double *vdst, hipStream_t st);
+hipError_t launch_copy_f64(const double *src, double *dst, int n, hipStream_t st);
 hipError_t launch_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs,
                              hipStream_t st);
 

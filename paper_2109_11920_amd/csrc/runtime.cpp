@@ -1599,6 +1599,28 @@ boac_status boac_gp_ei(boac_ctx *ctx, const boac_gp_info *info, const double *d_
     return timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); });
 }
 
+// The local rounds of the acquisition search: n_local rounds of points, EI, centre moves and chain steps
+// (the chains split evenly over nc centres, per = P / nc each), writing each round's points and values.
+static boac_status chaos_local_rounds(boac_ctx *ctx, GpEiArgs a, double *d_z, int P, double *d_centres,
+                                      double *d_centre_ei, int nc, double radius0, double shrink, int n_local,
+                                      double *d_pts, double *d_vals, hipStream_t st) {
+    const int per = P / nc, M = per * nc, d = a.d;
+    double r = radius0;
+    for (int t = 0; t < n_local; ++t) {
+        double *U = d_pts + (size_t)t * M * d;
+        double *e = d_vals + (size_t)t * M;
+        HIP_TRY(launch_chaos_points(d_z, d_centres, r, per, nc, d, U, st));
+        a.q = U;
+        a.ei = e;
+        a.mu = a.sd = nullptr;
+        BOAC_TRY(timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); }));
+        HIP_TRY(launch_chaos_centres(U, e, per, nc, d, d_centres, d_centre_ei, st));
+        HIP_TRY(launch_chaos_step(d_z, P * d, st));
+        r *= shrink;
+    }
+    return BOAC_OK;
+}
+
 boac_status boac_gp_chaos_local(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
                                 const double *d_alpha, double best, double xi, double *d_z, int32_t P,
                                 double *d_centres, double *d_centre_ei, int32_t n_centres, double radius0,
@@ -1622,20 +1644,99 @@ boac_status boac_gp_chaos_local(boac_ctx *ctx, const boac_gp_info *info, const d
         return fail(BOAC_EINVAL, "P x d or n_local x M x d too large");
     CTX_CHECK();
     BOAC_TRY(gp_ei_scratch(ctx, &a));
+    return chaos_local_rounds(ctx, a, d_z, P, d_centres, d_centre_ei, n_centres, radius0, shrink, n_local, d_pts,
+                              d_vals, (hipStream_t)stream);
+}
+
+boac_status boac_gp_chaos_search(boac_ctx *ctx, const boac_gp_info *info, const double *d_u, const double *d_linv,
+                                 const double *d_alpha, double best, double xi, const double *d_z0, int32_t P,
+                                 int32_t n_global, int32_t n_local, int32_t centres, int32_t q, double radius0,
+                                 double shrink, double exclusion, int32_t per_step, const double *d_taken,
+                                 int32_t T, double *d_props, int32_t *h_count, double *h_max, int64_t *h_queries,
+                                 void *stream) {
+    if (P < 1 || P > kPoolMax) return fail(BOAC_EINVAL, "P = %d chains outside [1, %d]", P, kPoolMax);
+    if (n_global < 1 || n_global > 4096 || n_local < 0 || n_local > 4096)
+        return fail(BOAC_EINVAL, "n_global = %d or n_local = %d outside [1, 4096] / [0, 4096]", n_global, n_local);
+    if (centres < 1 || q < 1 || per_step < 1 || T < 0)
+        return fail(BOAC_EINVAL, "centres, q and per_step must be >= 1 and T >= 0");
+    if (!std::isfinite(radius0) || !(radius0 >= 0.0) || !std::isfinite(shrink) || !(shrink >= 0.0) ||
+        !std::isfinite(exclusion) || !(exclusion >= 0.0))
+        return fail(BOAC_EINVAL, "radius0, shrink and exclusion must be finite and >= 0");
+    const long kept = std::min(P, per_step);
+    const long npool = kept * ((long)n_global + n_local);
+    if (npool > kGreedyMax)
+        return fail(BOAC_EINVAL, "pool of %ld entries above %d: fewer rounds or a smaller per_step", npool, kGreedyMax);
+    if ((long)n_global * P > (1L << 20)) return fail(BOAC_EINVAL, "n_global x P above 2^20 queries");
+    BOAC_TRY(check_ptr(d_z0, "d_z0"));
+    BOAC_TRY(check_ptr(d_taken, "d_taken", T == 0));
+    BOAC_TRY(check_ptr(d_props, "d_props"));
+    if (!h_count || !h_max || !h_queries) return fail(BOAC_EINVAL, "h_count, h_max and h_queries must be given");
+    GpEiArgs ag{};
+    BOAC_TRY(gp_ei_args(info, d_u, d_linv, d_alpha, n_global * P, best, xi, &ag));
+    const int d = ag.d;
+    const int nc_max = std::min(std::max(centres, q), P);
+    CTX_CHECK();
     const hipStream_t st = (hipStream_t)stream;
-    double r = radius0;
-    for (int t = 0; t < n_local; ++t) {
-        double *U = d_pts + (size_t)t * M * d;
-        double *e = d_vals + (size_t)t * M;
-        HIP_TRY(launch_chaos_points(d_z, d_centres, r, per, n_centres, d, U, st));
-        a.q = U;
-        a.ei = e;
-        a.mu = a.sd = nullptr;
-        BOAC_TRY(timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(a, st); }));
-        HIP_TRY(launch_chaos_centres(U, e, per, n_centres, d, d_centres, d_centre_ei, st));
-        HIP_TRY(launch_chaos_step(d_z, P * d, st));
-        r *= shrink;
+    double *z = nullptr, *gpts = nullptr, *gvals = nullptr, *lpts = nullptr, *lvals = nullptr, *pool = nullptr,
+           *poolv = nullptr, *C = nullptr, *Ce = nullptr, *vmax = nullptr;
+    int *idx = nullptr, *cnt = nullptr;
+    BOAC_TRY(ensure_t(ctx, "gs_z", (size_t)P * d, &z));
+    BOAC_TRY(ensure_t(ctx, "gs_gpts", (size_t)n_global * P * d, &gpts));
+    BOAC_TRY(ensure_t(ctx, "gs_gvals", (size_t)n_global * P, &gvals));
+    BOAC_TRY(ensure_t(ctx, "gs_lpts", (size_t)std::max(n_local, 1) * P * d, &lpts));
+    BOAC_TRY(ensure_t(ctx, "gs_lvals", (size_t)std::max(n_local, 1) * P, &lvals));
+    BOAC_TRY(ensure_t(ctx, "gs_pool", (size_t)npool * d, &pool));
+    BOAC_TRY(ensure_t(ctx, "gs_poolv", (size_t)npool, &poolv));
+    BOAC_TRY(ensure_t(ctx, "gs_C", (size_t)nc_max * d, &C));
+    BOAC_TRY(ensure_t(ctx, "gs_Ce", (size_t)nc_max, &Ce));
+    BOAC_TRY(ensure_t(ctx, "gs_idx", (size_t)std::max(q, nc_max), &idx));
+    BOAC_TRY(ensure_t(ctx, "gs_cnt", 2, &cnt));
+    BOAC_TRY(ensure_t(ctx, "gs_max", 2, &vmax));
+    BOAC_TRY(gp_ei_scratch(ctx, &ag));
+    // global stage: the chains' points of n_global rounds, their EI in one launch, each round's pool
+    HIP_TRY(launch_copy_f64(d_z0, z, P * d, st));
+    for (int t = 0; t < n_global; ++t) {
+        HIP_TRY(launch_copy_f64(z, gpts + (size_t)t * P * d, P * d, st));
+        HIP_TRY(launch_chaos_step(z, P * d, st));
     }
+    ag.q = gpts;
+    ag.ei = gvals;
+    ag.mu = ag.sd = nullptr;
+    BOAC_TRY(timed(ctx, BOAC_K_GP, 0.0, st, [&] { return launch_gp_ei(ag, st); }));
+    HIP_TRY(launch_pool_top(gpts, gvals, n_global, P, d, per_step, pool, poolv, st));
+    // centres: the greedy choice over the global pool; their count fixes the local stage's split
+    const int ng = (int)(kept * n_global);
+    HIP_TRY(launch_greedy(pool, poolv, ng, d, nullptr, 0, nc_max, exclusion * exclusion, idx, cnt, vmax, st));
+    int nc = 0;
+    HIP_TRY(hipMemcpyAsync(&nc, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nc < 1) return fail(BOAC_EINVAL, "no finite acquisition value in the global stage");
+    HIP_TRY(launch_take_rows(pool, poolv, idx, cnt, nc, d, C, Ce, st));
+    // local stage and its pools
+    const int M = (P / nc) * nc;
+    long long nq = (long long)n_global * P;
+    int nl_pool = 0;
+    if (n_local > 0) {
+        GpEiArgs al{};
+        BOAC_TRY(gp_ei_args(info, d_u, d_linv, d_alpha, M, best, xi, &al));
+        BOAC_TRY(gp_ei_scratch(ctx, &al));
+        BOAC_TRY(chaos_local_rounds(ctx, al, z, P, C, Ce, nc, radius0, shrink, n_local, lpts, lvals, st));
+        HIP_TRY(launch_pool_top(lpts, lvals, n_local, M, d, per_step, pool + (size_t)ng * d, poolv + ng, st));
+        nl_pool = std::min(M, per_step) * n_local;
+        nq += (long long)n_local * M;
+    }
+    // proposals: the greedy choice over every pool, away from the points taken
+    HIP_TRY(launch_greedy(pool, poolv, ng + nl_pool, d, d_taken, T, q, exclusion * exclusion, idx, cnt + 1, vmax + 1,
+                          st));
+    HIP_TRY(launch_take_rows(pool, nullptr, idx, cnt + 1, q, d, d_props, nullptr, st));
+    int count = 0;
+    double mx = 0.0;
+    HIP_TRY(hipMemcpyAsync(&count, cnt + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&mx, vmax + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *h_count = count;
+    *h_max = mx;
+    *h_queries = nq;
     return BOAC_OK;
 }
 

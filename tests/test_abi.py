@@ -138,3 +138,26 @@ def test_device_search_entry_point_validates_before_the_device(lib):
     assert call((1 << 21), 1) == 1 and b"M" in lib.boac_last_error()   # per x n_centres above 2^20
     # valid arguments, no context: refused before any device call
     assert call(64, 8) == 1 and b"context" in lib.boac_last_error()
+
+
+def test_device_whole_search_validates_before_the_device(lib):
+    from paper_2109_11920_amd._lib import BoacGpInfo
+    info = BoacGpInfo(4, 8, 0.5, 1.0, 1e-6, 10.0, 2.0, -3.0)
+    cnt, mx, nq = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+
+    def call(P=512, ng=4, nl=4, centres=8, q=8, r0=0.1, shrink=0.85, excl=0.02, per=64, T=0, taken=None,
+             props=ALIGNED, counts=True):
+        return lib.boac_gp_chaos_search(None, ctypes.byref(info), ALIGNED, ALIGNED, ALIGNED, 1.0, 0.0, ALIGNED, P, ng,
+                                        nl, centres, q, r0, shrink, excl, per, taken, T, props,
+                                        ctypes.byref(cnt) if counts else None, ctypes.byref(mx), ctypes.byref(nq),
+                                        None)
+    assert call(P=0) == 1 and b"chains" in lib.boac_last_error()
+    assert call(P=8193) == 1
+    assert call(ng=0) == 1 and call(nl=-1) == 1
+    assert call(q=0) == 1 and call(per=0) == 1 and call(centres=0) == 1
+    assert call(excl=-1.0) == 1 and call(r0=float("inf")) == 1
+    assert call(P=4096, ng=8, nl=8, per=4096) == 1 and b"pool" in lib.boac_last_error()
+    assert call(T=3) == 1   # taken rows without a pointer
+    assert call(counts=False) == 1
+    # valid arguments, no context: refused before any device call
+    assert call() == 1 and b"context" in lib.boac_last_error()
