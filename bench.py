@@ -101,7 +101,7 @@ def _oracle_worker_eval(args):
 
 def cpu_baseline(workload_S, n_cand, n_iter, workers):
     """The FP64 oracle as it stands on a bounded sample of the batch: one thread, then one process per
-    host core (candidate-parallel, the core count the box grants this job)."""
+    host core (candidate-parallel, the core count granted to this job)."""
     import multiprocessing as mp
 
     import numpy as np
@@ -133,7 +133,7 @@ def cpu_baseline(workload_S, n_cand, n_iter, workers):
                               "sample": f"{n_cand} candidates on one thread, {dt:.1f} s"}}
 
 
-def survey_bytes(n, na, nb, nt, K, paired):
+def full_tensor_bytes(n, na, nb, nt, K, paired):
     """Algorithmic HBM bytes of one candidate's evaluation (K MLEM iterations + objective):
     (2K+3) V + (4K+3) I + (3K+1) Y with V the attenuation tensor, I an image, Y a sinogram (FP32);
     with opposed-ray pairing the tensor is half the angles plus exp(-T) per held ray."""
@@ -145,7 +145,7 @@ def survey_bytes(n, na, nb, nt, K, paired):
     return (2 * K + 3) * V + (4 * K + 3) * I + (3 * K + 1) * Y
 
 
-def gather_survey_bytes(n, na, nb, nt):
+def gather_full_tensor_bytes(n, na, nb, nt):
     """Algorithmic bytes of one candidate's MLEM backprojection-and-update (V + Y + 3I, full tensor)."""
     return 4.0 * (na * nb * nt + na * nb + 3 * n * n)
 
@@ -185,7 +185,7 @@ def plain_line(ctx, g, S, theta, dev, reps=10):
     avg = kms / max(cnt, 1)
     ach = by / max(cnt, 1) / (avg / 1e3) / 1e9
     paired = os.environ.get("BOAC_OPPOSED_RAYS", "1") != "0"
-    step = survey_bytes(128, 128, 128, 128, K, paired)
+    step = full_tensor_bytes(128, 128, 128, 128, K, paired)
     return {"value": round(K / (ms / 1e3), 1), "unit": "cand·it/s", "ms_per_evaluation": round(ms, 3),
             "us_per_iteration": round(1e3 * ms / K, 2),
             "kernel_ms_per_evaluation": {k: round(v[1] / reps, 4) for k, v in ks.items() if v[0]},
@@ -514,7 +514,7 @@ def main():
         print("bench.py measures one GPU: candidates are independent and this build has no multi-GPU "
               "path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    # host cores granted to this job (the box's share, which OMP_NUM_THREADS states there), for the
+    # host cores granted to this job (OMP_NUM_THREADS states the share where it is set), for the
     # all-cores oracle leg: one single-threaded process per core
     workers = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1))
     for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
@@ -603,20 +603,20 @@ def main():
     bytes_per_launch = by / max(cnt, 1)
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     paired = os.environ.get("BOAC_OPPOSED_RAYS", "1") != "0"
-    survey_launch = C * gather_survey_bytes(128, 128, 128, 128)
-    step_survey = C * survey_bytes(128, 128, 128, 128, K, False)
-    step_paired = C * survey_bytes(128, 128, 128, 128, K, paired)
+    full_launch = C * gather_full_tensor_bytes(128, 128, 128, 128)
+    step_full = C * full_tensor_bytes(128, 128, 128, 128, K, False)
+    step_paired = C * full_tensor_bytes(128, 128, 128, 128, K, paired)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, "batch256_n128"),
             "kernel": kernel_name(dom, C), "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bytes_per_launch,
             "launches": cnt,
             "bytes_convention": "achieved/frac: the bytes this kernel must move as built (with opposed-ray "
                                 "pairing the held half of the attenuation tensor plus exp(-T) per ray, the "
-                                "ratio sinogram, F and s read, F written); frac_survey_bytes: the full-tensor "
+                                "ratio sinogram, F and s read, F written); frac_full_tensor_bytes: the full-tensor "
                                 "count V + Y + 3I per candidate over the same time",
-            "frac_survey_bytes": round(survey_launch / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "step": {"survey_bytes": step_survey, "paired_bytes": step_paired,
-                     "frac_survey_bytes": round(step_survey / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_full_tensor_bytes": round(full_launch / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step": {"full_tensor_bytes": step_full, "paired_bytes": step_paired,
+                     "frac_full_tensor_bytes": round(step_full / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "frac_paired_bytes": round(step_paired / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                      "what": "whole step: (2K+3) V + (4K+3) I + (3K+1) Y per candidate over the step time; "
                              "paired: V -> V/2 + exp(-T) per held ray"}}
