@@ -141,7 +141,9 @@ def test_device_local_search_rejects_bad_sizes(ctx):
 
 @pytest.mark.parametrize("P,q,centres,n_global,n_local,exclusion,per_step,n_taken",
                          [(512, 12, 8, 6, 10, 0.02, 64, 40), (300, 3, 8, 4, 6, 0.2, 64, 0), (4096, 64, 8, 16, 32, 0.02, 256, 320),
-                          (700, 20, 5, 3, 0, 0.05, 100, 10)])
+                          (700, 20, 5, 3, 0, 0.05, 100, 10),
+                          # every round's points kept (per_step > P), and an exclusion that leaves fewer than q
+                          (200, 64, 8, 3, 4, 1.2, 256, 5)])
 def test_device_search_equals_host_search(ctx, P, q, centres, n_global, n_local, exclusion, per_step, n_taken):
     # the whole acquisition search on the device (boac_gp_chaos_search) against the host search
     # (chaotic_acquire around boac_gp_ei) from the same chains: the same proposals in the same order, the
@@ -169,6 +171,8 @@ def test_device_search_equals_host_search(ctx, P, q, centres, n_global, n_local,
     np.testing.assert_array_equal(zt.cpu().numpy(), z)  # the chains are not modified
     assert nd == nh and vd == vh, (nd, nh, vd, vh)
     np.testing.assert_array_equal(Ud, Uh)
+    if exclusion >= 1.0:
+        assert len(Ud) < q   # the case meant: the pool runs out before q proposals
     print(f"[parity] device search P={P} q={q} rounds {n_global}+{n_local}: {len(Ud)} proposals, largest EI and "
           f"{nd} evaluations identical to the host search", flush=True)
 
