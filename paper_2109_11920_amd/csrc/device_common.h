@@ -406,6 +406,15 @@ __device__ __forceinline__ float4 buffer_ld4(__amdgpu_buffer_rsrc_t r, unsigned 
     const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, uniform_off, 0);
     return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
 }
+// The same load with the non-temporal hint, for data a launch streams once (the ray kernels' walks over
+// the attenuation tensors): the lines are not kept for reuse. Measured on the paired projection of the
+// 256-candidate batch: 197 against 223 us per launch. The gather, whose tiles reuse each other's
+// samples through L2, keeps the plain load (4% slower with the hint).
+__device__ __forceinline__ float4 buffer_ld4_stream(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, uniform_off, 2);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+}
 // Vector store of one float at a per-lane plus a uniform byte offset.
 __device__ __forceinline__ void buffer_st(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, uniform_off, 0);

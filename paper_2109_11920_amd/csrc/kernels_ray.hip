@@ -353,13 +353,13 @@ __device__ __forceinline__ void k_fwd_body(int bid, float *lds, float *red, DevG
                 Comp c2 = PAIRED ? acc2[j] : Comp{0.f, 0.f};
                 float4 cur[KG], nxt[KG];
 #pragma unroll
-                for (int q = 0; q < KG; ++q) cur[q] = (4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, 4 * q)) : z4;
+                for (int q = 0; q < KG; ++q) cur[q] = (4 * q < g.nt) ? buffer_ld4_stream(rs, roff, 4u * att_row(g, 4 * q)) : z4;
                 float tau = -g.cT;
                 for (int k0 = 0; k0 < g.nt; k0 += KC) {
 #pragma unroll
                     for (int q = 0; q < KG; ++q) {
                         const int k = k0 + KC + 4 * q;
-                        nxt[q] = (k < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, k)) : z4;
+                        nxt[q] = (k < g.nt) ? buffer_ld4_stream(rs, roff, 4u * att_row(g, k)) : z4;
                     }
                     float part = 0.f, part2 = 0.f;
 #pragma unroll
@@ -499,8 +499,8 @@ __device__ __forceinline__ void k_fwd_pair_body(int bid, float *lds, float *red,
         float4 u0[KG], u1[KG], n0[KG], n1[KG];
 #pragma unroll
         for (int q = 0; q < KG; ++q) {
-            u0[q] = (4 * q < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, 4 * q)) : z4;
-            u1[q] = (4 * q < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, 4 * q)) : z4;
+            u0[q] = (4 * q < g.nt) ? buffer_ld4_stream(r0, roff, 4u * att_row(g, 4 * q)) : z4;
+            u1[q] = (4 * q < g.nt) ? buffer_ld4_stream(r1, roff, 4u * att_row(g, 4 * q)) : z4;
         }
         Comp s0 = acc0[j], s1 = acc1[j], t0 = opp0[j], t1 = opp1[j];
         float tau = -g.cT;
@@ -508,8 +508,8 @@ __device__ __forceinline__ void k_fwd_pair_body(int bid, float *lds, float *red,
 #pragma unroll
             for (int q = 0; q < KG; ++q) {
                 const int k = k0 + KC + 4 * q;
-                n0[q] = (k < g.nt) ? buffer_ld4(r0, roff, 4u * att_row(g, k)) : z4;
-                n1[q] = (k < g.nt) ? buffer_ld4(r1, roff, 4u * att_row(g, k)) : z4;
+                n0[q] = (k < g.nt) ? buffer_ld4_stream(r0, roff, 4u * att_row(g, k)) : z4;
+                n1[q] = (k < g.nt) ? buffer_ld4_stream(r1, roff, 4u * att_row(g, k)) : z4;
             }
             float p0 = 0.f, p1 = 0.f, o0 = 0.f, o1 = 0.f;
 #pragma unroll
@@ -648,8 +648,8 @@ __device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g,
 #pragma unroll
                 for (int q = 0; q < KG; ++q) {
                     const unsigned o = 4u * att_row(g, 4 * q);
-                    at[q] = (4 * q < g.nt) ? buffer_ld4(ra, roff, o) : z4;
-                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
+                    at[q] = (4 * q < g.nt) ? buffer_ld4_stream(ra, roff, o) : z4;
+                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4_stream(rb, roff, o) : z4;
                 }
                 const size_t si2 = cand * A.sino_cs + (size_t)((a + g.nah) * g.nb + (g.nb - 1 - b));
                 const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
@@ -662,8 +662,8 @@ __device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g,
                     for (int q = 0; q < KG; ++q) {
                         const int k = k0 + KC + 4 * q;
                         const unsigned o = 4u * att_row(g, k);
-                        an[q] = (k < g.nt) ? buffer_ld4(ra, roff, o) : z4;
-                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
+                        an[q] = (k < g.nt) ? buffer_ld4_stream(ra, roff, o) : z4;
+                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4_stream(rb, roff, o) : z4;
                     }
                     float part = 0.f, part2 = 0.f, epart = 0.f;
                     float ov[4];
@@ -864,8 +864,8 @@ __device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, cons
 #pragma unroll
                 for (int q = 0; q < KG; ++q) {
                     const unsigned o = 4u * att_row(g, 4 * q);
-                    at[q] = (4 * q < g.nt) ? buffer_ld4(ra, roff, o) : z4;
-                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4(rb, roff, o) : z4;
+                    at[q] = (4 * q < g.nt) ? buffer_ld4_stream(ra, roff, o) : z4;
+                    bt[q] = (A.accumulate && 4 * q < g.nt) ? buffer_ld4_stream(rb, roff, o) : z4;
                 }
                 Comp P{0.f, 0.f};
                 const float e_ray = PAIRED ? A.E[cand * A.e_cs + ray] : 0.f;
@@ -878,8 +878,8 @@ __device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, cons
                     for (int q = 0; q < KG; ++q) {
                         const int k = k0 + KC + 4 * q;
                         const unsigned o = 4u * att_row(g, k);
-                        an[q] = (k < g.nt) ? buffer_ld4(ra, roff, o) : z4;
-                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4(rb, roff, o) : z4;
+                        an[q] = (k < g.nt) ? buffer_ld4_stream(ra, roff, o) : z4;
+                        bn[q] = (A.accumulate && k < g.nt) ? buffer_ld4_stream(rb, roff, o) : z4;
                     }
                     float ov[4];
                     float epart = 0.f;
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(DevGeom g, Band band, int chu
         const int k0 = ck * KC;
         float4 v[KG];
 #pragma unroll
-        for (int q = 0; q < KG; ++q) v[q] = (k0 + 4 * q < g.nt) ? buffer_ld4(rs, roff, 4u * att_row(g, k0 + 4 * q)) : z4;
+        for (int q = 0; q < KG; ++q) v[q] = (k0 + 4 * q < g.nt) ? buffer_ld4_stream(rs, roff, 4u * att_row(g, k0 + 4 * q)) : z4;
         float tau = (float)k0 - g.cT;
         float p = 0.f, p2 = 0.f;
 #pragma unroll
