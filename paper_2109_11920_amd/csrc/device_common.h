@@ -425,6 +425,15 @@ __device__ __forceinline__ void buffer_st4(__amdgpu_buffer_rsrc_t r, unsigned by
     const u4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
     __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, uniform_off, 0);
 }
+// The same store with the non-temporal hint, for the single-stage ray kernels' streams written once per
+// launch (the attenuation build's tensor, the reverse sweep's and tail's adjoint): measured 1-2% faster
+// on those kernels.
+__device__ __forceinline__ void buffer_st4_stream(__amdgpu_buffer_rsrc_t r, unsigned byte_off, unsigned uniform_off,
+                                                  float4 v) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, uniform_off, 2);
+}
 // Component q (0..3, a compile-time constant after unrolling) of v.
 __device__ __forceinline__ float f4at(const float4 &v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
 

@@ -246,7 +246,7 @@ __device__ __forceinline__ void k_att_scan_body(int bid, float *lds, DevGeom g, 
                         comp_add(T, m[q]);
                     }
                 }
-                buffer_st4(rs, roff + 4u * att_row(g, 4 * grp), 0u, make_float4(e[0], e[1], e[2], e[3]));
+                buffer_st4_stream(rs, roff + 4u * att_row(g, 4 * grp), 0u, make_float4(e[0], e[1], e[2], e[3]));
             }
             comp_merge(carry, total);
         }
@@ -695,7 +695,7 @@ __device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g,
                         }
                         tau += 1.f;
                         if ((q & 3) == 3 && k - 3 < g.nt)
-                            buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
+                            buffer_st4_stream(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     kahan_add(c, part);
                     if constexpr (PAIRED) {
@@ -912,7 +912,7 @@ __device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, cons
                         }
                         tau += 1.f;
                         if ((q & 3) == 3 && k - 3 < g.nt)
-                            buffer_st4(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
+                            buffer_st4_stream(rb, roff, 4u * att_row(g, k - 3), make_float4(ov[0], ov[1], ov[2], ov[3]));
                     }
                     if constexpr (PAIRED) kahan_add(eb, epart);
 #pragma unroll
