@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import argparse
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -39,15 +40,43 @@ def common_flags():
             "-I", os.path.join(HERE, "..", "include"), "-I", CSRC]
 
 
+# Translation units whose kernels may use scratch memory: the persistent executor inlines every kernel
+# body into one kernel under a 128-register budget, so it spills; every other kernel must not (a spill
+# there means an accumulator array left unrolled, which multiplies its memory traffic).
+SCRATCH_ALLOWED = {"kernels_persist.hip"}
+
+
+def scratch_kernels(remarks: str):
+    """(kernel, bytes per lane) of the kernels whose resource-usage remarks report scratch memory."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            out.append((name, int(m.group(1))))
+    return out
+
+
 def compile_one(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc()] + common_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile {src} failed:\n{r.stdout}\n{r.stderr}")
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
+    if src.endswith(".hip") and src not in SCRATCH_ALLOWED:
+        bad = scratch_kernels(r.stderr)
+        if bad:
+            raise RuntimeError(f"compile {src}: kernels use scratch memory (spilled or unrolled-array registers): "
+                               + ", ".join(f"{k} {b} B/lane" for k, b in bad))
+    err = "\n".join(l for l in r.stderr.splitlines()
+                    if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l and l.strip())
     if err and verbose:
         print(err, file=sys.stderr)
     return obj
