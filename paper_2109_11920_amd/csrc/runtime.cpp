@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/boac.h"
@@ -1515,14 +1517,32 @@ boac_status boac_gp_fit(const double *h_u, const double *h_y, int32_t n, int32_t
         ys[r] = h_y[idx[r]];
         for (int c = 0; c < d; ++c) us[(size_t)r * d + c] = h_u[(size_t)idx[r] * d + c];
     }
+    // the grid's fits are independent: up to 16 host threads take them in turn, each with its own
+    // factor; the choice below runs over the results in grid order (first on ties), as a serial loop
+    std::vector<double> lmls(n_lengths, 0.0);
+    std::vector<char> ok(n_lengths, 0);
+    const int nthreads = std::max(1, std::min({n_lengths, 16, (int)std::thread::hardware_concurrency()}));
+    std::atomic<int> next{0};
+    auto worker = [&] {
+        std::vector<double> Lw((size_t)ns * ns), aw(ns);
+        double mw, sw, lw;
+        for (int g = next++; g < n_lengths; g = next++) {
+            ok[g] = gp_fit_fixed(us.data(), ys.data(), ns, d, h_lengths[g], 1.0, noise, Lw.data(), aw.data(), &mw, &sw,
+                                 &lw);
+            lmls[g] = lw;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
     int best = -1;
     double best_lml = 0.0, m0, s, lml;
     for (int g = 0; g < n_lengths; ++g) {
-        if (!gp_fit_fixed(us.data(), ys.data(), ns, d, h_lengths[g], 1.0, noise, L.data(), al.data(), &m0, &s, &lml))
-            continue;
-        if (best < 0 || lml > best_lml) {
+        if (!ok[g]) continue;
+        if (best < 0 || lmls[g] > best_lml) {
             best = g;
-            best_lml = lml;
+            best_lml = lmls[g];
         }
     }
     if (best < 0) return fail(BOAC_EINVAL, "no length-scale gives a positive definite covariance; raise noise");
