@@ -148,7 +148,7 @@ __device__ void run_task(const TaskRec &T, int item, float *lds, float *red) {
         }
         case T_ATT_SCAN: {
             const auto &A = T.u.att;
-            k_att_scan_body(item, lds, A.r.g, A.r.bands.b[0], A.passes, A.r.chunks, A.r.C, A.mu, A.att, A.img_cs,
+            k_att_scan_body(item, lds, A.r.g, A.r.bands.band(0, A.r.g.n), A.passes, A.r.chunks, A.r.C, A.mu, A.att, A.img_cs,
                             A.att_cs, A.E, A.e_cs);
             break;
         }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void k_att_body(int bid, float *lds, DevGeom g, const
     float *out = att + cand * att_cs;
 
     for (int bi = 0; bi < bands.count; ++bi) {
-        const Band band = bands.b[bi];
+        const Band band = bands.band(bi, g.n);
         __syncthreads();
         stage_band<1>(img, g.n, band, lds);
         __syncthreads();
@@ -322,7 +322,7 @@ __device__ __forceinline__ void k_fwd_body(int bid, float *lds, float *red, DevG
     for (int j = 0; j < (PAIRED ? kMaxRpt : 1); ++j) acc2[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
-        const Band band = bands.b[bi];
+        const Band band = bands.band(bi, g.n);
         __syncthreads();
         if (A.img_comps == 1)
             stage_band<1>(img, g.n, band, lds);
@@ -473,7 +473,7 @@ __device__ __forceinline__ void k_fwd_pair_body(int bid, float *lds, float *red,
     const int nrays = g.nah * g.nb;
     const int pitch = g.n + 3;
     const float nf = (float)g.n;
-    stage_band_pair(A.img + c0 * A.img_cs, A.img + c1 * A.img_cs, g.n, bands.b[0], lds);
+    stage_band_pair(A.img + c0 * A.img_cs, A.img + c1 * A.img_cs, g.n, bands.band(0, g.n), lds);
     __syncthreads();
     const float2 *lds2 = reinterpret_cast<const float2 *>(lds);
     const __amdgpu_buffer_rsrc_t r0 = buffer_rsrc(A.att + c0 * A.att_cs, (unsigned)(4 * A.att_cs));
@@ -616,7 +616,7 @@ __device__ __forceinline__ void k_adj_sweep_body(int bid, float *lds, DevGeom g,
     for (int j = 0; j < kMaxRpt; ++j) acc[j] = acc2[j] = ebj[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
-        const Band band = bands.b[bi];
+        const Band band = bands.band(bi, g.n);
         __syncthreads();
         stage_band<2>(img, g.n, band, lds);
         __syncthreads();
@@ -838,7 +838,7 @@ __device__ __forceinline__ void k_tail_body(int bid, float *lds, DevGeom g, cons
     for (int j = 0; j < kMaxRpt; ++j) ebj[j] = Comp{0.f, 0.f};
 
     for (int bi = 0; bi < bands.count; ++bi) {
-        const Band band = bands.b[bi];
+        const Band band = bands.band(bi, g.n);
         __syncthreads();
         stage_band<2>(img, g.n, band, lds);
         __syncthreads();
@@ -1143,7 +1143,7 @@ hipError_t launch_att(const DevGeom &g, const RayCfg &rc, const Bands &bands, co
     if (rc.single && rc.scan_passes > 0) {
         if (rc.scan_block % 64 != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_att_scan, dim3((unsigned)(rc.scan_chunks * C)), dim3(rc.scan_block), rc.lds, st, g,
-                           bands.b[0], rc.scan_passes, rc.scan_chunks, C, mu, att, img_cs, att_cs, E, e_cs);
+                           bands.band(0, g.n), rc.scan_passes, rc.scan_chunks, C, mu, att, img_cs, att_cs, E, e_cs);
         return hipGetLastError();
     }
     if (rc.single)
@@ -1161,7 +1161,7 @@ static void fwd_mode(const DevGeom &g, const RayCfg &rc, const Bands &bands, con
     if constexpr (MODE != FWD_NLL) {
         if (rc.split_chunks > 0 && rc.single && a.img_comps == 1 && g.nt <= 16 * kSplitLanes * kSplitCpl) {
             hipLaunchKernelGGL((k_fwd_split<MODE, PAIRED>), dim3((unsigned)(rc.split_chunks * C)), dim3(256), rc.lds,
-                               st, g, bands.b[0], rc.split_chunks, C, a);
+                               st, g, bands.band(0, g.n), rc.split_chunks, C, a);
             return;
         }
     }

@@ -11,10 +11,16 @@
 
 namespace boac {
 
-constexpr int kMaxBands = 16;
+// Row bands of an n x n image, uniform: band i is assigned rows [-1 + i rows, -1 + (i + 1) rows),
+// clipped to n + 1; one band (rows = n + 2) when the whole image fits one LDS stage.
 struct Bands {
     int count;
-    Band b[kMaxBands];
+    int rows;
+    __host__ __device__ Band band(int i, int n) const {
+        const int lo = -1 + i * rows;
+        const int hi = lo + rows < n + 1 ? lo + rows : n + 1;
+        return Band{lo, hi, i == 0, i == count - 1};
+    }
 };
 
 // A ray-kernel launch covers `cand` candidates of one slice, each with n_angles * n_bins rays split

@@ -447,29 +447,24 @@ static boac_status dev_geom(boac_ctx *ctx, const boac_geom &g, DevGeom *dg) {
 }
 
 // ------------------------------------------------------------------ plans
+// Row bands needed to stage an n x n image of `comps` float components (columns -1..n+1) within
+// the LDS budget: 1 when the whole image fits.
+static constexpr int band_count(int n, int comps) {
+    const size_t pitch_bytes = (size_t)(n + 3) * 4 * comps;
+    if (pitch_bytes * (n + 3) <= kLdsBudget) return 1;
+    const int rows = (int)(kLdsBudget / pitch_bytes) - 1;  // assigned rows per band (staged = rows + 1)
+    return (n + 2 + rows - 1) / rows;                     // assigned range [-1, n+1)
+}
 static void make_bands(int n, int comps, RayCfg *rc, Bands *bands) {
     const size_t pitch_bytes = (size_t)(n + 3) * 4 * comps;
-    const size_t full = pitch_bytes * (n + 3);
-    if (full <= kLdsBudget) {
-        rc->single = true;
-        bands->count = 1;
-        bands->b[0] = Band{-1, n + 1, true, true};
-        rc->lds = full;
-        return;
-    }
-    rc->single = false;
-    int rows = (int)(kLdsBudget / pitch_bytes) - 1;  // assigned rows per band (staged = rows + 1)
-    const int span = n + 2;                           // assigned range [-1, n+1)
-    int count = (span + rows - 1) / rows;
-    if (count > kMaxBands) count = kMaxBands;
-    rows = (span + count - 1) / count;
+    const int count = band_count(n, comps);
+    const int span = n + 2;  // assigned range [-1, n+1)
+    // the same number of bands with rows spread evenly: the last band is not empty and no band
+    // stages more rows than band_count allowed for
     bands->count = count;
-    for (int i = 0; i < count; ++i) {
-        const int lo = -1 + i * rows;
-        const int hi = std::min(-1 + (i + 1) * rows, n + 1);
-        bands->b[i] = Band{lo, hi, i == 0, i == count - 1};
-    }
-    rc->lds = pitch_bytes * (size_t)(rows + 1);
+    bands->rows = (span + count - 1) / count;
+    rc->single = count == 1;
+    rc->lds = pitch_bytes * (size_t)(bands->rows + 1);
 }
 
 static std::string shape_key(const char *kind, const boac_geom &g, int C, int extra) {

@@ -129,6 +129,27 @@ def test_banded_large_images(ctx, n):
         report(f"banded backproject n={n} cand {c}", x[c], oracle.backproject(og, att, z[c]), TOL)
 
 
+@pytest.mark.parametrize("shape", [(640, 8, 640, 640), (1024, 4, 1024, 1024)])
+def test_many_row_bands(ctx, shape):
+    # the largest admitted images: one image takes 11 and 27 row bands, the two-image stage of the
+    # reverse sweeps 22 and 57 (each band still within one workgroup's LDS); the objective, the
+    # unrolled and the envelope gradients against the oracle
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=41)
+    th = cands(42, 2)
+    J, G, st = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 1, 1, mode="unrolled")
+    Je, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 1, 1, mode="envelope")
+    Jf, _, _ = ctx.objective(g, dev(S), dev(th), DR, 1)
+    assert torch.allclose(J, Jf, rtol=2e-6, atol=0) and torch.allclose(Je, Jf, rtol=2e-6, atol=0)
+    J, G, Ge = J.cpu().numpy(), G.cpu().numpy(), Ge.cpu().numpy()
+    for c in range(2):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 1, with_delta_r=True)
+        report(f"bands {shape} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"bands {shape} cand {c} dJ", G[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 1, with_delta_r=True)
+        report(f"bands {shape} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
