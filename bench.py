@@ -260,6 +260,7 @@ def uneven_serial(ctx, dev, slices, wu, replay_ms=None):
     try:
         ctx.reset_stats()
         ctx.set_profiling(True)
+        st.wait_stream(torch.cuda.current_stream(dev))  # calls on one context do not overlap
         with torch.cuda.stream(st):
             ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)
         st.synchronize()
@@ -300,6 +301,7 @@ def uneven_line(ctx, dev, serial=True):
     import torch
     slices, wu = uneven_slices(dev)
     ustream = torch.cuda.Stream(dev)
+    ustream.wait_stream(torch.cuda.current_stream(dev))  # calls on one context do not overlap
     with torch.cuda.stream(ustream):
         ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # runs eagerly, then captures
         ctx.evaluate_batch(slices, DELTA_R, wu.n_iter, wu.ckpt_every)   # graph replay (warm)
@@ -333,6 +335,7 @@ def persistent_line(ctx, g, S, cand, K, dev, steps):
     stream = torch.cuda.Stream(dev)
 
     def timed(slices, k, ck, reps):
+        stream.wait_stream(torch.cuda.current_stream(dev))  # calls on one context do not overlap
         with torch.cuda.stream(stream):
             ctx.evaluate_batch(slices, DELTA_R, k, ck)   # eager run, then capture
             ctx.evaluate_batch(slices, DELTA_R, k, ck)   # replay (warm)
@@ -635,6 +638,7 @@ def main():
         # ---- the same step replayed from a captured HIP graph
         gstream = torch.cuda.Stream(dev)
         sb = [SliceBatch(g, S, cand, torch.empty(C, device=dev), None, torch.empty(C, device=dev, dtype=torch.int32))]
+        gstream.wait_stream(torch.cuda.current_stream(dev))  # calls on one context do not overlap
         with torch.cuda.stream(gstream):
             ctx.evaluate_batch(sb, DELTA_R, K)
             ctx.evaluate_batch(sb, DELTA_R, K)

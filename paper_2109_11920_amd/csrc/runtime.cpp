@@ -481,23 +481,31 @@ constexpr int kFewCand = 8;
 static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg *rc, Bands *bands, int nah) {
     make_bands(g.n, comps, rc, bands);
     const int nrays = nah * g.n_bins;
-    // default: the largest workgroups (the image stage is shared by more waves, and a stage that
-    // fills the LDS still gives 16 waves per CU) and the most rays per thread that still give every
-    // CU a workgroup
-    static const int prefs[][2] = {{1024, 4}, {1024, 2}, {1024, 1}, {512, 1}, {256, 1}};
-    rc->block = 256;
-    rc->rpt = 1;
-    for (const auto &pf : prefs) {
-        const long chunks = (nrays + pf[0] * pf[1] - 1) / (pf[0] * pf[1]);
-        if (chunks * C >= ctx->n_cu) {
-            rc->block = pf[0];
-            rc->rpt = pf[1];
-            break;
-        }
-    }
     // the paired forward projection where both images fit one stage (default on)
     const bool pair_fits = comps == 1 && rc->single && 2 * rc->lds <= kLdsBudget && C >= 2;
     rc->pair = pair_fits;
+    // default: 1024-thread workgroups (the image stage is shared by more waves, and a stage that fills
+    // the LDS still gives 16 waves per CU), one resident per CU; the rays per thread that minimise
+    // (rounds of workgroups over the CUs) x (rays per thread + a fixed cost per workgroup: the image
+    // stage, the first loads and the epilogue, about 0.6 of a ray pass as measured on the paired
+    // projection at 96-192 candidates). A paired projection has one workgroup per chunk and candidate
+    // pair. Where even one ray per thread leaves CUs without a workgroup, smaller workgroups.
+    const long groups = pair_fits ? (C + 1) / 2 : C;
+    rc->block = 1024;
+    rc->rpt = 1;
+    double best = 0.0;
+    for (int rpt : {4, 2, 1}) {
+        const long wgs = (long)((nrays + 1024 * rpt - 1) / (1024 * rpt)) * groups;
+        const double cost = (double)((wgs + ctx->n_cu - 1) / ctx->n_cu) * (rpt + 0.6);
+        if (rpt == 4 || cost < best) {
+            best = cost;
+            rc->rpt = rpt;
+        }
+    }
+    if ((long)((nrays + 1023) / 1024) * groups < ctx->n_cu) {
+        rc->rpt = 1;
+        rc->block = ((long)((nrays + 511) / 512) * groups >= ctx->n_cu) ? 512 : 256;
+    }
     // plan cache entry: [threads per workgroup, rays per thread, paired forward projection]
     auto it = ctx->tune.find(shape_key("ray", g, C, comps));
     if (it != ctx->tune.end() && it->second.size() >= 2) {
@@ -738,6 +746,19 @@ static Sizes sizes_of(const boac_geom &g, int nah = -1) {
 static bool pairing_enabled() {
     const char *e = std::getenv("BOAC_OPPOSED_RAYS");
     return !(e && e[0] == '0');
+}
+
+// The plan switches read from the environment (each on unless set to 0), one bit each: part of a
+// captured batch graph's key, so that a graph is not replayed under other switches.
+static uint64_t plan_switch_bits() {
+    uint64_t bits = 0;
+    int i = 0;
+    for (const char *name : {"BOAC_OPPOSED_RAYS", "BOAC_FWD_SPLIT", "BOAC_ATT_SCAN", "BOAC_GATHER_SPLIT"}) {
+        const char *e = std::getenv(name);
+        if (e && e[0] == '0') bits |= 1ull << i;
+        ++i;
+    }
+    return bits;
 }
 
 // Launch geometry, plan and sizes of one slice for the attenuation-weighted paths (projection,
@@ -1829,9 +1850,13 @@ static boac_status batch_body(boac_ctx *ctx, const boac_slice *h_in, int32_t ns_
     const int32_t ns = (int32_t)parts.size();
     const int L = std::min(batch_lanes(), (int)ns);
     if (L <= 1) {
+        // the first lane's scratch, not the eager entry points' (a batch and an eager call issued on
+        // different streams without ordering between them then do not share buffers)
+        ctx->ns = "L0:";
+        boac_status rs = BOAC_OK;
+        for (int i = 0; i < ns && rs == BOAC_OK; ++i) rs = eval_slice(ctx, h[i], delta_r, K, ck, st);
         ctx->ns.clear();
-        for (int i = 0; i < ns; ++i) BOAC_TRY(eval_slice(ctx, h[i], delta_r, K, ck, st));
-        return BOAC_OK;
+        return rs;
     }
     while ((int)ctx->lanes.size() < L) {
         if (ctx->capturing) return fail(BOAC_EDEVICE, "lane streams must exist before graph capture");
@@ -2070,6 +2095,11 @@ boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32
     }
     key.push_back((uint64_t)ctx->batch_mode);
     key.push_back((uint64_t)persist_spin_limit(ctx));
+    // the schedule's settings (read from the environment on every call)
+    key.push_back((uint64_t)batch_lanes());
+    key.push_back((uint64_t)batch_split());
+    key.push_back((uint64_t)persist_lanes());
+    key.push_back(plan_switch_bits());
     if (ctx->batch_mode == BOAC_BATCH_PERSISTENT)
         return persist_batch(ctx, h_slices, n_slices, delta_r_cm, n_iter, ckpt_every, st, key);
     const bool use_graph = (st != nullptr) && !ctx->profiling && std::getenv("BOAC_NO_GRAPH") == nullptr;

@@ -25,6 +25,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
     stream = torch.cuda.Stream()
     with Context(0) as ctx:
         sb = SliceBatch.make(g, meas, torch.as_tensor(th, dtype=torch.float32, device="cuda"), with_grad=False)
+        stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
         with torch.cuda.stream(stream):
             ctx.evaluate_batch([sb], DR, 6)          # eager run, then capture
         stream.synchronize()
@@ -34,6 +35,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
 
         # a larger objective call grows the shared scratch: the captured graph's buffers are freed
         big = torch.as_tensor(cands(12, 64), dtype=torch.float32, device="cuda")
+        stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
         with torch.cuda.stream(stream):
             ctx.objective(g, meas, big, DR, 2)
         stream.synchronize()
@@ -41,6 +43,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
         assert gen1 > gen0
 
         sb.obj.fill_(0)
+        stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
         with torch.cuda.stream(stream):
             ctx.evaluate_batch([sb], DR, 6)          # stale graph dropped: eager run and a new capture
         stream.synchronize()
@@ -49,6 +52,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
         assert torch.equal(sb.obj, J0)
 
         sb.obj.fill_(0)
+        stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
         with torch.cuda.stream(stream):
             ctx.evaluate_batch([sb], DR, 6)          # replay of the fresh graph
         stream.synchronize()

@@ -483,12 +483,14 @@ def test_evaluate_batch_uneven_and_graph_replay(ctx):
         slices.append(SliceBatch.make(g, dev(S), dev(th), with_grad=(i % 2 == 0)))
         refs.append((og, S, th))
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch(slices, DR, 4, 2)
     stream.synchronize()
     first = [(s.obj.clone(), None if s.grad is None else s.grad.clone()) for s in slices]
     for s in slices:
         s.obj.fill_(0)
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch(slices, DR, 4, 2)   # replays the captured graph
     stream.synchronize()
@@ -506,15 +508,19 @@ def test_evaluate_batch_uneven_and_graph_replay(ctx):
             report(f"batch slice {i} n={og.n} J cand {c}", s.obj[c:c + 1].cpu().numpy(), np.array([Jr]), TOL)
 
 
-def test_evaluate_batch_split_slice_matches_eager(ctx, slice64):
-    # a slice of >= 128 candidates runs as two halves on two lanes (130 = 64 + 66: the split point is
-    # rounded for alignment); objective, status and gradient equal the eager entry points bit for bit
+@pytest.mark.parametrize("split", ["1", "2"])
+def test_evaluate_batch_split_slice_matches_eager(ctx, slice64, split, monkeypatch):
+    # one slice of 130 candidates, whole on one lane (BOAC_BATCH_SPLIT=1, the default) or as two halves
+    # on two lanes (130 = 64 + 66: the split point is rounded for alignment); objective, status and
+    # gradient equal the eager entry points bit for bit
     from paper_2109_11920_amd.api import SliceBatch
+    monkeypatch.setenv("BOAC_BATCH_SPLIT", split)
     g, og = geom_pair(64, 64, pixel=0.4)
     S = dev(slice64["meas"].astype(np.float64))
     th = dev(cands(50, 130))
     sb = SliceBatch.make(g, S, th, with_grad=True)
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch([sb], DR, 3, 2)
     stream.synchronize()
@@ -522,6 +528,7 @@ def test_evaluate_batch_split_slice_matches_eager(ctx, slice64):
     assert torch.equal(sb.obj, J) and torch.equal(sb.grad, G) and torch.equal(sb.status, st)
     Jf, _, stf = ctx.objective(g, S, th, DR, 3)
     sf = SliceBatch.make(g, S, th, with_grad=False)
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch([sf], DR, 3, 2)
     stream.synchronize()

@@ -40,6 +40,7 @@ def _eval(env, slices, K, ck=2):
                 sb.obj.fill_(-1)
                 if sb.grad is not None:
                     sb.grad.fill_(-1)
+            stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
             with torch.cuda.stream(stream):
                 ctx.evaluate_batch(slices, DR, K, ck)
             stream.synchronize()

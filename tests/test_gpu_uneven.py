@@ -33,6 +33,7 @@ def uneven():
                                       torch.as_tensor(th, dtype=torch.float32, device="cuda"), with_grad=True))
         host.append((og, S, th))
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch(slices, DR, w.n_iter, w.ckpt_every)
     stream.synchronize()
@@ -56,6 +57,7 @@ def test_uneven_batch_replay_is_identical(uneven):
     G0 = [sb.grad.clone() for sb in slices]
     for sb in slices:
         sb.obj.fill_(0)
+    stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
     with torch.cuda.stream(stream):
         ctx.evaluate_batch(slices, DR, w.n_iter, w.ckpt_every)   # graph replay
     stream.synchronize()
