@@ -187,8 +187,11 @@ typedef struct {
 
 /* Batched evaluation of many slices of uneven sizes (and their candidates) with one launch per phase
  * covering every slice; the launch sequence is captured once into a HIP graph per batch shape and
- * replayed on later calls with the same shape. h_slices is host memory [n_slices]. Slices needing a
- * gradient use ckpt_every as in boac_objective_grad. */
+ * replayed on later calls with the same shape (same pointers, sizes, n_iter, ckpt_every, delta_r_cm,
+ * stream, batch mode and the BOAC_BATCH_LANES / BOAC_BATCH_SPLIT / BOAC_PERSIST_LANES and plan-switch
+ * environment settings). h_slices is host memory [n_slices]. Slices needing a gradient use ckpt_every
+ * as in boac_objective_grad. The batch's scratch is the lanes' own, apart from the eager entry points';
+ * calls on one context still must not overlap. */
 boac_status boac_evaluate_batch(boac_ctx *ctx, const boac_slice *h_slices, int32_t n_slices, float delta_r_cm,
                                 int32_t n_iter, int32_t ckpt_every, void *stream);
 

@@ -1,10 +1,10 @@
-"""The batch graph cache never replays a graph whose scratch was reallocated after its capture.
+"""The batch graph cache never replays a graph captured before a scratch reallocation.
 
-A one-slice batch of fewer than 128 candidates evaluates in the context's default scratch namespace,
-which boac_objective shares. Capturing batch A, then growing that scratch with a larger objective call,
-must retire A's graph: the next batch A runs eagerly and is captured afresh, and only the fresh graph is
-replayed afterwards. The library's graph counters show which happened, so the check never depends on
-replaying a stale graph."""
+The scratch generation is one counter per context: any buffer that grows (here the eager entry points'
+scratch, grown by a larger objective call after batch A was captured) retires every graph captured
+before it, since a graph cannot tell which of its buffers moved. The next batch A runs eagerly and is
+captured afresh, and only the fresh graph is replayed afterwards. The library's graph counters show
+which happened, so the check never depends on replaying a stale graph."""
 import numpy as np
 import pytest
 
@@ -33,7 +33,7 @@ def test_stale_graph_is_dropped_after_scratch_growth():
         graphs, captures, replays, gen0 = ctx.graph_stats()
         assert (graphs, captures, replays) == (1, 1, 0)
 
-        # a larger objective call grows the shared scratch: the captured graph's buffers are freed
+        # a larger objective call grows the eager scratch: the scratch generation moves on
         big = torch.as_tensor(cands(12, 64), dtype=torch.float32, device="cuda")
         stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
         with torch.cuda.stream(stream):
