@@ -59,7 +59,10 @@ def cnr(x: np.ndarray, hot: np.ndarray, background: np.ndarray) -> float:
     """(mean over hot - mean over background) / population std over background."""
     x = np.asarray(x, np.float64)
     b = x[background]
-    return float((x[hot].mean() - b.mean()) / b.std())
+    d, sd = x[hot].mean() - b.mean(), b.std()
+    if sd == 0.0:  # a flat background (the true activity itself): the contrast's sign as an infinity
+        return float(np.sign(d) * np.inf) if d != 0.0 else float("nan")
+    return float(d / sd)
 
 
 def psnr(x: np.ndarray, ref: np.ndarray) -> float:
