@@ -150,6 +150,27 @@ def test_many_row_bands(ctx, shape):
         report(f"bands {shape} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 2, 2), (3, 3, 6, 5), (16, 8192, 32, 16), (20, 6, 40, 1024)])
+def test_extreme_shapes(ctx, shape):
+    # the smallest image, an odd angle count (no opposed-ray pairing) with the widest bin window
+    # (n_bins = 2 n), the largest angle count, the largest sample count: objective and the unrolled and
+    # envelope gradients (with dJ/d(dR)) against the oracle
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=61)
+    th = cands(62, 2)
+    J, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 2, 1, mode="unrolled")
+    Je, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 2, 1, mode="envelope")
+    Jf, _, _ = ctx.objective(g, dev(S), dev(th), DR, 2)
+    assert torch.allclose(J, Jf, rtol=2e-6, atol=0) and torch.allclose(Je, Jf, rtol=2e-6, atol=0)
+    J, G, Ge = J.cpu().numpy(), G.cpu().numpy(), Ge.cpu().numpy()
+    for c in range(2):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 2, with_delta_r=True)
+        report(f"extreme {shape} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"extreme {shape} cand {c} dJ", G[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 2, with_delta_r=True)
+        report(f"extreme {shape} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
