@@ -171,6 +171,22 @@ def test_extreme_shapes(ctx, shape):
         report(f"extreme {shape} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
 
 
+def test_largest_candidate_count(ctx):
+    # C = 2^20, the largest admitted count, on a small slice: sampled objectives against the oracle,
+    # every objective finite, and each sample equal to its one-candidate evaluation bit for bit
+    g, og = geom_pair(12, 8, 12, 12)
+    S, _ = make_slice(og, seed=71)
+    C = 1 << 20
+    th = cands(72, C)
+    J, _, _ = ctx.objective(g, dev(S), dev(th), DR, 2)
+    assert bool(torch.isfinite(J).all())
+    for c in (0, 1, 524287, C - 1):
+        Jr = oracle.evaluate(og, S, th[c], DR, 2)[0]
+        report(f"C = 2^20 J cand {c}", J[c:c + 1].cpu().numpy(), np.array([Jr]), TOL)
+        J1, _, _ = ctx.objective(g, dev(S), dev(th[c:c + 1]), DR, 2)
+        assert torch.equal(J1[0], J[c])
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
