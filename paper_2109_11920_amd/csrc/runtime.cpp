@@ -85,9 +85,13 @@ static size_t att_slab(const boac_geom &g) {
     return (size_t)((g.n_samples + 3) / 4 * 4) * (size_t)((g.n_bins + 7) / 8 * 8);
 }
 
+// Half width, in bins, of the window of bins around a pixel's nearest bin that can hold samples of its
+// bilinear support: ceil(sqrt(2) rho - 1/2), rho = n_bins / n. Below rho ~ 0.35 that is 0 (bins wider
+// than ~2.8 pixels: only the nearest bin can reach the pixel); the kernels' narrowest window, one bin
+// either side, then also covers it (the extra taps carry weight 0).
 static int bin_half_window(const boac_geom &g) {
     const double rho = (double)g.n_bins / (double)g.n;
-    return (int)std::ceil(std::sqrt(2.0) * rho - 0.5);
+    return std::max(1, (int)std::ceil(std::sqrt(2.0) * rho - 0.5));
 }
 
 static boac_status check_geom(const boac_geom *g) {
@@ -104,7 +108,7 @@ static boac_status check_geom(const boac_geom *g) {
         return fail(BOAC_ESHAPE, "n_angles * n_bins * n_samples = %.0f samples: above 2^30 per candidate",
                     (double)g->n_angles * g->n_bins * g->n_samples);
     const int hb = bin_half_window(*g);
-    if (hb < 1 || hb > 3)
+    if (hb > 3)
         return fail(BOAC_ESHAPE, "n_bins / n = %g gives a bin window of %d; supported 1..3", (double)g->n_bins / g->n, hb);
     if ((size_t)(g->n + 3) * 4 * 2 * 2 > kLdsBudget)
         return fail(BOAC_ESHAPE, "n = %d too large for LDS row staging", g->n);

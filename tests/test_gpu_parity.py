@@ -187,6 +187,30 @@ def test_largest_candidate_count(ctx):
         assert torch.equal(J1[0], J[c])
 
 
+# drawn once from a seeded generator over the admitted sizes (n from 3 to 196, 2 to 39 angles, 2 to 2n
+# bins, 2 to 2n + 19 samples): odd and even angle counts, bins above and below n, sample counts off
+# the 4-sample groups, single-tile images, images on both sides of the paired-stage limit (140) and
+# row-banded gradient images (150, 196)
+RANDOM_GEOMS = [(15, 27, 4, 12), (17, 13, 31, 43), (196, 39, 32, 60), (150, 4, 51, 59), (196, 15, 105, 71),
+                (47, 24, 76, 71), (196, 6, 192, 233), (90, 2, 38, 94), (3, 39, 5, 21), (47, 24, 34, 38),
+                (7, 9, 11, 16), (150, 12, 217, 280), (150, 10, 111, 89), (141, 32, 126, 82)]
+
+
+@pytest.mark.parametrize("shape", RANDOM_GEOMS)
+def test_random_geometries(ctx, shape):
+    g, og = geom_pair(*shape)
+    S, _ = make_slice(og, seed=81)
+    th = cands(82, 3)
+    J, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 2, 1, mode="unrolled")
+    Jf, _, _ = ctx.objective(g, dev(S), dev(th), DR, 2)
+    assert torch.allclose(J, Jf, rtol=2e-6, atol=0)
+    J, G = J.cpu().numpy(), G.cpu().numpy()
+    for c in (1, 2):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 2, with_delta_r=True)
+        report(f"random {shape} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"random {shape} cand {c} dJ", G[c], Gr, TOL_GRAD)
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
