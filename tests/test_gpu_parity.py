@@ -211,6 +211,34 @@ def test_random_geometries(ctx, shape):
         report(f"random {shape} cand {c} dJ", G[c], Gr, TOL_GRAD)
 
 
+# a second seeded draw with candidate counts (one, the few-candidate plans, many) and pixel sizes:
+# (n, n_angles, n_bins, n_samples, C, pixel_cm)
+RANDOM_CASES = [(256, 13, 351, 359, 5, 0.3), (160, 2, 97, 98, 33, 0.1), (64, 98, 18, 118, 1, 0.37),
+                (64, 42, 37, 107, 2, 0.5), (64, 61, 75, 82, 5, 0.81), (256, 14, 319, 137, 33, 0.29),
+                (210, 4, 361, 245, 1, 0.13), (2, 18, 3, 23, 5, 0.93), (210, 13, 186, 206, 2, 0.32),
+                (64, 119, 3, 16, 1, 0.72), (210, 5, 304, 149, 5, 0.85), (2, 80, 2, 13, 2, 0.89),
+                (16, 62, 31, 44, 9, 0.77), (128, 57, 25, 68, 5, 0.56)]
+
+
+@pytest.mark.parametrize("case", RANDOM_CASES)
+def test_random_geometries_counts_and_pixels(ctx, case):
+    n, na, nb, nt, C, px = case
+    g, og = geom_pair(n, na, nb, nt, pixel=px)
+    S, _ = make_slice(og, seed=91)
+    th = cands(92, C)
+    J, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 2, 1, mode="unrolled")
+    Je, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 2, 1, mode="envelope")
+    Jf, _, _ = ctx.objective(g, dev(S), dev(th), DR, 2)
+    assert torch.allclose(J, Jf, rtol=2e-6, atol=0) and torch.allclose(Je, Jf, rtol=2e-6, atol=0)
+    J, G, Ge = J.cpu().numpy(), G.cpu().numpy(), Ge.cpu().numpy()
+    for c in sorted({0, C - 1}):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 2, with_delta_r=True)
+        report(f"random {case} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"random {case} cand {c} dJ", G[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 2, with_delta_r=True)
+        report(f"random {case} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
