@@ -239,6 +239,30 @@ def test_random_geometries_counts_and_pixels(ctx, case):
         report(f"random {case} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
 
 
+@pytest.mark.parametrize("case", RANDOM_CASES[::2])
+def test_random_geometries_other_entry_points(ctx, case):
+    # rasterisation, projection, backprojection and MLEM on the second draw's geometries
+    n, na, nb, nt, C, px = case
+    g, og = geom_pair(n, na, nb, nt, pixel=px)
+    C = min(C, 3)
+    th = cands(93, C)
+    mu = ctx.rasterize_mu(g, dev(th), DR).cpu().numpy()
+    rng = np.random.default_rng(94)
+    imgs = f32(rng.uniform(0.0, 2.0, (C, n, n)))
+    z = f32(rng.uniform(0.0, 1.0, (C, na, nb)))
+    mus = f32(mu)
+    y = ctx.project(g, dev(mus), dev(imgs)).cpu().numpy()
+    x = ctx.backproject(g, dev(mus), dev(z)).cpu().numpy()
+    S, _ = make_slice(og, seed=95)
+    F = ctx.mlem(g, dev(mus), dev(S), 3).cpu().numpy()
+    for c in range(C):
+        report(f"random {case} mu cand {c}", mu[c], oracle.rasterize_mu(og, th[c], DR), TOL)
+        att = oracle.attenuation(og, mus[c])
+        report(f"random {case} project cand {c}", y[c], oracle.project(og, att, imgs[c]), TOL)
+        report(f"random {case} backproject cand {c}", x[c], oracle.backproject(og, att, z[c]), TOL)
+        report(f"random {case} mlem cand {c}", F[c], oracle.mlem(og, att, S, 3), TOL)
+
+
 @pytest.mark.parametrize("shape,K", [((40, 24, 40, 40), 8), ((64, 64, 64, 64), 20)])
 def test_mlem(ctx, shape, K):
     g, og = geom_pair(*shape)
