@@ -589,6 +589,37 @@ def test_autograd_function(ctx, slice64):
     assert torch.allclose(th.grad, w[:, None] * G)
 
 
+@pytest.mark.parametrize("lanes", ["1", "8"])
+def test_evaluate_batch_random_slices_equal_eager(ctx, lanes, monkeypatch):
+    # a batch of the second draw's geometries (objective only and with gradients alternating), on one
+    # lane or on eight: every slice's J, gradient and status equal the eager entry points bit for bit,
+    # on the eager pass and on a graph replay
+    from paper_2109_11920_amd.api import SliceBatch
+    monkeypatch.setenv("BOAC_BATCH_LANES", lanes)
+    slices = []
+    for i, (n, na, nb, nt, C, px) in enumerate(RANDOM_CASES):
+        g, og = geom_pair(n, na, nb, nt, pixel=px)
+        S, _ = make_slice(og, seed=96 + i)
+        slices.append(SliceBatch.make(g, dev(S), dev(cands(97 + i, C)), with_grad=(i % 2 == 1)))
+    stream = torch.cuda.Stream()
+    for rep in range(2):
+        for sb in slices:
+            sb.obj.fill_(-1)
+            if sb.grad is not None:
+                sb.grad.fill_(-1)
+        stream.wait_stream(torch.cuda.current_stream())  # calls on one context do not overlap
+        with torch.cuda.stream(stream):
+            ctx.evaluate_batch(slices, DR, 3, 2)   # eager pass and capture, then a replay
+        stream.synchronize()
+        for i, sb in enumerate(slices):
+            if sb.grad is None:
+                J, _, st = ctx.objective(sb.geom, sb.meas, sb.cand, DR, 3)
+                assert torch.equal(sb.obj, J) and torch.equal(sb.status, st), (rep, i)
+            else:
+                J, G, st = ctx.objective_grad(sb.geom, sb.meas, sb.cand, DR, 3, 2)
+                assert torch.equal(sb.obj, J) and torch.equal(sb.grad, G) and torch.equal(sb.status, st), (rep, i)
+
+
 def test_evaluate_batch_uneven_and_graph_replay(ctx):
     from paper_2109_11920_amd.api import SliceBatch
     shapes = [(96, 16), (128, 24), (192, 12), (256, 8)]
