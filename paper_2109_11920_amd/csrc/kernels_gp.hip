@@ -109,7 +109,10 @@ __global__ __launch_bounds__(256) void k_gp_ei(GpEiArgs A) {
             const double g = imp / sd;
             const double cdf = 0.5 * erfc(-g * 0.70710678118654752440);
             const double pdf = 0.39894228040143267794 * exp(-0.5 * g * g);
+            // g Phi(g) + phi(g) > 0, but for g far below 0 its two terms cancel and rounding can leave a
+            // tiny negative: EI, the mean of a non-negative improvement, is clamped at 0
             ei = sd * fma(g, cdf, pdf);
+            if (!(ei > 0.0)) ei = 0.0;
         } else {
             ei = imp > 0.0 ? imp : 0.0;
         }

@@ -26,10 +26,12 @@ def _obs(n, d, seed):
     return U, y
 
 
-@pytest.mark.parametrize("n,M,xi", [(1, 100, 0.0), (37, 4999, 0.01), (150, 2000, 0.0), (300, 3001, 0.5)])
-def test_gp_ei_matches_oracle(ctx, n, M, xi):
+@pytest.mark.parametrize("n,M,xi,d", [(1, 100, 0.0, 8), (37, 4999, 0.01, 8), (150, 2000, 0.0, 8), (300, 3001, 0.5, 8),
+                                      (5, 777, 0.0, 1), (65, 1025, 0.02, 3), (200, 300, 0.0, 9), (129, 2048, 0.1, 64),
+                                      (700, 20000, 0.0, 8)])
+def test_gp_ei_matches_oracle(ctx, n, M, xi, d):
+    # observation counts on both sides of the 64-row blocks, one to 64 dimensions
     from paper_2109_11920_amd.api import gp_fit
-    d = 8
     U, y = _obs(n, d, 100 + n)
     m = gp_fit(U, y, obo.LENGTH_GRID, noise=obo.NOISE)
     ref = obo.fit_gp(U, y, obo.LENGTH_GRID, obo.NOISE)
@@ -46,7 +48,7 @@ def test_gp_ei_matches_oracle(ctx, n, M, xi):
     e_mu = np.abs(mu - mu_r).max() / ref.s
     e_sd = np.abs(sd - sd_r).max() / ref.s
     e_ei = np.abs(ei - ei_r).max() / ref.s
-    print(f"[parity] gp_ei n={n} M={M}: max|dmu|/s={e_mu:.2e} max|dsigma|/s={e_sd:.2e} max|dEI|/s={e_ei:.2e}",
+    print(f"[parity] gp_ei n={n} d={d} M={M}: max|dmu|/s={e_mu:.2e} max|dsigma|/s={e_sd:.2e} max|dEI|/s={e_ei:.2e}",
           flush=True)
     assert e_mu < 1e-8 and e_sd < 1e-6 and e_ei < 1e-6
     assert np.all(ei >= 0) and np.all(sd >= 0)
