@@ -14,7 +14,8 @@ def _obs(n, d, seed):
     return U, y
 
 
-@pytest.mark.parametrize("n,d,n_select", [(1, 8, 0), (2, 8, 0), (37, 8, 0), (150, 8, 64), (300, 3, 0)])
+@pytest.mark.parametrize("n,d,n_select", [(1, 8, 0), (2, 8, 0), (37, 8, 0), (150, 8, 64), (300, 3, 0),
+                                          (64, 1, 0), (65, 64, 0), (129, 9, 100), (520, 5, 0)])
 def test_gp_fit_matches_oracle(n, d, n_select):
     U, y = _obs(n, d, n)
     m = gp_fit(U, y, obo.LENGTH_GRID, n_select=n_select, noise=obo.NOISE)
