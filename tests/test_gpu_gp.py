@@ -145,7 +145,9 @@ def test_device_local_search_rejects_bad_sizes(ctx):
                          [(512, 12, 8, 6, 10, 0.02, 64, 40), (300, 3, 8, 4, 6, 0.2, 64, 0), (4096, 64, 8, 16, 32, 0.02, 256, 320),
                           (700, 20, 5, 3, 0, 0.05, 100, 10),
                           # every round's points kept (per_step > P), and an exclusion that leaves fewer than q
-                          (200, 64, 8, 3, 4, 1.2, 256, 5)])
+                          (200, 64, 8, 3, 4, 1.2, 256, 5),
+                          # one chain; no exclusion (equal points may both be proposed); the most chains
+                          (1, 1, 1, 1, 0, 0.0, 1, 0), (17, 5, 3, 2, 3, 0.0, 4, 2), (8192, 8, 8, 2, 2, 0.05, 8, 0)])
 def test_device_search_equals_host_search(ctx, P, q, centres, n_global, n_local, exclusion, per_step, n_taken):
     # the whole acquisition search on the device (boac_gp_chaos_search) against the host search
     # (chaotic_acquire around boac_gp_ei) from the same chains: the same proposals in the same order, the
