@@ -528,6 +528,25 @@ def test_unrolled_gradient_with_delta_r(ctx):
         ctx.objective_grad_ex(g, dev(S), th, DR, 3, 2, mode="nope")
 
 
+@pytest.mark.parametrize("dr", [0.05, 0.4, 1.5, 3.0])
+def test_cranium_thickness_range(ctx, dr):
+    # thin to thick shells: the rasterised map, J and both gradients with dJ/d(dR) against the oracle
+    g, og = geom_pair(48, 20, 62, 48)
+    S, _ = make_slice(og, seed=27)
+    th = cands(28, 2)
+    mu = ctx.rasterize_mu(g, dev(th), dr).cpu().numpy()
+    J, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), dr, 3, 2, mode="unrolled")
+    Je, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), dr, 3, 2, mode="envelope")
+    J, G, Ge = J.cpu().numpy(), G.cpu().numpy(), Ge.cpu().numpy()
+    for c in range(2):
+        report(f"dR={dr} mu cand {c}", mu[c], oracle.rasterize_mu(og, th[c], dr), TOL)
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], dr, 3, with_delta_r=True)
+        report(f"dR={dr} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"dR={dr} cand {c} dJ", G[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], dr, 3, with_delta_r=True)
+        report(f"dR={dr} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
+
+
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
     # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
     g, og = geom_pair(128, 128, pixel=0.2)
