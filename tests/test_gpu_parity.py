@@ -547,6 +547,34 @@ def test_cranium_thickness_range(ctx, dr):
         report(f"dR={dr} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
 
 
+def test_candidates_outside_the_search_box(ctx):
+    # no head (c0 = 0), a head past the field of view, harmonics large enough to make R negative in
+    # places, no attenuation, and attenuation 13-30x the head's: maps, J, F^K and the gradient against
+    # the oracle
+    g, og = geom_pair(48, 20, 62, 48)
+    S, _ = make_slice(og, seed=29)
+    th = f32(np.array([[0.0, 0, 0, 0, 0, 0, 0.15, 0.25],
+                       [30.0, 0, 0, 0, 0, 0, 0.15, 0.25],
+                       [7.5, 6.0, -5.0, 4.0, -3.0, 2.0, 0.15, 0.25],
+                       [7.5, 0, 1.2, 0, -0.3, 0, 0.0, 0.0],
+                       [7.5, 0, 1.2, 0, -0.3, 0, 2.0, 5.0]]))
+    mu = ctx.rasterize_mu(g, dev(th), DR).cpu().numpy()
+    J, F, _ = ctx.objective(g, dev(S), dev(th), DR, 3, want_image=True)
+    Jg, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 3, 2, mode="unrolled")
+    J, F, G = J.cpu().numpy(), F.cpu().numpy(), G.cpu().numpy()
+    for c in range(th.shape[0]):
+        mr = oracle.rasterize_mu(og, th[c], DR)
+        if np.abs(mr).max() > 0:
+            report(f"outside cand {c} mu", mu[c], mr, TOL)
+        else:
+            assert np.all(mu[c] == 0)
+        Jr, Fr, _ = oracle.evaluate(og, S, th[c], DR, 3)
+        report(f"outside cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"outside cand {c} F^K", F[c], Fr, TOL)
+        _, Gr = oracle.objective_and_grad(og, S, th[c], DR, 3, with_delta_r=True)
+        report(f"outside cand {c} dJ", G[c], Gr, TOL_GRAD)
+
+
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
     # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
     g, og = geom_pair(128, 128, pixel=0.2)
