@@ -19,7 +19,9 @@
  *   R(theta) = sum_{k=0}^{5} c_k P_k(cos theta); partial-volume fractions from 4 x 4 sub-samples with
  *   a C^1 smoothstep edge of width dx/4; mu = mu_b fb + mu_c (fo - fb);
  *   MLEM: F^0 = 1, r = S / (A F) where A F > 0 else 0, F <- F * (A^T r) / s with s = A^T 1;
- *   objective J = sum_i [y_i - S_i ln y_i + ln Gamma(S_i + 1)] at y = A F^K.
+ *   objective J = sum_i [y_i - S_i ln y_i + ln Gamma(S_i + 1)] at y = A F^K, evaluated as
+ *   sum_i [y_i - S_i - S_i ln(y_i / S_i)] (FP32, compensated) + sum_i [ln Gamma(S_i + 1) - S_i ln S_i + S_i]
+ *   (FP64), both over S_i > 0 (bins with S_i = 0 add y_i), so that J keeps its precision at high counts.
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are caller-owned DEVICE buffers (e.g. a contiguous float32 torch tensor's
@@ -33,8 +35,9 @@
  *     non-null and 16-byte-aligned pointers where required. Nothing aborts or throws across the ABI.
  *   - On failure the return value is non-zero and boac_last_error() holds a message (thread-local).
  *     HIP failures map to BOAC_EDEVICE with the HIP error text.
- *   - All GPU arithmetic is FP32; ray sums, angle sums, scans and the likelihood are accumulated with
- *     compensated (error-free transformation) summation.
+ *   - The reconstruction's GPU arithmetic is FP32 (the likelihood's measurement-only constant is FP64;
+ *     the surrogate's kernels are FP64); ray sums, angle sums, scans and the likelihood are accumulated
+ *     with compensated (error-free transformation) summation.
  *   - With an even n_angles, ray (a, b) and ray (a + n_angles/2, n_bins-1-b) share their samples in
  *     reverse order, and under the half-self rule their attenuations multiply to exp(-T), T the ray's
  *     total. Where the backprojection runs on its column-group kernel, the library then stores the

@@ -183,25 +183,42 @@ __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, in
 
 // sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup (up to 1024
 // threads); red: 32 floats of shared memory.
+// The part of the likelihood that depends on the measurement alone, summed in double: per bin with
+// S > 0, ln Gamma(S + 1) - S ln S + S. The projection's epilogue adds y - S - S ln(y / S) per bin (y for
+// S = 0), so that J = sum of both is Eq. (5) rearranged: every term the projection adds is of the size of
+// the misfit, not of S ln y, and J keeps its FP32 precision at high counts where the model fits. The
+// workgroup's sum runs in a fixed order (a butterfly in each wave, then the waves in order); out holds
+// it as a float pair (value, remainder). red: scratch of one double per wave (8-byte aligned).
 __device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas, int count, float2 *out,
                                                   uint32_t *flag) {
-    Comp c{0.f, 0.f};
+    double c = 0.0;
     bool neg = false;
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
-        const float S = meas[i];
-        neg |= !(S >= 0.f);
-        if (S > 0.f) comp_add(c, lgammaf(S + 1.f));
+        const float Sf = meas[i];
+        neg |= !(Sf >= 0.f);
+        if (Sf > 0.f) {
+            const double S = (double)Sf;
+            c += (lgamma(S + 1.0) - S * log(S)) + S;
+        }
     }
-    const Comp r = block_reduce(c, red);
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    double *rd = reinterpret_cast<double *>(red);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    __syncthreads();
+    if (lane == 0) rd[wave] = c;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        out[0] = make_float2(r.s, r.e);
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += rd[w];
+        const float hi = (float)t;
+        out[0] = make_float2(hi, (float)(t - (double)hi));
     }
     if (neg) atomicOr(flag, 8u);
 }
 
 #ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
-    __shared__ float red[32];
+    __shared__ __align__(8) float red[32];
     k_lgamma_sum_body(red, meas, count, out, flag);
 }
 #endif

@@ -227,7 +227,7 @@ __device__ void run_task(const TaskRec &T, int item, float *lds, float *red) {
 __global__ __launch_bounds__(kPersistThreads) void k_persist(const TaskRec *__restrict__ tasks, int ntasks,
                                                             int *__restrict__ state, long long spin_limit) {
     extern __shared__ float lds[];
-    __shared__ float red[32];
+    __shared__ __align__(8) float red[32];  // 32 floats or 16 doubles
     __shared__ int s_task, s_item;
     int *head = state, *err = state + 1, *abort_word = state + 2;
     int *claimed = state + 8, *done = state + 8 + 8 * ntasks;

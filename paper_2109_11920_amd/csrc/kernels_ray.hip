@@ -284,7 +284,11 @@ __device__ __forceinline__ float fwd_emit(const FwdArgs &A, size_t cand, int ray
         float term;
         if (S > 0.f) {
             if (y > 0.f) {
-                term = y - S * logf(y);
+                // y - S ln y less its measurement-only part S - S ln S (summed with ln Gamma(S + 1) in the
+                // likelihood constant): y - S - S ln(y / S), with y - S exact where y is within a factor
+                // of 2 of S
+                const float d = y - S;
+                term = d - S * log1pf(d / S);
             } else if (y <= 0.f) {
                 term = __builtin_inff();
                 zero_proj = true;

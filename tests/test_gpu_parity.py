@@ -575,6 +575,23 @@ def test_candidates_outside_the_search_box(ctx):
         report(f"outside cand {c} dJ", G[c], Gr, TOL_GRAD)
 
 
+@pytest.mark.parametrize("counts", [5e5, 5e7, 5e9])
+def test_objective_at_high_counts(ctx, counts):
+    # up to ~4e6 counts per bin, 200 iterations, the true head first: where the model fits, J is a small
+    # remainder of sums of S ln y; the library sums the misfit y - S - S ln(y/S) in FP32 and the
+    # measurement-only part in FP64, so J keeps the parity gate (the plain per-bin y - S ln y in FP32 was
+    # 1e-2 off at 5e9 counts)
+    g, og = geom_pair(48, 20, 62, 48)
+    S, _ = make_slice(og, seed=31, counts=counts)
+    S = f32(S)
+    th = cands(30, 2)
+    J, _, _ = ctx.objective(g, dev(S), dev(th), DR, 200)
+    J = J.cpu().numpy()
+    for c in range(2):
+        Jr = oracle.evaluate(og, S, th[c], DR, 200)[0]
+        report(f"counts {counts:.0e} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+
+
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
     # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
     g, og = geom_pair(128, 128, pixel=0.2)
