@@ -171,7 +171,8 @@ __device__ __forceinline__ void ybar_final_at(const float *meas, const float *yK
                                               size_t sino_cs, size_t t) {
     const size_t c = t / nrays, i = t - c * nrays;
     const float y = yK[c * sino_cs + i], S = meas[i];
-    ybar[c * sino_cs + i] = (y > 0.f) ? 1.f - S / y : (S == 0.f ? 1.f : 0.f);
+    // dJ/dy = 1 - S / y, as (y - S) / y: exact difference where y is within a factor of 2 of S
+    ybar[c * sino_cs + i] = (y > 0.f) ? (y - S) / y : (S == 0.f ? 1.f : 0.f);
 }
 #ifndef BOAC_BODIES_ONLY
 __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, int C, int nrays, size_t sino_cs) {
@@ -181,14 +182,13 @@ __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, in
 }
 #endif
 
-// sum_i ln Gamma(S_i + 1) (compensated) and a flag for negative counts. One workgroup (up to 1024
-// threads); red: 32 floats of shared memory.
 // The part of the likelihood that depends on the measurement alone, summed in double: per bin with
 // S > 0, ln Gamma(S + 1) - S ln S + S. The projection's epilogue adds y - S - S ln(y / S) per bin (y for
 // S = 0), so that J = sum of both is Eq. (5) rearranged: every term the projection adds is of the size of
 // the misfit, not of S ln y, and J keeps its FP32 precision at high counts where the model fits. The
 // workgroup's sum runs in a fixed order (a butterfly in each wave, then the waves in order); out holds
-// it as a float pair (value, remainder). red: scratch of one double per wave (8-byte aligned).
+// it as a float pair (value, remainder); flag gets bit 8 for negative counts. One workgroup (up to 1024
+// threads); red: scratch of one double per wave (8-byte aligned).
 __device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas, int count, float2 *out,
                                                   uint32_t *flag) {
     double c = 0.0;

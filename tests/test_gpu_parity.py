@@ -586,10 +586,16 @@ def test_objective_at_high_counts(ctx, counts):
     S = f32(S)
     th = cands(30, 2)
     J, _, _ = ctx.objective(g, dev(S), dev(th), DR, 200)
-    J = J.cpu().numpy()
+    _, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 200, 5, mode="envelope")
+    _, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 50, 5, mode="unrolled")
+    J, Ge, G = J.cpu().numpy(), Ge.cpu().numpy(), G.cpu().numpy()
     for c in range(2):
         Jr = oracle.evaluate(og, S, th[c], DR, 200)[0]
         report(f"counts {counts:.0e} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 200, with_delta_r=True)
+        report(f"counts {counts:.0e} cand {c} envelope dJ (200 iterations)", Ge[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_grad(og, S, th[c], DR, 50, with_delta_r=True)
+        report(f"counts {counts:.0e} cand {c} dJ (50 iterations)", G[c], Gr, TOL_GRAD)
 
 
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
