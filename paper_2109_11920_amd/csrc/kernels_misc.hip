@@ -217,7 +217,7 @@ __device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas,
 }
 
 #ifndef BOAC_BODIES_ONLY
-__global__ __launch_bounds__(256) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
+__global__ __launch_bounds__(512) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
     __shared__ __align__(8) float red[32];
     k_lgamma_sum_body(red, meas, count, out, flag);
 }
@@ -415,7 +415,9 @@ hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t
         t.grid = t.items = 1;
         return record_task(r, t);
     }
-    hipLaunchKernelGGL(k_lgamma_sum, dim3(1), dim3(256), 0, st, meas, count, out, flag);
+    // 512 threads: double-precision ln Gamma needs more than the 128 registers a 1024-thread workgroup
+    // leaves each lane
+    hipLaunchKernelGGL(k_lgamma_sum, dim3(1), dim3(512), 0, st, meas, count, out, flag);
     return hipGetLastError();
 }
 hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
