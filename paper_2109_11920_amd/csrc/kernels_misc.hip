@@ -185,15 +185,15 @@ __global__ void k_ybar_final(const float *meas, const float *yK, float *ybar, in
 // The part of the likelihood that depends on the measurement alone, summed in double: per bin with
 // S > 0, ln Gamma(S + 1) - S ln S + S. The projection's epilogue adds y - S - S ln(y / S) per bin (y for
 // S = 0), so that J = sum of both is Eq. (5) rearranged: every term the projection adds is of the size of
-// the misfit, not of S ln y, and J keeps its FP32 precision at high counts where the model fits. The
-// workgroup's sum runs in a fixed order (a butterfly in each wave, then the waves in order); out holds
-// it as a float pair (value, remainder); flag gets bit 8 for negative counts. One workgroup (up to 1024
-// threads); red: scratch of one double per wave (8-byte aligned).
-__device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas, int count, float2 *out,
-                                                  uint32_t *flag) {
+// the misfit, not of S ln y, and J keeps its FP32 precision at high counts where the model fits.
+// One workgroup's sum over bins first, first + stride, ... in a fixed order (each thread's bins in
+// turn, a butterfly in each wave, then the waves in order), returned to thread 0; flag gets bit 8 for
+// negative counts. red: scratch of one double per wave (8-byte aligned).
+__device__ __forceinline__ double lgamma_block_sum(double *red, const float *meas, int count, int first, int stride,
+                                                   uint32_t *flag) {
     double c = 0.0;
     bool neg = false;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    for (int i = first; i < count; i += stride) {
         const float Sf = meas[i];
         neg |= !(Sf >= 0.f);
         if (Sf > 0.f) {
@@ -202,24 +202,49 @@ __device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas,
         }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    double *rd = reinterpret_cast<double *>(red);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
     __syncthreads();
-    if (lane == 0) rd[wave] = c;
+    if (lane == 0) red[wave] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += rd[w];
-        const float hi = (float)t;
-        out[0] = make_float2(hi, (float)(t - (double)hi));
-    }
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t += red[w];
     if (neg) atomicOr(flag, 8u);
+    return t;
+}
+
+__device__ __forceinline__ void put_double(float2 *out, double t) {
+    const float hi = (float)t;
+    out[0] = make_float2(hi, (float)(t - (double)hi));
+}
+
+// The whole constant in one workgroup (the persistent executor's task); out[0] as (value, remainder).
+__device__ __forceinline__ void k_lgamma_sum_body(float *red, const float *meas, int count, float2 *out,
+                                                  uint32_t *flag) {
+    const double t = lgamma_block_sum(reinterpret_cast<double *>(red), meas, count, threadIdx.x, blockDim.x, flag);
+    if (threadIdx.x == 0) put_double(out, t);
 }
 
 #ifndef BOAC_BODIES_ONLY
 __global__ __launch_bounds__(512) void k_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag) {
     __shared__ __align__(8) float red[32];
     k_lgamma_sum_body(red, meas, count, out, flag);
+}
+
+// The constant over gridDim.x workgroups: workgroup b sums the bins b * blockDim.x + tid + k * gridDim.x *
+// blockDim.x into part[b]; k_lgamma_final adds the parts in order.
+__global__ __launch_bounds__(512) void k_lgamma_part(const float *meas, int count, double *part, uint32_t *flag) {
+    __shared__ double red[16];
+    const double t = lgamma_block_sum(red, meas, count, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                                      flag);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_lgamma_final(const double *part, int nparts, float2 *out) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int p = 0; p < nparts; ++p) t += part[p];
+    put_double(out, t);
 }
 #endif
 
@@ -415,9 +440,13 @@ hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t
         t.grid = t.items = 1;
         return record_task(r, t);
     }
-    // 512 threads: double-precision ln Gamma needs more than the 128 registers a 1024-thread workgroup
-    // leaves each lane
-    hipLaunchKernelGGL(k_lgamma_sum, dim3(1), dim3(512), 0, st, meas, count, out, flag);
+    // 512-thread workgroups (double-precision ln Gamma needs more than the 128 registers a 1024-thread
+    // workgroup leaves each lane), about 8 bins per thread, at most kLgammaParts of them; the parts in
+    // out[2..]
+    const int nparts = std::min(kLgammaParts, std::max(1, (count + 4095) / 4096));
+    double *part = reinterpret_cast<double *>(out + 2);
+    hipLaunchKernelGGL(k_lgamma_part, dim3((unsigned)nparts), dim3(512), 0, st, meas, count, part, flag);
+    hipLaunchKernelGGL(k_lgamma_final, dim3(1), dim3(64), 0, st, (const double *)part, nparts, out);
     return hipGetLastError();
 }
 hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,

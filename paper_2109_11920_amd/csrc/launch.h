@@ -247,6 +247,10 @@ hipError_t launch_tail(const DevGeom &g, const RayCfg &rc, const Bands &bands, c
 hipError_t launch_back(int mode, const DevGeom &g, const BackCfg &bc, const BackArgs &a, hipStream_t st);
 hipError_t launch_fill(float *p, size_t count, float v, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t v, hipStream_t st);
+// The likelihood's measurement-only constant (FP64). out holds kLgammaOut float2: out[0] receives the
+// constant as (value, remainder), the rest the per-workgroup partial sums (doubles).
+constexpr int kLgammaParts = 32;
+constexpr int kLgammaOut = 2 + 2 * kLgammaParts;
 hipError_t launch_lgamma_sum(const float *meas, int count, float2 *out, uint32_t *flag, hipStream_t st);
 hipError_t launch_nll_finish(const float2 *partial, int chunks, int C, const float2 *lg, const uint32_t *meas_flag,
                              float *obj, uint32_t *status, hipStream_t st);

@@ -868,7 +868,7 @@ static int arena_chunk(const boac_geom &g, int C, size_t cap) {
                        8 * 256.0;
     const double tiles = std::ceil(g.n / 16.0) * std::ceil(g.n / 16.0);
     const double fixed = 8.0 * g.n_angles + 48.0 * tiles * g.n_angles + 32.0 * g.n_angles + 4.0 * C + 64.0 +
-                         16 * 256.0;
+                         16 * 256.0 + 8.0 * kLgammaOut;
     if ((double)cap < fixed + per) return 0;
     return (int)std::min<double>(C, std::floor(((double)cap - fixed) / per));
 }
@@ -899,7 +899,7 @@ static boac_status eval_forward(boac_ctx *ctx, const boac_geom &g, const float *
     BOAC_TRY(ensure_t(ctx, "F1", (size_t)Cc * z.I, &F1));
     BOAC_TRY(ensure_t(ctx, "r", (size_t)Cc * z.Y, &r));
     BOAC_TRY(ensure_t(ctx, "partial", (size_t)Cc * p.ray1.chunks, &partial));
-    BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
+    BOAC_TRY(ensure_t(ctx, "lg", kLgammaOut, &lg));
     BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
     BOAC_TRY(ensure_t(ctx, "status_int", (size_t)C, &st_int));
     float *attbar = nullptr, *yK = nullptr, *ybar = nullptr, *mubar = nullptr, *gtmp = nullptr;
@@ -1023,7 +1023,7 @@ static boac_status eval_grad(boac_ctx *ctx, const boac_geom &g, const float *mea
     BOAC_TRY(ensure_t(ctx, "Fwork", (size_t)2 * Cc * I, &Fwork));
     BOAC_TRY(ensure_t(ctx, "pair", (size_t)Cc * I, &pair));
     BOAC_TRY(ensure_t(ctx, "partial", (size_t)Cc * p.ray1.chunks, &partial));
-    BOAC_TRY(ensure_t(ctx, "lg", 2, &lg));
+    BOAC_TRY(ensure_t(ctx, "lg", kLgammaOut, &lg));
     BOAC_TRY(ensure_t(ctx, "flag", 4, &flag));
     BOAC_TRY(ensure_t(ctx, "status_int", (size_t)C, &st_int));
     BOAC_TRY(ensure_t(ctx, "recF", (size_t)std::max(nck, 1) * Cc * I, &recF));
