@@ -598,6 +598,24 @@ def test_objective_at_high_counts(ctx, counts):
         report(f"counts {counts:.0e} cand {c} dJ (50 iterations)", G[c], Gr, TOL_GRAD)
 
 
+@pytest.mark.parametrize("px", [0.01, 0.05, 2.0, 5.0])
+def test_pixel_size_range(ctx, px):
+    # a 32-pixel grid from 0.32 cm (the head far larger than the field: nearly uniform attenuation
+    # everywhere) to 160 cm (the head a few pixels wide); J and both gradients against the oracle
+    g, og = geom_pair(32, 16, 32, 32, pixel=px)
+    S, _ = make_slice(og, seed=33)
+    th = cands(34, 2)
+    J, G, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 3, 2, mode="unrolled")
+    _, Ge, _ = ctx.objective_grad_ex(g, dev(S), dev(th), DR, 3, 2, mode="envelope")
+    J, G, Ge = J.cpu().numpy(), G.cpu().numpy(), Ge.cpu().numpy()
+    for c in range(2):
+        Jr, Gr = oracle.objective_and_grad(og, S, th[c], DR, 3, with_delta_r=True)
+        report(f"pixel {px} cand {c} J", J[c:c + 1], np.array([Jr]), TOL)
+        report(f"pixel {px} cand {c} dJ", G[c], Gr, TOL_GRAD)
+        _, Gr = oracle.objective_and_envelope_grad(og, S, th[c], DR, 3, with_delta_r=True)
+        report(f"pixel {px} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
+
+
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
     # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
     g, og = geom_pair(128, 128, pixel=0.2)
