@@ -616,6 +616,19 @@ def test_pixel_size_range(ctx, px):
         report(f"pixel {px} cand {c} envelope dJ", Ge[c], Gr, TOL_GRAD)
 
 
+def test_long_mlem_run(ctx):
+    # 1000 iterations: the FP32 iterates stay within 2e-5 of the oracle's FP64 ones, J within 1e-6
+    g, og = geom_pair(48, 20, 62, 48)
+    S, _ = make_slice(og, seed=35)
+    th = cands(36, 2)
+    J, F, _ = ctx.objective(g, dev(S), dev(th), DR, 1000, want_image=True)
+    J, F = J.cpu().numpy(), F.cpu().numpy()
+    for c in range(2):
+        Jr, Fr, _ = oracle.evaluate(og, S, th[c], DR, 1000)
+        report(f"K=1000 cand {c} J", J[c:c + 1], np.array([Jr]), 1e-6)
+        report(f"K=1000 cand {c} F^K", F[c], Fr, 1e-4)
+
+
 def test_envelope_gradient_adjoint_config_samples(ctx, slice128):
     # 128 x 128, 128 angles, the 64-candidate draw, 20 iterations; two sampled candidates
     g, og = geom_pair(128, 128, pixel=0.2)
