@@ -274,6 +274,24 @@ def test_mlem(ctx, shape, K):
         report(f"mlem {shape} K={K} cand {c}", F[c], ref, TOL)
 
 
+def test_mlem_from_a_given_start(ctx):
+    # boac_mlem continues from the image passed in: a random positive start with a zero region (which
+    # stays zero), and K = 0 (the start comes back unchanged)
+    g, og = geom_pair(40, 24, 40, 40)
+    S, _ = make_slice(og, seed=37)
+    mus, _ = _mu_img(og, 38, 2)
+    rng = np.random.default_rng(39)
+    F0 = f32(rng.uniform(0.5, 2.0, (2, 40, 40)))
+    F0[:, :8, :] = 0.0
+    F = ctx.mlem(g, dev(mus), dev(S), 6, img=dev(F0)).cpu().numpy()
+    F00 = ctx.mlem(g, dev(mus), dev(S), 0, img=dev(F0)).cpu().numpy()
+    assert np.array_equal(F00, F0.astype(np.float32))
+    for c in range(2):
+        ref = oracle.mlem(og, oracle.attenuation(og, mus[c]), S, 6, f0=F0[c])
+        report(f"mlem from a start cand {c}", F[c], ref, TOL)
+        assert np.all(F[c][:8, :] == 0)
+
+
 def test_objective_smoke_config(ctx, slice64):
     # 64 x 64, 0.4 cm, 64 angles, true head, 20 iterations
     g, og = geom_pair(64, 64, pixel=0.4)
