@@ -67,6 +67,13 @@ struct Vec<8> {
 // hat(x) = max(0, 1 - |x|); since 1 - |x| <= 1 this equals clamp(1 - |x|, 0, 1), which is one VALU
 // instruction (subtract with the clamp bit).
 __device__ __forceinline__ float hat1(float x) { return __builtin_amdgcn_fmed3f(1.f - fabsf(x), 0.f, 1.f); }
+// hat(du) hat(dv) in two instructions: with h = hat(dv) in [0, 1], h - |du| h = h (1 - |du|) lies in
+// [0, 1] where |du| <= 1 and is at most 0 elsewhere, so its clamp to [0, 1] (the FMA's clamp bit) is
+// the product, rounded once
+__device__ __forceinline__ float hat2(float du, float dv) {
+    const float h = hat1(dv);
+    return __builtin_amdgcn_fmed3f(fmaf(-fabsf(du), h, h), 0.f, 1.f);
+}
 
 // Rows of the footprint rectangle a wave stages per angle (waves take rows wave, wave + 4, ...).
 template <int TW, int TH>
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(256) void k_back(DevGeom g, BackCfg T, BackArgs A, 
                 for (int dk = -1; dk <= 1; ++dk) {
                     const float du = fmaf((float)dk, -s, dub);
                     const float dv = fmaf((float)dk, c, dvb);
-                    const float w = hat1(du) * hat1(dv);
+                    const float w = hat2(du, dv);
                     Vec<CG> gv;
                     gv.load(base + dk * rstep + db * CG);
 #pragma unroll
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(256) void k_back_slid(DevGeom g, BackCfg T, BackArg
                 for (int dk = -1; dk <= 1; ++dk) {
                     const float du = (dk == 0) ? dub : (dk < 0 ? dub + s : dub - s);
                     const float dv = (dk == 0) ? dvb : (dk < 0 ? dvb - c : dvb + c);
-                    const float w = hat1(du) * hat1(dv);
+                    const float w = hat2(du, dv);
 #pragma unroll
                     for (int h = 0; h < PLANES; ++h) {
                         Vec<V> gv;
@@ -664,6 +671,11 @@ __device__ __forceinline__ void k_back_col4_body(int bid, int tid, float *lds, b
     const int bb = tid & (P - 1), kb = tid >> 5;
     const float fbb = (float)bb, fkc = (float)(4 * kb) + 1.5f;  // group centre, in samples
     const unsigned a_stride = 4u * (unsigned)g.slab;
+    // byte offset of the group's first sample in the attenuation layout, less the block origin's part:
+    // rows 4 kb .. + 3 are one 4-row line group (the block's first row is a multiple of 4) and bin b
+    // sits at 4 att_col(b) = 16 b bytes of it
+    const unsigned line_bytes = 4u * ((unsigned)g.nb8 << 5);
+    const unsigned grp_off = (unsigned)kb * line_bytes + 16u * (unsigned)bb;
     const unsigned cand_src = 4u * (unsigned)A.att_cs, cand_z = 4u * (unsigned)A.sino_cs;
     const float *src = (mode == BACK_FIELD) ? A.z : A.att;
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src + (size_t)c0 * A.att_cs, (unsigned)ncg * cand_src);
@@ -731,9 +743,10 @@ __device__ __forceinline__ void k_back_col4_body(int bid, int tid, float *lds, b
         const float V = fmaf(fkc, t.x, fmaf(fbb, t.w, __int_as_float(r.w)));
         // a group sample is within 1.5 samples of the group centre; one sample step moves (U, V) by (-s, c)
         if (fabsf(U) < fmaf(1.5f, fabsf(t.y), hu) && fabsf(V) < fmaf(1.5f, fabsf(t.x), hv)) {
-            const unsigned off = 4u * (att_row(g, r.y + 4 * kb) + att_col(r.x + bb));
+            // the block origin's part of the offset is uniform: (r.y / 4) lines and 16 r.x bytes
+            const unsigned org = (unsigned)a * a_stride + (unsigned)(r.y >> 2) * line_bytes + 16u * (unsigned)r.x;
 #pragma unroll
-            for (int q = 0; q < CG; ++q) pre[q] = buffer_ld4(rs, off, (unsigned)a * a_stride + qs[q]);
+            for (int q = 0; q < CG; ++q) pre[q] = buffer_ld4(rs, grp_off, org + qs[q]);
         }
     };
 
@@ -819,7 +832,7 @@ __device__ __forceinline__ void k_back_col4_body(int bid, int tid, float *lds, b
                 for (int dk = -1; dk <= 1; ++dk) {
                     const float du = (dk == 0) ? dub : (dk < 0 ? dub + s : dub - s);
                     const float dv = (dk == 0) ? dvb : (dk < 0 ? dvb - c : dvb + c);
-                    const float w = hat1(du) * hat1(dv);
+                    const float w = hat2(du, dv);
 #pragma unroll
                     for (int h = 0; h < PLANES; ++h) {
                         Vec<V> gv;
