@@ -504,6 +504,7 @@ def main():
     ap.add_argument("--no-bo", action="store_true", help="skip the BOAC outer-loop line")
     ap.add_argument("--only-grad", action="store_true", help="the gradient lines only (for profiler runs)")
     ap.add_argument("--only-gp", action="store_true", help="the acquisition-kernel line only (for profiler runs)")
+    ap.add_argument("--only-paper72", action="store_true", help="the 72-angle line only (for profiler runs)")
     ap.add_argument("--only-uneven", action="store_true",
                     help="the uneven batch's replay only, without the serialised pass (for profiler runs)")
     ap.add_argument("--only-bo", action="store_true", help="the BOAC outer-loop line only")
@@ -558,8 +559,10 @@ def main():
         print(json.dumps({"uneven48_serialised": uneven_serial(ctx, dev, slices, wu)}), flush=True)
         ctx.close()
         return
-    if args.only_uneven or args.only_gp or args.only_grad or args.only_bo:
+    if args.only_uneven or args.only_gp or args.only_grad or args.only_bo or args.only_paper72:
         out = {}
+        if args.only_paper72:
+            out["paper72"] = paper72_line(ctx, dev)
         if args.only_bo:
             import numpy as np
             d = np.load(os.path.join(ROOT, "tests", "golden", "slice_n128.npz"))

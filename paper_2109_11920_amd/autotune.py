@@ -119,6 +119,7 @@ def tune_workload(name: str, cache: dict, log=print):
             log(f"[tune] {name} {shape} back tile={tw}x{th} cg={cg} slid={slid}: {t * 1e3:.1f} us/launch")
             if best is None or t < best[0]:
                 best = (t, [tw, th, cg, 1, slid])
+        remap_t = {}
         for remap in (0, 1):
             cfg = best[1][:3] + [remap, best[1][4]]
             e = dict(cache)
@@ -126,8 +127,11 @@ def tune_workload(name: str, cache: dict, log=print):
             t = _time(g, meas, cand, e, "back", K)
             log(f"[tune] {name} {shape} back tile={cfg[0]}x{cfg[1]} cg={cfg[2]} slid={cfg[4]} xcd_remap={remap}: "
                 f"{t * 1e3:.1f} us/launch")
-            if t < best[0]:
-                best = (t, cfg)
+            remap_t[remap] = (t, cfg)
+        # a candidate group's tiles on one XCD share its samples in that XCD's L2 (fewer HBM bytes: 0.98x
+        # against 1.51x the algorithmic count on the 72-angle batch), so the remap stays unless running
+        # without it is clearly faster; near-ties are timing noise
+        best = remap_t[0] if remap_t[0][0] < 0.98 * remap_t[1][0] else remap_t[1]
         cache[key("back", g, C, 0)] = best[1]
         log(f"[tune] {name} {shape} -> ray {cache[key('ray', g, C, 1)]} back {best[1]}")
     return cache
