@@ -28,7 +28,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 
-RAY_CONFIGS = [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4), (1024, 1), (1024, 2), (1024, 4)]
+RAY_CONFIGS = [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4), (1024, 1), (1024, 2), (1024, 4), (768, 1),
+               (768, 2)]
 # (tile width, tile height, candidates per workgroup, slid-block kernel: 0 general, 1 slot staging,
 # 2 column-group staging)
 BACK_CONFIGS = [(16, 16, 1, 0), (16, 16, 2, 0), (16, 16, 4, 0), (16, 16, 8, 0), (32, 16, 2, 0), (32, 16, 4, 0),

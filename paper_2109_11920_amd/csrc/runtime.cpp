@@ -514,7 +514,7 @@ static void ray_plan(boac_ctx *ctx, const boac_geom &g, int C, int comps, RayCfg
     auto it = ctx->tune.find(shape_key("ray", g, C, comps));
     if (it != ctx->tune.end() && it->second.size() >= 2) {
         const int blk = it->second[0], rpt = it->second[1];
-        if ((blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024) && rpt >= 1 && rpt <= 4) {
+        if (blk >= 64 && blk <= 1024 && blk % 64 == 0 && rpt >= 1 && rpt <= 4) {
             rc->block = blk;
             rc->rpt = rpt;
         }
